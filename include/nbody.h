@@ -1,0 +1,223 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) gravitational octree library.
+ *
+ * The library computes the gravitational acceleration of Eq. 1 of Miki,
+ * "Gravitational octree code performance evaluation on Volta GPU" (CPC
+ * 2019), a_i = sum_{j != i} G m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2),
+ * with the tree method of that paper's Sec. 1: an octree of Morton-sorted
+ * particles, monopole moments of every cell (total mass and centre of mass,
+ * the "calcNode" function of Sec. 2.2), and a walk in which a group of
+ * particles shares one interaction list built with the acceleration
+ * multipole acceptance criterion (MAC) of Eq. 2,
+ *     G m_J / d^2 (b_J / d)^2 <= delta_acc |a_old|.
+ * It also advances particles with a kick-drift-kick leapfrog.
+ *
+ * Conventions for every entry point
+ *  - All particle arrays are DEVICE pointers to contiguous arrays indexed by
+ *    the caller's particle order ("caller order"), structure of arrays.
+ *    They are owned by the caller and must stay valid until the work
+ *    enqueued on the context's stream has finished.
+ *  - All work is enqueued on the HIP stream given to nbody_create and the
+ *    call returns without waiting, except the functions marked BLOCKING.
+ *  - The library allocates no device memory after nbody_bind_workspace: all
+ *    scratch lives in the caller-owned workspace.
+ *  - Return values are nbody_status codes. Argument errors are returned
+ *    directly. Errors found by kernels (non-finite input, overflow of the
+ *    walk's frontier buffer) are latched in a device status word, reported
+ *    by nbody_sync and by every later call on the context ("sticky").
+ *  - No C++ exception crosses this interface. Not thread-safe per context.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBODY_ABI_VERSION 1
+
+typedef int32_t nbody_status;
+enum {
+  NBODY_OK = 0,
+  NBODY_EINVAL = -1,     /* bad argument (null pointer, eps <= 0, ...) */
+  NBODY_ENOMEM = -2,     /* workspace missing or too small for n */
+  NBODY_EHIP = -3,       /* a HIP runtime call failed */
+  NBODY_EOVERFLOW = -4,  /* walk frontier buffer overflowed (sticky) */
+  NBODY_ENOTREE = -5,    /* calc_acc/refit/export before build_tree */
+  NBODY_ENONFINITE = -6, /* NaN or Inf in particle input (sticky) */
+  NBODY_ECORRUPT = -7    /* a kernel's consistency check failed (sticky) */
+};
+
+/* Method parameters.
+ *  G, eps      : Eq. 1 constants; eps > 0 (softening, removes the j == i term).
+ *  delta_acc   : Eq. 2 accuracy parameter, >= 0. 0 makes the walk exact
+ *                (equal to direct summation up to FP32 rounding).
+ *  leaf_max    : a cell holding more than leaf_max particles is split
+ *                (until level 21); 1 <= leaf_max <= group_max.
+ *  group_max   : largest i-group (particles sharing one interaction list);
+ *                1 <= group_max <= 64.
+ *  compensated : 0 plain FP32 accumulation; 1 compensated (Neumaier) sum.
+ *  order       : group queue order of the walk: 0 group (Morton) order,
+ *                1 by the previous walk's per-group list length (longest
+ *                first), 2 by a learned cost model (nbody_set_cost_model).
+ *                The order never changes the results (bit-identical).
+ *  frontier_cap: cells per wavefront in the walk's breadth-first frontier
+ *                buffer (power of two; 0 = 65536).
+ *  list_tile   : interaction-list entries held in LDS per wavefront before a
+ *                flush (multiple of 8, 64..2048; 0 = 256).
+ *  waves_per_cu: resident wavefronts per compute unit of the persistent walk
+ *                (1..32; 0 = 8).
+ */
+typedef struct {
+  float G;
+  float eps;
+  float delta_acc;
+  int32_t leaf_max;
+  int32_t group_max;
+  int32_t compensated;
+  int32_t order;
+  int32_t frontier_cap;
+  int32_t list_tile;
+  int32_t waves_per_cu;
+} nbody_params;
+
+typedef struct nbody_ctx nbody_ctx; /* opaque; one per HIP stream */
+
+/* Integration state (all arrays device, caller order, length n).
+ * x, y, z: FP64 positions; vx, vy, vz: FP32 velocities; m: FP32 masses;
+ * ax, ay, az: FP32 accelerations of the last force evaluation (they are the
+ * a_old of Eq. 2 and are overwritten by each step); t: simulation time
+ * (host); dt: step length; have_acc: 0 if ax..az are not yet valid (the
+ * first step then runs a bootstrap force evaluation first);
+ * rebuild_interval: rebuild the tree every k steps (k >= 1), or 0 to let
+ * the library choose by the measured build and walk times. */
+typedef struct {
+  int64_t n;
+  double *x, *y, *z;
+  float *vx, *vy, *vz;
+  float *m;
+  float *ax, *ay, *az;
+  double t;
+  double dt;
+  int32_t have_acc;
+  int32_t rebuild_interval;
+} nbody_state;
+
+/* Per-call statistics (host struct filled by nbody_get_stats, BLOCKING). */
+typedef struct {
+  int64_t n, ncell, ngroup;
+  int64_t list_entries;  /* sum over groups of interaction-list entries */
+  int64_t interactions;  /* sum over groups of entries x group size */
+  int64_t steps, rebuilds;
+  double t_build_ms, t_walk_ms, t_step_ms; /* last measured (events) */
+} nbody_stats;
+
+/* What nbody_export copies (element type, length). */
+enum {
+  NBODY_X_KEYS = 1,      /* uint64[n]  sorted Morton keys */
+  NBODY_X_PERM = 2,      /* uint32[n]  sorted position -> caller index */
+  NBODY_X_LEVEL = 3,     /* int32[ncell] */
+  NBODY_X_PBEGIN = 4,    /* uint32[ncell] first sorted particle of a cell */
+  NBODY_X_PCOUNT = 5,    /* uint32[ncell] */
+  NBODY_X_FCHILD = 6,    /* int32[ncell] first child (-1 for a leaf) */
+  NBODY_X_NCHILD = 7,    /* int32[ncell] */
+  NBODY_X_PARENT = 8,    /* int32[ncell] (-1 for the root) */
+  NBODY_X_NODE = 9,      /* float32[ncell][4]: com x, y, z, b^2 */
+  NBODY_X_MQ = 10,       /* float32[ncell][2]: m32, q = G m32 b^2 */
+  NBODY_X_MOM64 = 11,    /* float64[ncell][4]: M, Sx, Sy, Sz */
+  NBODY_X_GBEGIN = 12,   /* uint32[ngroup] */
+  NBODY_X_GCOUNT = 13,   /* uint32[ngroup] */
+  NBODY_X_GBOX = 14,     /* float32[ngroup][8]: lo xyz, dA, hi xyz, amin */
+  NBODY_X_GENTRIES = 15, /* uint32[ngroup] list entries of the last walk */
+  NBODY_X_GHASH = 16,    /* uint64[ngroup] order-independent entry hash */
+  NBODY_X_XYZM = 17,     /* float32[n][4] sorted positions and masses */
+  NBODY_X_BOX = 18       /* float64[4]: root cube lo x, y, z, side L */
+};
+
+int32_t nbody_abi_version(void);
+const char *nbody_strerror(nbody_status s);
+
+/* Fill *p with defaults: G = 1, eps = 2^-7, delta_acc = 2^-9, leaf_max 16,
+ * group_max 64, compensated 0, order 0, and the autotunable sizes 0. */
+nbody_status nbody_params_default(nbody_params *p);
+
+/* Create a context bound to `hip_stream` (a hipStream_t, NULL = default
+ * stream) on the current device. Validates *p (see nbody_params). */
+nbody_status nbody_create(const nbody_params *p, void *hip_stream,
+                          nbody_ctx **out);
+void nbody_destroy(nbody_ctx *ctx);
+
+/* Bytes of device workspace needed for up to n_max particles. BLOCKING
+ * only in the sense that it queries the device's compute-unit count. */
+nbody_status nbody_workspace_query(const nbody_params *p, int64_t n_max,
+                                   size_t *bytes);
+
+/* Bind caller-owned device memory (>= nbody_workspace_query bytes, 256-byte
+ * aligned) for up to n_max particles. The library keeps no other device
+ * state; rebinding drops the tree. */
+nbody_status nbody_bind_workspace(nbody_ctx *ctx, void *dev_ptr, size_t bytes,
+                                  int64_t n_max);
+
+/* Tree pipeline of Sec. 1 / Sec. 2.2 for n particles (1 <= n <= n_max):
+ * root cube and 63-bit Morton keys, stable radix sort, level-order octree
+ * (leaves hold at most leaf_max particles, or sit at level 21), i-groups,
+ * and the monopole moments of every cell ("calcNode"). Inputs are FP32
+ * positions and masses in caller order (masses >= 0). */
+nbody_status nbody_build_tree(nbody_ctx *ctx, int64_t n, const float *x,
+                              const float *y, const float *z, const float *m);
+
+/* New positions/masses, same topology: recompute the moments and group
+ * boxes on the existing tree (the paper rebuilds the tree only every few
+ * steps, Sec. 4.1, while calcNode runs every step). */
+nbody_status nbody_refit(nbody_ctx *ctx, const float *x, const float *y,
+                         const float *z, const float *m);
+
+/* Group-wise tree walk: accelerations of Eq. 1 under the MAC of Eq. 2 for
+ * every particle, written in caller order to ax, ay, az. a_old (caller
+ * order) is the previous acceleration used by Eq. 2; pass NULL for all
+ * three to run the bootstrap walk, which accepts a cell iff its distance to
+ * the group exceeds twice its size b_J. Needs a tree (ENOTREE). */
+nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *ax_old,
+                            const float *ay_old, const float *az_old,
+                            float *ax, float *ay, float *az);
+
+/* Advance the state by n_steps kick-drift-kick leapfrog steps of length
+ * st->dt: v += a dt/2 (FP32); x += v dt (FP64); tree rebuild or refit from
+ * the FP32 image of x; a = walk(a_old = previous a); v += a dt/2.
+ * st->t is advanced on the host. */
+nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps);
+
+/* Eq. 1 by direct O(N^2) summation in FP32 on the GPU (the tree walk's
+ * arithmetic calibration and the delta_acc = 0 reference). */
+nbody_status nbody_direct(nbody_ctx *ctx, int64_t n, const float *x,
+                          const float *y, const float *z, const float *m,
+                          float *ax, float *ay, float *az);
+
+/* Copy an internal array (see NBODY_X_*) to caller device memory `dst`
+ * holding at least `capacity` elements. Returns ENOMEM if too small.
+ * Sizes come from nbody_get_stats. */
+nbody_status nbody_export(nbody_ctx *ctx, int32_t what, void *dst,
+                          int64_t capacity);
+
+/* BLOCKING: synchronise the stream, then fill *out. */
+nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
+
+/* BLOCKING: synchronise the stream and return the sticky status. */
+nbody_status nbody_sync(nbody_ctx *ctx);
+
+/* Host-only rebuild rule used by nbody_step when rebuild_interval == 0
+ * (the paper tunes the rebuild interval to minimise tree-construction plus
+ * gravity time, Sec. 1 and Sec. 4.1). With A = (t_build_ms + walk_sum_ms) /
+ * steps_since the mean cost per step since the last rebuild, returns 1
+ * (rebuild) iff steps_since >= max_interval or last_walk_ms >= A; 0 if
+ * steps_since <= 0. Pure function, no device access. */
+int32_t nbody_rebuild_decide(double t_build_ms, double walk_sum_ms,
+                             double last_walk_ms, int32_t steps_since,
+                             int32_t max_interval);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

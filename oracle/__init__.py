@@ -88,7 +88,10 @@ def lib():
 
 
 def nthreads_default() -> int:
-    return max(1, len(os.sched_getaffinity(0)))
+    """Threads for the oracle's OpenMP loops: the affinity count, capped by
+    OMP_NUM_THREADS (default cap 16, the CPU share of one GPU on the box)."""
+    cap = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    return max(1, min(len(os.sched_getaffinity(0)), cap))
 
 
 def _c(a, dt):

@@ -1,0 +1,590 @@
+// api.hip -- the C ABI (include/nbody.h): contexts, workspace, orchestration.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "nbody_internal.h"
+
+using namespace nb;
+
+struct nbody_ctx {
+  nbody_params p;
+  hipStream_t st = nullptr;
+  int device = 0;
+  int num_cu = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout L;
+  Ptrs P;
+  bool bound = false;
+  int64_t n = 0;
+  bool have_tree = false;
+  uint64_t *keys = nullptr;  // sorted keys of the current tree
+  uint32_t *perm = nullptr;  // sorted position -> caller index
+  nbody_status sticky = NBODY_OK;
+  // step statistics and rebuild controller
+  int64_t steps = 0, rebuilds = 0;
+  int32_t since_rebuild = 0;
+  double walk_sum_ms = 0.0;  // walk time since the last rebuild
+  double t_build_ms = 0.0, t_walk_ms = 0.0, t_step_ms = 0.0;
+  hipEvent_t ev[6] = {};
+  bool ev_pending = false;
+  bool ev_had_build = false;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int device_cu_count(int *dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -1;
+  if (dev_out) *dev_out = dev;
+  return cu;
+}
+
+nbody_status check_params(const nbody_params *p) {
+  if (!p) return NBODY_EINVAL;
+  if (!(p->eps > 0.0f) || !isfinite(p->eps)) return NBODY_EINVAL;
+  if (!(p->delta_acc >= 0.0f) || !isfinite(p->delta_acc)) return NBODY_EINVAL;
+  if (!isfinite(p->G)) return NBODY_EINVAL;
+  if (p->group_max < 1 || p->group_max > 64) return NBODY_EINVAL;
+  if (p->leaf_max < 1 || p->leaf_max > p->group_max) return NBODY_EINVAL;
+  if (p->compensated != 0 && p->compensated != 1) return NBODY_EINVAL;
+  if (p->order < 0 || p->order > 2) return NBODY_EINVAL;
+  if (p->frontier_cap != 0 &&
+      (p->frontier_cap < 64 || (p->frontier_cap & (p->frontier_cap - 1)) != 0))
+    return NBODY_EINVAL;
+  if (p->list_tile != 0 && (p->list_tile < 64 || p->list_tile > 2048 || p->list_tile % 8))
+    return NBODY_EINVAL;
+  if (p->waves_per_cu < 0 || p->waves_per_cu > 32) return NBODY_EINVAL;
+  return NBODY_OK;
+}
+
+int eff_waves(const nbody_params &p) {
+  int w = p.waves_per_cu ? p.waves_per_cu : 8;
+  w = (w + kWalkWavesPerWG - 1) / kWalkWavesPerWG * kWalkWavesPerWG;
+  return w;
+}
+int eff_tile(const nbody_params &p) { return p.list_tile ? p.list_tile : 256; }
+int eff_frontier(const nbody_params &p) { return p.frontier_cap ? p.frontier_cap : 65536; }
+
+nbody_status hip_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? NBODY_OK : NBODY_EHIP;
+}
+
+nbody_status status_from_bits(int32_t b) {
+  if (b & kStNonFinite) return NBODY_ENONFINITE;
+  if (b & kStOverflow) return NBODY_EOVERFLOW;
+  if (b & kStCapacity) return NBODY_ENOMEM;
+  if (b & kStCorrupt) return NBODY_ECORRUPT;
+  return NBODY_OK;
+}
+
+}  // namespace
+
+namespace nb {
+
+Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
+  Layout L;
+  L.n_max = n;
+  L.cell_cap = n + cdiv(21 * n, p.leaf_max + 1) + 2;
+  L.sort_blocks = cdiv(n, kSortTile);
+  L.build_blocks = cdiv(n, kBuildThreads);
+  L.walk_waves = (int64_t)num_cu * eff_waves(p);
+  L.frontier_cap = eff_frontier(p);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  const size_t C = (size_t)L.cell_cap, N = (size_t)n;
+  L.off_scalars = take(sizeof(DevScalars));
+  L.off_keysA = take(8 * N);
+  L.off_keysB = take(8 * N);
+  L.off_valsA = take(4 * N);
+  L.off_valsB = take(4 * N);
+  L.off_hist = take(4 * ((size_t)kSortRadix * L.sort_blocks + kSortRadix));
+  L.off_xyzm = take(16 * N);
+  L.off_x32 = take(12 * N);
+  L.off_pinfo = take(4 * N);
+  L.off_leafof = take(4 * N);
+  L.off_blkcnt = take(4 * ((size_t)(kLevels + 1) * L.build_blocks + kLevels + 1));
+  L.off_clevel = take(4 * C);
+  L.off_cpbegin = take(4 * C);
+  L.off_cpcount = take(4 * C);
+  L.off_cfchild = take(4 * C);
+  L.off_cnchild = take(4 * C);
+  L.off_cparent = take(4 * C);
+  L.off_mom64 = take(32 * C);
+  L.off_nodeA = take(16 * C);
+  L.off_nodeB = take(16 * C);
+  L.off_gbegin = take(4 * (N + 1));
+  L.off_gcount = take(4 * N);
+  L.off_gbox = take(32 * N);
+  L.off_gent = take(4 * N);
+  L.off_ghash = take(8 * N);
+  L.off_order = take(4 * N);
+  L.off_prevcnt = take(4 * N);
+  L.off_frontier = take(4 * (size_t)L.walk_waves * (size_t)L.frontier_cap);
+  L.total = o;
+  return L;
+}
+
+Ptrs carve(void *base, const Layout &L) {
+  char *b = static_cast<char *>(base);
+  Ptrs P;
+  P.sc = reinterpret_cast<DevScalars *>(b + L.off_scalars);
+  P.keysA = reinterpret_cast<uint64_t *>(b + L.off_keysA);
+  P.keysB = reinterpret_cast<uint64_t *>(b + L.off_keysB);
+  P.valsA = reinterpret_cast<uint32_t *>(b + L.off_valsA);
+  P.valsB = reinterpret_cast<uint32_t *>(b + L.off_valsB);
+  P.hist = reinterpret_cast<uint32_t *>(b + L.off_hist);
+  P.xyzm = reinterpret_cast<float4 *>(b + L.off_xyzm);
+  P.x32 = reinterpret_cast<float *>(b + L.off_x32);
+  P.pinfo = reinterpret_cast<uint32_t *>(b + L.off_pinfo);
+  P.leafof = reinterpret_cast<uint32_t *>(b + L.off_leafof);
+  P.blkcnt = reinterpret_cast<uint32_t *>(b + L.off_blkcnt);
+  P.clevel = reinterpret_cast<int32_t *>(b + L.off_clevel);
+  P.cpbegin = reinterpret_cast<uint32_t *>(b + L.off_cpbegin);
+  P.cpcount = reinterpret_cast<uint32_t *>(b + L.off_cpcount);
+  P.cfchild = reinterpret_cast<int32_t *>(b + L.off_cfchild);
+  P.cnchild = reinterpret_cast<int32_t *>(b + L.off_cnchild);
+  P.cparent = reinterpret_cast<int32_t *>(b + L.off_cparent);
+  P.mom64 = reinterpret_cast<double4 *>(b + L.off_mom64);
+  P.nodeA = reinterpret_cast<float4 *>(b + L.off_nodeA);
+  P.nodeB = reinterpret_cast<float4 *>(b + L.off_nodeB);
+  P.gbegin = reinterpret_cast<uint32_t *>(b + L.off_gbegin);
+  P.gcount = reinterpret_cast<uint32_t *>(b + L.off_gcount);
+  P.gbox = reinterpret_cast<float4 *>(b + L.off_gbox);
+  P.gent = reinterpret_cast<uint32_t *>(b + L.off_gent);
+  P.ghash = reinterpret_cast<unsigned long long *>(b + L.off_ghash);
+  P.order = reinterpret_cast<uint32_t *>(b + L.off_order);
+  P.prevcnt = reinterpret_cast<uint32_t *>(b + L.off_prevcnt);
+  P.frontier = reinterpret_cast<uint32_t *>(b + L.off_frontier);
+  return P;
+}
+
+}  // namespace nb
+
+// Reduction of the walk statistics: sum of entries and entries x size.
+__global__ __launch_bounds__(256) void k_stats(DevScalars *sc, const uint32_t *gent,
+                                               const uint32_t *gcount) {
+  const uint32_t ng = sc->ngroup;
+  unsigned long long e = 0, it = 0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = gent[g] == 0xffffffffu ? 0u : gent[g];
+    e += v;
+    it += (unsigned long long)v * gcount[g];
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    e += __shfl_xor(e, d, 64);
+    it += __shfl_xor(it, d, 64);
+  }
+  if (lane_id() == 0) {
+    atomicAdd(&sc->entries_total, e);
+    atomicAdd(&sc->inter_total, it);
+  }
+}
+
+__global__ void k_stats_zero(DevScalars *sc) {
+  sc->entries_total = 0;
+  sc->inter_total = 0;
+}
+
+__global__ void k_scalars_init(DevScalars *sc) {
+  sc->status = 0;
+  sc->ncell = 0;
+  sc->ngroup = 0;
+  sc->queue_head = 0;
+  for (int l = 0; l <= kLevels; ++l) sc->lvl_off[l] = 0;
+  sc->entries_total = 0;
+  sc->inter_total = 0;
+}
+
+// FP32 image of FP64 positions (caller order) into x32[3][n].
+__global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *x, const double *y,
+                                                const double *z, float *x32) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x32[i] = (float)x[i];
+    x32[n + i] = (float)y[i];
+    x32[2 * n + i] = (float)z[i];
+  }
+}
+
+namespace {
+
+nbody_status pre(nbody_ctx *ctx) {
+  if (!ctx) return NBODY_EINVAL;
+  if (ctx->sticky != NBODY_OK) return ctx->sticky;
+  if (!ctx->bound) return NBODY_ENOMEM;
+  return NBODY_OK;
+}
+
+WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap) {
+  WalkCfg c;
+  c.G = ctx->p.G;
+  c.eps = ctx->p.eps;
+  c.bootstrap = bootstrap ? 1 : 0;
+  c.compensated = ctx->p.compensated;
+  c.list_tile = eff_tile(ctx->p);
+  c.frontier_cap = eff_frontier(ctx->p);
+  c.waves_per_cu = eff_waves(ctx->p);
+  c.num_cu = ctx->num_cu;
+  c.use_order = 0;
+  return c;
+}
+
+nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
+                      const float *z, const float *m) {
+  const Ptrs &P = ctx->P;
+  launch_bbox(x, y, z, n, P.sc, ctx->st);
+  launch_keys(x, y, z, n, P.sc, P.keysA, P.valsA, ctx->st);
+  uint64_t *ks;
+  uint32_t *pm;
+  launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
+              &ks, &pm);
+  launch_gather(x, y, z, m, pm, n, P.xyzm, ctx->st);
+  launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, P, ctx->L, ctx->st);
+  launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
+  ctx->keys = ks;
+  ctx->perm = pm;
+  ctx->n = n;
+  ctx->have_tree = true;
+  return hip_status();
+}
+
+nbody_status do_refit(nbody_ctx *ctx, const float *x, const float *y, const float *z,
+                      const float *m) {
+  launch_gather(x, y, z, m, ctx->perm, ctx->n, ctx->P.xyzm, ctx->st);
+  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, ctx->st);
+  return hip_status();
+}
+
+nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const float *azo,
+                     float *ax, float *ay, float *az) {
+  const bool boot = axo == nullptr;
+  launch_group_bounds(axo, ayo, azo, ctx->perm, ctx->n, ctx->p.delta_acc, ctx->P, ctx->st);
+  launch_walk(walk_cfg(ctx, boot), ctx->perm, ctx->n, ax, ay, az, ctx->P, ctx->st);
+  return hip_status();
+}
+
+nbody_status read_scalars(nbody_ctx *ctx, DevScalars *h) {
+  if (hipMemcpyAsync(h, ctx->P.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->st) !=
+      hipSuccess)
+    return NBODY_EHIP;
+  if (hipStreamSynchronize(ctx->st) != hipSuccess) return NBODY_EHIP;
+  return NBODY_OK;
+}
+
+// Non-blocking harvest of the last step's event timings.
+void harvest_events(nbody_ctx *ctx) {
+  if (!ctx->ev_pending) return;
+  if (hipEventQuery(ctx->ev[5]) != hipSuccess) return;
+  float tb = 0.f, tw = 0.f, ts = 0.f;
+  if (ctx->ev_had_build && hipEventElapsedTime(&tb, ctx->ev[1], ctx->ev[2]) == hipSuccess)
+    ctx->t_build_ms = tb;
+  if (hipEventElapsedTime(&tw, ctx->ev[3], ctx->ev[4]) == hipSuccess) ctx->t_walk_ms = tw;
+  if (hipEventElapsedTime(&ts, ctx->ev[0], ctx->ev[5]) == hipSuccess) ctx->t_step_ms = ts;
+  ctx->ev_pending = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t nbody_abi_version(void) { return NBODY_ABI_VERSION; }
+
+const char *nbody_strerror(nbody_status s) {
+  switch (s) {
+    case NBODY_OK: return "ok";
+    case NBODY_EINVAL: return "invalid argument";
+    case NBODY_ENOMEM: return "workspace missing or too small";
+    case NBODY_EHIP: return "HIP runtime error";
+    case NBODY_EOVERFLOW: return "walk frontier buffer overflow";
+    case NBODY_ENOTREE: return "no tree built";
+    case NBODY_ENONFINITE: return "non-finite particle data";
+    case NBODY_ECORRUPT: return "internal consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+nbody_status nbody_params_default(nbody_params *p) {
+  if (!p) return NBODY_EINVAL;
+  memset(p, 0, sizeof(*p));
+  p->G = 1.0f;
+  p->eps = 0.0078125f;      // 2^-7
+  p->delta_acc = 0.001953125f;  // 2^-9
+  p->leaf_max = 16;
+  p->group_max = 64;
+  return NBODY_OK;
+}
+
+// Rebuild rule (the paper's auto-tuned rebuild interval, Sec. 1 and 4.1,
+// minimises tree-construction plus gravity time): with average cost per step
+// since the last rebuild A = (t_build + sum of walk times) / k, rebuild when
+// the latest walk time reaches A. Exported for host-side testing.
+int32_t nbody_rebuild_decide(double t_build_ms, double walk_sum_ms, double last_walk_ms,
+                             int32_t steps_since, int32_t max_interval) {
+  if (steps_since <= 0) return 0;
+  if (steps_since >= max_interval) return 1;
+  const double avg = (t_build_ms + walk_sum_ms) / (double)steps_since;
+  return last_walk_ms >= avg ? 1 : 0;
+}
+
+nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **out) {
+  if (!out) return NBODY_EINVAL;
+  *out = nullptr;
+  const nbody_status s = check_params(p);
+  if (s != NBODY_OK) return s;
+  nbody_ctx *c = new (std::nothrow) nbody_ctx();
+  if (!c) return NBODY_EINVAL;
+  c->p = *p;
+  c->st = static_cast<hipStream_t>(hip_stream);
+  c->num_cu = device_cu_count(&c->device);
+  if (c->num_cu <= 0) {
+    delete c;
+    return NBODY_EHIP;
+  }
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return NBODY_EHIP;
+    }
+  *out = c;
+  return NBODY_OK;
+}
+
+void nbody_destroy(nbody_ctx *ctx) {
+  if (!ctx) return;
+  for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+nbody_status nbody_workspace_query(const nbody_params *p, int64_t n_max, size_t *bytes) {
+  const nbody_status s = check_params(p);
+  if (s != NBODY_OK) return s;
+  if (!bytes || n_max < 1 || n_max > (int64_t)0x7fffffff / 2) return NBODY_EINVAL;
+  const int cu = device_cu_count(nullptr);
+  if (cu <= 0) return NBODY_EHIP;
+  *bytes = make_layout(*p, n_max, cu).total;
+  return NBODY_OK;
+}
+
+nbody_status nbody_bind_workspace(nbody_ctx *ctx, void *dev_ptr, size_t bytes,
+                                  int64_t n_max) {
+  if (!ctx || !dev_ptr || n_max < 1 || n_max > (int64_t)0x7fffffff / 2) return NBODY_EINVAL;
+  if (((uintptr_t)dev_ptr & 255u) != 0) return NBODY_EINVAL;
+  const Layout L = make_layout(ctx->p, n_max, ctx->num_cu);
+  if (bytes < L.total) return NBODY_ENOMEM;
+  ctx->ws = dev_ptr;
+  ctx->ws_bytes = bytes;
+  ctx->L = L;
+  ctx->P = carve(dev_ptr, L);
+  ctx->bound = true;
+  ctx->have_tree = false;
+  ctx->sticky = NBODY_OK;
+  hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
+  return hip_status();
+}
+
+nbody_status nbody_build_tree(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
+                              const float *z, const float *m) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!x || !y || !z || !m || n < 1) return NBODY_EINVAL;
+  if (n > ctx->L.n_max) return NBODY_ENOMEM;
+  return do_build(ctx, n, x, y, z, m);
+}
+
+nbody_status nbody_refit(nbody_ctx *ctx, const float *x, const float *y, const float *z,
+                         const float *m) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!ctx->have_tree) return NBODY_ENOTREE;
+  if (!x || !y || !z || !m) return NBODY_EINVAL;
+  return do_refit(ctx, x, y, z, m);
+}
+
+nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *axo, const float *ayo,
+                            const float *azo, float *ax, float *ay, float *az) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!ctx->have_tree) return NBODY_ENOTREE;
+  if (!ax || !ay || !az) return NBODY_EINVAL;
+  const int nnull = (axo == nullptr) + (ayo == nullptr) + (azo == nullptr);
+  if (nnull != 0 && nnull != 3) return NBODY_EINVAL;
+  return do_calc(ctx, axo, ayo, azo, ax, ay, az);
+}
+
+nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!st || n_steps < 0 || st->n < 1 || !st->x || !st->y || !st->z || !st->vx || !st->vy ||
+      !st->vz || !st->m || !st->ax || !st->ay || !st->az || !(st->dt > 0.0) ||
+      st->rebuild_interval < 0)
+    return NBODY_EINVAL;
+  if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
+  const int64_t n = st->n;
+  float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
+  if (!st->have_acc) {
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>(cdiv(n, 1024), 8192)),
+                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, x32);
+    if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+    if ((s = do_calc(ctx, nullptr, nullptr, nullptr, st->ax, st->ay, st->az)) != NBODY_OK)
+      return s;
+    if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
+      return s;
+    st->have_acc = 1;
+    ctx->since_rebuild = 0;
+    ctx->walk_sum_ms = 0.0;
+  }
+  const float hdt = (float)(0.5 * st->dt);
+  for (int32_t k = 0; k < n_steps; ++k) {
+    harvest_events(ctx);
+    bool rebuild;
+    if (st->rebuild_interval > 0)
+      rebuild = ctx->since_rebuild >= st->rebuild_interval;
+    else
+      rebuild = nbody_rebuild_decide(ctx->t_build_ms, ctx->walk_sum_ms, ctx->t_walk_ms,
+                                     ctx->since_rebuild, 64) != 0;
+    if (ctx->n != n) rebuild = true;
+    const bool time_it = !ctx->ev_pending;
+    if (time_it) (void)hipEventRecord(ctx->ev[0], ctx->st);
+    launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
+    launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32, ctx->st);
+    if (time_it) (void)hipEventRecord(ctx->ev[1], ctx->st);
+    if (rebuild) {
+      if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+      ctx->rebuilds++;
+      ctx->since_rebuild = 0;
+      ctx->walk_sum_ms = 0.0;
+    } else {
+      if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
+    }
+    if (time_it) {
+      (void)hipEventRecord(ctx->ev[2], ctx->st);
+      (void)hipEventRecord(ctx->ev[3], ctx->st);
+    }
+    if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
+      return s;
+    if (time_it) (void)hipEventRecord(ctx->ev[4], ctx->st);
+    launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
+    if (time_it) {
+      (void)hipEventRecord(ctx->ev[5], ctx->st);
+      ctx->ev_pending = true;
+      ctx->ev_had_build = rebuild;
+    }
+    ctx->since_rebuild++;
+    ctx->walk_sum_ms += ctx->t_walk_ms;
+    ctx->steps++;
+    st->t += st->dt;
+    if ((s = hip_status()) != NBODY_OK) return s;
+  }
+  return NBODY_OK;
+}
+
+nbody_status nbody_direct(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
+                          const float *z, const float *m, float *ax, float *ay, float *az) {
+  if (!ctx) return NBODY_EINVAL;
+  if (ctx->sticky != NBODY_OK) return ctx->sticky;
+  if (n < 1 || !x || !y || !z || !m || !ax || !ay || !az) return NBODY_EINVAL;
+  launch_direct(n, x, y, z, m, ctx->p.G, ctx->p.eps, ax, ay, az, ctx->st);
+  return hip_status();
+}
+
+nbody_status nbody_sync(nbody_ctx *ctx) {
+  if (!ctx) return NBODY_EINVAL;
+  if (hipStreamSynchronize(ctx->st) != hipSuccess) return ctx->sticky = NBODY_EHIP;
+  if (ctx->sticky != NBODY_OK || !ctx->bound) return ctx->sticky;
+  int32_t bits = 0;
+  if (hipMemcpy(&bits, &ctx->P.sc->status, sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess)
+    return ctx->sticky = NBODY_EHIP;
+  ctx->sticky = status_from_bits(bits);
+  harvest_events(ctx);
+  return ctx->sticky;
+}
+
+nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
+  if (!ctx || !out) return NBODY_EINVAL;
+  nbody_status s = nbody_sync(ctx);
+  if (s != NBODY_OK) return s;
+  memset(out, 0, sizeof(*out));
+  out->n = ctx->n;
+  out->steps = ctx->steps;
+  out->rebuilds = ctx->rebuilds;
+  out->t_build_ms = ctx->t_build_ms;
+  out->t_walk_ms = ctx->t_walk_ms;
+  out->t_step_ms = ctx->t_step_ms;
+  if (!ctx->have_tree) return NBODY_OK;
+  hipLaunchKernelGGL(k_stats_zero, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
+  hipLaunchKernelGGL(k_stats, dim3(256), dim3(256), 0, ctx->st, ctx->P.sc, ctx->P.gent,
+                     ctx->P.gcount);
+  DevScalars h;
+  if ((s = read_scalars(ctx, &h)) != NBODY_OK) return s;
+  out->ncell = h.ncell;
+  out->ngroup = h.ngroup;
+  out->list_entries = (int64_t)h.entries_total;
+  out->interactions = (int64_t)h.inter_total;
+  return NBODY_OK;
+}
+
+nbody_status nbody_export(nbody_ctx *ctx, int32_t what, void *dst, int64_t capacity) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!dst || capacity < 0) return NBODY_EINVAL;
+  if (!ctx->have_tree) return NBODY_ENOTREE;
+  DevScalars h;
+  if ((s = read_scalars(ctx, &h)) != NBODY_OK) return s;
+  const Ptrs &P = ctx->P;
+  const int64_t n = ctx->n, nc = h.ncell, ng = h.ngroup;
+  const void *src = nullptr;
+  int64_t count = 0;
+  size_t esz = 4;
+  switch (what) {
+    case NBODY_X_KEYS: src = ctx->keys; count = n; esz = 8; break;
+    case NBODY_X_PERM: src = ctx->perm; count = n; break;
+    case NBODY_X_LEVEL: src = P.clevel; count = nc; break;
+    case NBODY_X_PBEGIN: src = P.cpbegin; count = nc; break;
+    case NBODY_X_PCOUNT: src = P.cpcount; count = nc; break;
+    case NBODY_X_FCHILD: src = P.cfchild; count = nc; break;
+    case NBODY_X_NCHILD: src = P.cnchild; count = nc; break;
+    case NBODY_X_PARENT: src = P.cparent; count = nc; break;
+    case NBODY_X_NODE: src = P.nodeA; count = 4 * nc; break;
+    case NBODY_X_MQ: src = nullptr; count = 2 * nc; break;
+    case NBODY_X_MOM64: src = P.mom64; count = 4 * nc; esz = 8; break;
+    case NBODY_X_GBEGIN: src = P.gbegin; count = ng; break;
+    case NBODY_X_GCOUNT: src = P.gcount; count = ng; break;
+    case NBODY_X_GBOX: src = P.gbox; count = 8 * ng; break;
+    case NBODY_X_GENTRIES: src = P.gent; count = ng; break;
+    case NBODY_X_GHASH: src = P.ghash; count = ng; esz = 8; break;
+    case NBODY_X_XYZM: src = P.xyzm; count = 4 * n; break;
+    case NBODY_X_BOX: src = P.sc->box; count = 4; esz = 8; break;
+    default: return NBODY_EINVAL;
+  }
+  if (capacity < count) return NBODY_ENOMEM;
+  if (what == NBODY_X_MQ) {
+    // nodeB holds m32, q, w0, w1: copy the first two floats of each cell
+    if (hipMemcpy2DAsync(dst, 8, P.nodeB, 16, 8, (size_t)nc, hipMemcpyDeviceToDevice,
+                         ctx->st) != hipSuccess)
+      return NBODY_EHIP;
+    return NBODY_OK;
+  }
+  if (count > 0 && hipMemcpyAsync(dst, src, (size_t)count * esz, hipMemcpyDeviceToDevice,
+                                  ctx->st) != hipSuccess)
+    return NBODY_EHIP;
+  return NBODY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,338 @@
+// k_build.hip -- level-order octree and i-groups from sorted Morton keys.
+//
+// Tree definition (the paper's makeTree, Sec. 2.2; details it leaves open):
+// a cell at level l holds the particles whose key >> 3(21-l) equals its
+// prefix; it is split iff it holds more than leaf_max particles and l < 21;
+// only non-empty octants become children, consecutive in octant order; cells
+// are numbered by level, then by prefix. i-groups (the particles sharing one
+// interaction list, Sec. 1) are the cells holding at most group_max
+// particles whose parent holds more; an oversized level-21 cell is cut into
+// consecutive pieces of group_max.
+//
+// Construction without a per-level host loop. For sorted keys K and
+// cpl(a, b) = number of leading octant digits K[a] and K[b] share:
+//  * particle i starts a run of equal level-l prefix iff l > cpl(i-1, i);
+//    let s_i = cpl(i-1, i) + 1 (s_0 = 0);
+//  * the level-l cell of i holds more than W particles iff some window of
+//    W+1 consecutive particles containing i shares its level-l prefix, i.e.
+//    iff l <= M_i(W) = max over s in [i-W, i] of cpl(s, s+W);
+//  * cells containing i exist at levels 0..D_i with D_i = min(M_i(leaf_max)
+//    + 1, 21); its group cell is at level min(M_i(group_max) + 1, D_i).
+// So particle i starts the cells (l, i) for s_i <= l <= D_i. The level-order
+// index of (l, i) is the number of cells of lower level plus the number of
+// level-l cells starting before i: per-level block counts, a scan over
+// blocks, and ballots inside the block give it. The window maxima use a
+// sparse table (doubling) in LDS.
+#include "nbody_internal.h"
+
+namespace nb {
+
+constexpr int kB = kBuildThreads;
+constexpr int kH = kBuildHalo;
+constexpr int kRows = kLevels + 1;  // 22 levels + groups
+
+__device__ __forceinline__ int cpl_keys(uint64_t a, uint64_t b) {
+  const uint64_t x = a ^ b;
+  if (x == 0) return kMaxLevel;
+  return (__clzll(x) - 1) / 3;
+}
+
+// First index j > i whose key differs from K[i] in the top 3l bits
+// (galloping, then bisection). Level 0: the whole array.
+__device__ uint32_t run_end(const uint64_t *__restrict__ K, uint32_t n, uint32_t i,
+                            int l) {
+  if (l == 0) return n;
+  const int sh = 3 * (kMaxLevel - l);
+  const uint64_t p = K[i] >> sh;
+  uint32_t lo = i, hi = n;
+  uint32_t step = 1;
+  while (true) {
+    const uint64_t j = (uint64_t)lo + step;
+    if (j >= n) break;
+    if ((K[j] >> sh) != p) {
+      hi = (uint32_t)j;
+      break;
+    }
+    lo = (uint32_t)j;
+    step <<= 1;
+  }
+  while (hi - lo > 1) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if ((K[mid] >> sh) == p)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+// First index of the run of keys equal to K[i] (galloping backwards).
+__device__ uint32_t run_begin_equal(const uint64_t *__restrict__ K, uint32_t i) {
+  const uint64_t p = K[i];
+  uint32_t hi = i;  // K[hi] == p
+  int64_t lo = -1;  // K[lo] != p or lo == -1
+  uint32_t step = 1;
+  while (true) {
+    const int64_t j = (int64_t)hi - step;
+    if (j < 0) break;
+    if (K[j] != p) {
+      lo = j;
+      break;
+    }
+    hi = (uint32_t)j;
+    step <<= 1;
+  }
+  while ((int64_t)hi - lo > 1) {
+    const int64_t mid = lo + ((int64_t)hi - lo) / 2;
+    if (K[mid] == p)
+      hi = (uint32_t)mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+// In-place doubling: t[s] <- max(t[s .. s + 2^k - 1]) for the valid prefix.
+__device__ void lds_window_max(int *t, int len, int k) {
+  for (int j = 0; j < k; ++j) {
+    const int d = 1 << j;
+    int a0 = -1, a1 = -1;
+    const int t0 = threadIdx.x, t1 = threadIdx.x + kB;
+    if (t0 < len) a0 = max(t[t0], t0 + d < len ? t[t0 + d] : -1);
+    if (t1 < len) a1 = max(t[t1], t1 + d < len ? t[t1 + d] : -1);
+    __syncthreads();
+    if (t0 < len) t[t0] = a0;
+    if (t1 < len) t[t1] = a1;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int ilog2_floor(int v) { return 31 - __clz(v); }
+
+// Pass A: per sorted particle s_i, D_i, group level and group-start flag;
+// per block and row (levels 0..21, groups) the count of starts.
+__global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
+                                                uint32_t n, int leaf_max, int group_max,
+                                                uint32_t *__restrict__ pinfo,
+                                                uint32_t *__restrict__ blkcnt,
+                                                uint32_t nblk) {
+  __shared__ uint64_t sk[kB + 2 * kH];
+  __shared__ int tL[kB + kH];
+  __shared__ int tG[kB + kH];
+  __shared__ uint32_t wc[kRows][kB / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kB;
+  for (int t = threadIdx.x; t < kB + 2 * kH; t += kB) {
+    const int64_t pos = b0 - kH + t;
+    sk[t] = (pos >= 0 && pos < n) ? K[pos] : 0ull;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kB + kH; t += kB) {
+    const int64_t s = b0 - kH + t;
+    tL[t] = (s >= 0 && s + leaf_max < n) ? cpl_keys(sk[t], sk[t + leaf_max]) : -1;
+    tG[t] = (s >= 0 && s + group_max < n) ? cpl_keys(sk[t], sk[t + group_max]) : -1;
+  }
+  __syncthreads();
+  const int kLw = ilog2_floor(leaf_max + 1), kGw = ilog2_floor(group_max + 1);
+  lds_window_max(tL, kB + kH, kLw);
+  lds_window_max(tG, kB + kH, kGw);
+  const int64_t i = b0 + threadIdx.x;
+  const bool valid = i < n;
+  const int li = threadIdx.x + kH;
+  int s = 0, D = 0, g = 0, gflag = 0;
+  if (valid) {
+    s = (i == 0) ? 0 : cpl_keys(sk[li - 1], sk[li]) + 1;
+    const int M = max(tL[li - leaf_max], tL[li - (1 << kLw) + 1]);
+    const int MG = max(tG[li - group_max], tG[li - (1 << kGw) + 1]);
+    D = min(M + 1, kMaxLevel);
+    g = min(MG + 1, D);
+    if (MG >= kMaxLevel) {
+      const uint32_t a = run_begin_equal(K, (uint32_t)i);
+      gflag = (((uint32_t)i - a) % (uint32_t)group_max) == 0;
+    } else {
+      gflag = s <= g;
+    }
+    pinfo[i] = (uint32_t)s | ((uint32_t)D << 5) | ((uint32_t)g << 10) |
+               ((uint32_t)gflag << 15);
+  }
+  const int w = threadIdx.x >> 6;
+  for (int l = 0; l < kRows; ++l) {
+    const bool bit = valid && (l < kLevels ? (s <= l && l <= D) : gflag);
+    const uint64_t b = __ballot(bit);
+    if (lane_id() == 0) wc[l][w] = (uint32_t)__popcll(b);
+  }
+  __syncthreads();
+  if (threadIdx.x < kRows) {
+    uint32_t t = 0;
+    for (int q = 0; q < kB / 64; ++q) t += wc[threadIdx.x][q];
+    blkcnt[threadIdx.x * nblk + blockIdx.x] = t;
+  }
+}
+
+// Pass B: exclusive scan of every row of blkcnt over the blocks; row totals
+// go to blkcnt[kRows * nblk + row].
+__global__ __launch_bounds__(256) void k_build_b(uint32_t *__restrict__ blkcnt,
+                                                 uint32_t nblk) {
+  __shared__ uint32_t wsum[4];
+  uint32_t *row = blkcnt + (int64_t)blockIdx.x * nblk;
+  const uint32_t per = (nblk + 255) / 256;
+  const uint32_t k0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (uint32_t k = k0; k < k0 + per && k < nblk; ++k) s += row[k];
+  const uint32_t inc = wave_incl_scan(s);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int q = 0; q < 4; ++q) {
+    if (q < w) off += wsum[q];
+    tot += wsum[q];
+  }
+  uint32_t run = off + inc - s;
+  for (uint32_t k = k0; k < k0 + per && k < nblk; ++k) {
+    const uint32_t v = row[k];
+    row[k] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) blkcnt[(int64_t)kRows * nblk + blockIdx.x] = tot;
+}
+
+// Pass C: level offsets, cell and group counts, group sentinel.
+__global__ void k_build_c(const uint32_t *__restrict__ blkcnt, uint32_t nblk, uint32_t n,
+                          DevScalars *sc, uint32_t *__restrict__ gbegin,
+                          int64_t cell_cap) {
+  if (threadIdx.x != 0) return;
+  const uint32_t *tot = blkcnt + (int64_t)kRows * nblk;
+  uint32_t o = 0;
+  for (int l = 0; l < kLevels; ++l) {
+    sc->lvl_off[l] = o;
+    o += tot[l];
+  }
+  sc->lvl_off[kLevels] = o;
+  if ((int64_t)o > cell_cap) {
+    atomicOr(&sc->status, kStCapacity);
+    o = 0;
+  }
+  sc->ncell = o;
+  sc->ngroup = tot[kLevels];
+  gbegin[tot[kLevels]] = n;
+}
+
+// Pass D: write every cell (l, i) and every group start.
+__global__ __launch_bounds__(kB) void k_build_d(
+    const uint64_t *__restrict__ K, uint32_t n, const uint32_t *__restrict__ pinfo,
+    const uint32_t *__restrict__ blkcnt, uint32_t nblk, const DevScalars *__restrict__ sc,
+    int64_t cell_cap, int32_t *__restrict__ clevel, uint32_t *__restrict__ cpbegin,
+    uint32_t *__restrict__ cpcount, int32_t *__restrict__ cfchild,
+    int32_t *__restrict__ cnchild, float4 *__restrict__ nodeB,
+    uint32_t *__restrict__ leafof, uint32_t *__restrict__ gbegin) {
+  __shared__ uint32_t wpre[kRows][kB / 64];
+  __shared__ uint32_t lvl_off[kLevels + 1];
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const bool valid = i < n;
+  const uint32_t pi = valid ? pinfo[i] : 0u;
+  const int s = pi & 31, D = (pi >> 5) & 31;
+  const bool gflag = valid && ((pi >> 15) & 1u);
+  const int w = threadIdx.x >> 6;
+  if (threadIdx.x <= kLevels) lvl_off[threadIdx.x] = sc->lvl_off[threadIdx.x];
+  for (int l = 0; l < kRows; ++l) {
+    const bool bit = valid && (l < kLevels ? (s <= l && l <= D) : gflag);
+    const uint64_t b = __ballot(bit);
+    if (lane_id() == 0) wpre[l][w] = (uint32_t)__popcll(b);
+  }
+  __syncthreads();
+  if (threadIdx.x < kRows) {
+    uint32_t o = 0;
+    for (int q = 0; q < kB / 64; ++q) {
+      const uint32_t t = wpre[threadIdx.x][q];
+      wpre[threadIdx.x][q] = o;
+      o += t;
+    }
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  uint32_t idx_prev = 0;
+  for (int l = 0; l < kRows; ++l) {
+    const bool bit = valid && (l < kLevels ? (s <= l && l <= D) : gflag);
+    const uint64_t b = __ballot(bit);
+    if (!bit) continue;
+    const uint32_t rank = blkcnt[(int64_t)l * nblk + blockIdx.x] + wpre[l][w] +
+                          (uint32_t)__popcll(b & lt);
+    if (l == kLevels) {  // group start
+      gbegin[rank] = (uint32_t)i;
+      continue;
+    }
+    const uint32_t idx = lvl_off[l] + rank;
+    if ((int64_t)idx >= cell_cap) continue;
+    if (l > s) cfchild[idx_prev] = (int32_t)idx;  // (l-1, i) is internal
+    const uint32_t end = run_end(K, n, (uint32_t)i, l);
+    const uint32_t cnt = end - (uint32_t)i;
+    clevel[idx] = l;
+    cpbegin[idx] = (uint32_t)i;
+    cpcount[idx] = cnt;
+    uint32_t *wB = reinterpret_cast<uint32_t *>(&nodeB[idx]);
+    if (l == D) {  // leaf
+      cfchild[idx] = -1;
+      cnchild[idx] = 0;
+      wB[2] = (uint32_t)i;
+      wB[3] = cnt | kLeafBit;
+      for (uint32_t p = (uint32_t)i; p < end; ++p) leafof[p] = idx;
+    } else {
+      int nc = 0;
+      uint32_t j = (uint32_t)i;
+      while (j < end) {
+        j = run_end(K, n, j, l + 1);
+        ++nc;
+      }
+      cnchild[idx] = nc;
+      wB[3] = (uint32_t)nc;
+      // wB[2] (first child) is written with cfchild below
+    }
+    idx_prev = idx;
+  }
+}
+
+// Pass E: parents, node first-child words, group sizes.
+__global__ __launch_bounds__(256) void k_build_e(DevScalars *__restrict__ sc,
+                                                 const int32_t *__restrict__ cfchild,
+                                                 const int32_t *__restrict__ cnchild,
+                                                 int32_t *__restrict__ cparent,
+                                                 float4 *__restrict__ nodeB,
+                                                 const uint32_t *__restrict__ gbegin,
+                                                 uint32_t *__restrict__ gcount) {
+  const uint32_t nc = sc->ncell, ng = sc->ngroup;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += stride) {
+    if (c == 0) cparent[0] = -1;
+    const int k = cnchild[c];
+    if (k > 0) {
+      const int32_t f = cfchild[c];
+      if (f <= (int32_t)c || k > 8 || (uint32_t)(f + k) > nc) {
+        atomicOr(&sc->status, kStCorrupt);
+        continue;
+      }
+      reinterpret_cast<uint32_t *>(&nodeB[c])[2] = (uint32_t)f;
+      for (int q = 0; q < k; ++q) cparent[f + q] = (int32_t)c;
+    }
+  }
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng; g += stride)
+    gcount[g] = gbegin[g + 1] - gbegin[g];
+}
+
+void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
+                  const Ptrs &P, const Layout &L, hipStream_t st) {
+  const uint32_t nblk = (uint32_t)cdiv(n, kB);
+  hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n,
+                     leaf_max, group_max, P.pinfo, P.blkcnt, nblk);
+  hipLaunchKernelGGL(k_build_b, dim3(kRows), dim3(256), 0, st, P.blkcnt, nblk);
+  hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, P.blkcnt, nblk, (uint32_t)n,
+                     P.sc, P.gbegin, L.cell_cap);
+  hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, P.pinfo,
+                     P.blkcnt, nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount,
+                     P.cfchild, P.cnchild, P.nodeB, P.leafof, P.gbegin);
+  int64_t ge = cdiv(n, 256);
+  if (ge > 4096) ge = 4096;
+  hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.cfchild, P.cnchild,
+                     P.cparent, P.nodeB, P.gbegin, P.gcount);
+}
+
+}  // namespace nb

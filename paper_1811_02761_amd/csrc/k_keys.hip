@@ -1,0 +1,159 @@
+// k_keys.hip -- root cube, 63-bit Morton keys and the key-order gather.
+//
+// The paper builds its tree from sorted particles ("makeTree", Sec. 2.2 and
+// Sec. 4.1) without naming the key. Here: the root cube has its corner at
+// the exact FP32 minimum of each axis and side L = the smallest power of two
+// not below the largest axis extent (computed in FP64); each axis is
+// quantised to 21 bits, q = min(floor((x - lo) * 2^21 / L), 2^21 - 1), and
+// the bits are interleaved x, y, z from the most significant end, so the
+// level-l octant digit is bits 3(21-l)..3(21-l)+2 of the key.
+#include "nbody_internal.h"
+
+namespace nb {
+
+__global__ void k_bbox_init(DevScalars *sc) {
+  if (threadIdx.x < 3) {
+    sc->bbox[threadIdx.x] = 0xffffffffu;     // min of ordered ints
+    sc->bbox[3 + threadIdx.x] = 0u;          // max
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x,
+                                              const float *__restrict__ y,
+                                              const float *__restrict__ z,
+                                              int64_t n, DevScalars *sc) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      bad |= !isfinite(v[k]);
+      lo[k] = fminf(lo[k], v[k]);
+      hi[k] = fmaxf(hi[k], v[k]);
+    }
+  }
+  __shared__ float red[6][4];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float a = wave_min(lo[k]);
+    const float b = wave_max(hi[k]);
+    if (lane_id() == 0) {
+      red[k][w] = a;
+      red[3 + k][w] = b;
+    }
+  }
+  if (__any(bad) && lane_id() == 0) atomicOr(&sc->status, kStNonFinite);
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    float a = red[k][0], b = red[3 + k][0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+      a = fminf(a, red[k][q]);
+      b = fmaxf(b, red[3 + k][q]);
+    }
+    atomicMin(&sc->bbox[k], f2ord(a));
+    atomicMax(&sc->bbox[3 + k], f2ord(b));
+  }
+}
+
+// Spread the low 21 bits of v so that bit b lands on bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t quantise21(float v, double lo, double scale) {
+  const double t = ((double)v - lo) * scale;
+  if (t >= 2097151.0) return 2097151u;
+  if (t <= 0.0) return 0u;
+  return (uint32_t)t;  // t > 0: truncation is floor
+}
+
+__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
+                                              const float *__restrict__ y,
+                                              const float *__restrict__ z,
+                                              int64_t n, DevScalars *sc,
+                                              uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ vals) {
+  // root cube from the reduced bounds (every thread recomputes it)
+  double lo[3], ext = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float a = ord2f(sc->bbox[k]);
+    const float b = ord2f(sc->bbox[3 + k]);
+    lo[k] = (double)a;
+    const double e = (double)b - (double)a;
+    ext = e > ext ? e : ext;
+  }
+  int eL = 0;  // L = 2^eL
+  if (ext > 0.0) {
+    int e;
+    const double f = frexp(ext, &e);
+    eL = (f == 0.5) ? e - 1 : e;
+  }
+  const double scale = ldexp(1.0, 21 - eL);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->box[0] = lo[0];
+    sc->box[1] = lo[1];
+    sc->box[2] = lo[2];
+    sc->box[3] = ldexp(1.0, eL);
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t qx = quantise21(x[i], lo[0], scale);
+    const uint32_t qy = quantise21(y[i], lo[1], scale);
+    const uint32_t qz = quantise21(z[i], lo[2], scale);
+    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    vals[i] = (uint32_t)i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather(const float *__restrict__ x,
+                                                const float *__restrict__ y,
+                                                const float *__restrict__ z,
+                                                const float *__restrict__ m,
+                                                const uint32_t *__restrict__ perm,
+                                                int64_t n, float4 *__restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = perm[i];
+    out[i] = make_float4(x[p], y[p], z[p], m[p]);
+  }
+}
+
+static int grid_for(int64_t n, int per_thread, int cap) {
+  int64_t g = cdiv(n, 256LL * per_thread);
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+void launch_bbox(const float *x, const float *y, const float *z, int64_t n,
+                 DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, sc);
+  hipLaunchKernelGGL(k_bbox, dim3(grid_for(n, 8, 2048)), dim3(256), 0, st, x, y, z,
+                     n, sc);
+}
+
+void launch_keys(const float *x, const float *y, const float *z, int64_t n,
+                 DevScalars *sc, uint64_t *keys, uint32_t *vals, hipStream_t st) {
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z, n,
+                     sc, keys, vals);
+}
+
+void launch_gather(const float *x, const float *y, const float *z, const float *m,
+                   const uint32_t *perm, int64_t n, float4 *xyzm, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z,
+                     m, perm, n, xyzm);
+}
+
+}  // namespace nb

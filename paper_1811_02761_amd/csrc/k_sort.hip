@@ -1,0 +1,181 @@
+// k_sort.hip -- stable LSD radix sort of (63-bit key, 32-bit index) pairs.
+//
+// The paper's tree build spends most of its time in a key/value radix sort
+// (Sec. 4.1). This is a reduce-then-scan LSD sort with 8-bit digits and 8
+// passes, written for wave64: every pass is a per-tile digit histogram, a
+// per-digit exclusive scan over tiles, and a scatter whose in-tile rank comes
+// from a wave-level multisplit (eight ballots give the lanes sharing a digit;
+// their popcount below the lane is the rank). Ranks follow input position, so
+// each pass is stable and equal keys keep their input order.
+#include "nbody_internal.h"
+
+namespace nb {
+
+constexpr int kWaves = kSortThreads / 64;
+constexpr int kWaveKeys = kSortTile / kWaves;  // 1024 keys per wave
+
+// Lanes whose digit equals this lane's digit (among `valid` lanes).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+  uint64_t peers = valid;
+#pragma unroll
+  for (int b = 0; b < kSortBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(
+    const uint64_t *__restrict__ keys, int64_t n, int shift,
+    uint32_t *__restrict__ hist, int64_t nblk) {
+  __shared__ uint32_t cnt[kWaves][kSortRadix];
+  for (int t = threadIdx.x; t < kWaves * kSortRadix; t += kSortThreads)
+    (&cnt[0][0])[t] = 0;
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int64_t base = blockIdx.x * (int64_t)kSortTile + w * kWaveKeys;
+  for (int it = 0; it < kWaveKeys / 64; ++it) {
+    const int64_t i = base + it * 64 + lane_id();
+    const bool valid = i < n;
+    const uint64_t vmask = __ballot(valid);
+    if (vmask == 0) break;
+    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & (kSortRadix - 1) : 0u;
+    const uint64_t peers = match_digit(d, vmask);
+    if (valid && (peers & lanemask_lt()) == 0) cnt[w][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kSortRadix; d += kSortThreads) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) s += cnt[q][d];
+    hist[d * nblk + blockIdx.x] = s;
+  }
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim = kSortThreads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tot,
+                                                    uint32_t *wsum) {
+  const uint32_t inc = wave_incl_scan(v);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, all = 0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+    if (q < w) off += wsum[q];
+    all += wsum[q];
+  }
+  if (tot) *tot = all;
+  __syncthreads();
+  return off + inc - v;
+}
+
+// One workgroup per digit: exclusive scan of hist[d][0..nblk) in place and
+// the digit total.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t *__restrict__ hist,
+                                                             int64_t nblk,
+                                                             uint32_t *__restrict__ totals) {
+  __shared__ uint32_t wsum[kWaves];
+  uint32_t *row = hist + blockIdx.x * nblk;
+  const int64_t per = cdiv(nblk, kSortThreads);
+  const int64_t b0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int64_t k = b0; k < b0 + per && k < nblk; ++k) s += row[k];
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, &tot, wsum);
+  for (int64_t k = b0; k < b0 + per && k < nblk; ++k) {
+    const uint32_t v = row[k];
+    row[k] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+    int shift, const uint32_t *__restrict__ hist, int64_t nblk,
+    const uint32_t *__restrict__ totals, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout) {
+  __shared__ uint32_t cnt[kWaves][kSortRadix];
+  __shared__ uint32_t dbase[kSortRadix];
+  __shared__ uint32_t wsum[kWaves];
+  for (int t = threadIdx.x; t < kWaves * kSortRadix; t += kSortThreads)
+    (&cnt[0][0])[t] = 0;
+  // digit start = exclusive scan of totals; plus this tile's offset
+  {
+    const uint32_t tv = totals[threadIdx.x];
+    const uint32_t ex = block_excl_scan(tv, nullptr, wsum);
+    dbase[threadIdx.x] = ex + hist[threadIdx.x * nblk + blockIdx.x];
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int64_t base = blockIdx.x * (int64_t)kSortTile + w * kWaveKeys;
+  uint64_t k[kSortItems];
+  uint32_t v[kSortItems];
+  uint32_t r[kSortItems];
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + it * 64 + lane_id();
+    const bool valid = i < n;
+    const uint64_t vmask = __ballot(valid);
+    k[it] = valid ? kin[i] : 0ull;
+    v[it] = valid ? vin[i] : 0u;
+    const uint32_t d = (uint32_t)(k[it] >> shift) & (kSortRadix - 1);
+    const uint64_t peers = match_digit(d, vmask);
+    const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
+    uint32_t c0 = 0;
+    if (valid) c0 = cnt[w][d];
+    r[it] = c0 + below;
+    // every lane has read the counter before the digit's first lane bumps it
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) cnt[w][d] = c0 + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // per digit: offsets of the waves within the tile
+  {
+    const int d = threadIdx.x;
+    uint32_t o = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t t = cnt[q][d];
+      cnt[q][d] = o;
+      o += t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t i = base + it * 64 + lane_id();
+    if (i < n) {
+      const uint32_t d = (uint32_t)(k[it] >> shift) & (kSortRadix - 1);
+      const uint32_t pos = dbase[d] + cnt[w][d] + r[it];
+      kout[pos] = k[it];
+      vout[pos] = v[it];
+    }
+  }
+}
+
+void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
+                 uint32_t *valsB, uint32_t *hist, int64_t blocks, hipStream_t st,
+                 uint64_t **keys_out, uint32_t **vals_out) {
+  const int64_t nblk = cdiv(n, kSortTile);
+  (void)blocks;
+  uint32_t *totals = hist + (int64_t)kSortRadix * nblk;
+  uint64_t *ki = keysA, *ko = keysB;
+  uint32_t *vi = valsA, *vo = valsB;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = pass * kSortBits;
+    hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortThreads), 0, st, ki, n, shift,
+                       hist, nblk);
+    hipLaunchKernelGGL(k_sort_scan, dim3(kSortRadix), dim3(kSortThreads), 0, st, hist,
+                       nblk, totals);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortThreads), 0, st, ki, vi, n,
+                       shift, hist, nblk, totals, ko, vo);
+    uint64_t *tk = ki; ki = ko; ko = tk;
+    uint32_t *tv = vi; vi = vo; vo = tv;
+  }
+  *keys_out = ki;
+  *vals_out = vi;
+}
+
+}  // namespace nb

@@ -1,0 +1,362 @@
+// k_walk.hip -- group bounds and the group-wise tree walk (Sec. 1).
+//
+// One wavefront serves one i-group at a time, taking groups from a global
+// work queue until the queue is empty (persistent kernel). For its group it
+// traverses the tree breadth first from the root: 64 candidate cells at a
+// time are tested against the acceleration MAC of Eq. 2 (one lane per cell);
+// accepted cells enter the interaction list as pseudo-particles (centre of
+// mass, mass), opened leaves contribute their particles, opened internal
+// cells append their children to the wave's frontier ring in global memory
+// (the paper's per-SM cell buffer, Sec. 3). Offsets come from wave prefix
+// sums. The list lives in LDS; whenever it holds `list_tile` entries it is
+// flushed: every lane adds Eq. 1 over the tile for its particle, in FP32.
+//
+// Canonical order: list entries appear in breadth-first candidate order and
+// a flush only cuts that sequence, so each lane's summation order is fixed by
+// the group alone. It does not depend on the tile size, the queue order or
+// which wave runs the group: results are bit-identical across them.
+//
+// Lane layout: groups of at most 8, 16 or 32 members use S = 8, 4 or 2
+// "streams": lane = stream * (64 / S) + member, stream s adds the entries
+// whose list index is s mod S, and the S partial sums are combined at the
+// end by a fixed butterfly. S depends only on the group size.
+//
+// Group-wise MAC (a reading of Eq. 2 for a shared list): d is the distance
+// from the cell's centre of mass to the group's bounding box (no larger than
+// any member's distance) and |a_old| the smallest previous acceleration in
+// the group; accept iff d^2 > b^2 and delta_acc*|a_old|*d^4 >= G m b^2, all in
+// FP32. Without a_old (bootstrap) accept iff d^2 > 4 b^2.
+#include "nbody_internal.h"
+
+namespace nb {
+
+__global__ __launch_bounds__(256) void k_group_bounds(
+    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
+    const uint32_t *__restrict__ gcount, const float4 *__restrict__ xyzm,
+    const uint32_t *__restrict__ perm, const float *__restrict__ axo,
+    const float *__restrict__ ayo, const float *__restrict__ azo, float delta_acc,
+    float4 *__restrict__ gbox) {
+  const uint32_t ng = sc->ngroup;
+  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < ng;
+       g += wstride) {
+    const uint32_t b = gbegin[g], c = gcount[g];
+    const uint32_t k = lane_id();
+    const bool ok = k < c;
+    const float4 p = xyzm[b + (ok ? k : 0)];
+    float lx = p.x, ly = p.y, lz = p.z;
+    float amin = INFINITY;
+    if (axo && ok) {
+      const uint32_t o = perm[b + k];
+      const float ax = axo[o], ay = ayo[o], az = azo[o];
+      amin = __fsqrt_rn(__builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
+    }
+    const float hx = wave_max(lx), hy = wave_max(ly), hz = wave_max(lz);
+    lx = wave_min(lx);
+    ly = wave_min(ly);
+    lz = wave_min(lz);
+    amin = axo ? wave_min(amin) : 0.0f;
+    if (k == 0) {
+      const float dA = delta_acc * amin;
+      gbox[2 * g] = make_float4(lx, ly, lz, dA);
+      gbox[2 * g + 1] = make_float4(hx, hy, hz, amin);
+    }
+  }
+}
+
+struct WalkArgs {
+  const float4 *nodeA;
+  const float4 *nodeB;
+  const float4 *xyzm;
+  const uint32_t *gbegin;
+  const uint32_t *gcount;
+  const float4 *gbox;
+  const uint32_t *perm;
+  const uint32_t *order;
+  uint32_t *frontier;
+  uint32_t *gent;
+  unsigned long long *ghash;
+  DevScalars *sc;
+  float *ax, *ay, *az;
+  float G, eps2;
+  uint32_t n;
+  uint32_t tile;
+  uint32_t fmask;
+  int bootstrap;
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t v) {
+  v += 0x9E3779B97F4A7C15ull;
+  v = (v ^ (v >> 30)) * 0xBF58476D1CE4E5B9ull;
+  v = (v ^ (v >> 27)) * 0x94D049BB133111EBull;
+  return v ^ (v >> 31);
+}
+
+template <bool kComp>
+struct Acc3 {
+  float x = 0.f, y = 0.f, z = 0.f;
+  __device__ __forceinline__ void add(float dx, float dy, float dz, float f) {
+    x = __builtin_fmaf(f, dx, x);
+    y = __builtin_fmaf(f, dy, y);
+    z = __builtin_fmaf(f, dz, z);
+  }
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+    ox = x;
+    oy = y;
+    oz = z;
+  }
+};
+
+// Neumaier's compensated summation (Neumaier 1974) per component.
+template <>
+struct Acc3<true> {
+  float x = 0.f, y = 0.f, z = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+  __device__ __forceinline__ static void nadd(float &s, float &c, float v) {
+    const float t = s + v;
+    c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
+    s = t;
+  }
+  __device__ __forceinline__ void add(float dx, float dy, float dz, float f) {
+    nadd(x, cx, f * dx);
+    nadd(y, cy, f * dy);
+    nadd(z, cz, f * dz);
+  }
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+    ox = x + cx;
+    oy = y + cy;
+    oz = z + cz;
+  }
+};
+
+template <bool kComp>
+__device__ __forceinline__ void flush_tile(const float4 *__restrict__ list, uint32_t cnt,
+                                           uint32_t stream, uint32_t S, float4 pi,
+                                           float eps2, Acc3<kComp> &acc) {
+#pragma unroll 4
+  for (uint32_t j = stream; j < cnt; j += S) {
+    const float4 e = list[j];
+    const float dx = e.x - pi.x;
+    const float dy = e.y - pi.y;
+    const float dz = e.z - pi.z;
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float mr = e.w * rinv;
+    const float rinv2 = rinv * rinv;
+    acc.add(dx, dy, dz, mr * rinv2);
+  }
+}
+
+template <bool kComp, bool kHash>
+__global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
+  HIP_DYNAMIC_SHARED(float4, lds_list)
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  float4 *list = lds_list + wv * a.tile;
+  uint32_t *ring =
+      a.frontier + (size_t)(blockIdx.x * kWalkWavesPerWG + wv) * (size_t)(a.fmask + 1);
+  const uint32_t F = a.fmask + 1;
+  const uint32_t ng = a.sc->ngroup;
+  const uint32_t ncell = a.sc->ncell;
+  const uint32_t npart = a.n;
+  for (;;) {
+    uint32_t qi = 0;
+    if (lane == 0) qi = atomicAdd(&a.sc->queue_head, 1u);
+    qi = __builtin_amdgcn_readfirstlane(qi);
+    if (qi >= ng) break;
+    const uint32_t g = a.order ? a.order[qi] : qi;
+    const uint32_t gb = a.gbegin[g], gc = a.gcount[g];
+    const float4 glo = a.gbox[2 * g], ghi = a.gbox[2 * g + 1];
+    const float dA = glo.w;
+    const uint32_t S = gc <= 8 ? 8u : gc <= 16 ? 4u : gc <= 32 ? 2u : 1u;
+    const uint32_t Wd = 64u / S;
+    const uint32_t member = lane & (Wd - 1);
+    const uint32_t stream = lane / Wd;
+    const bool mem_ok = member < gc;
+    const float4 pi = a.xyzm[gb + (mem_ok ? member : 0u)];
+    Acc3<kComp> acc;
+    uint64_t hsum = 0;
+    if (lane == 0) ring[0] = 0u;  // the root
+    uint32_t head = 0, tail = 1, cnt = 0;
+    uint32_t entries = 0;
+    bool overflow = false, corrupt = false;
+    while (head < tail) {
+      const uint32_t nc = min(64u, tail - head);
+      if (head + nc > ncell) {  // a tree visits each cell at most once
+        corrupt = true;
+        break;
+      }
+      const uint32_t cc = lane < nc ? ring[(head + lane) & a.fmask] : 0u;
+      const bool bad_c = lane < nc && cc >= ncell;
+      const bool has = lane < nc && !bad_c;
+      const uint32_t c = has ? cc : 0u;
+      head += nc;
+      float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+      if (has) {
+        A = a.nodeA[c];
+        B = a.nodeB[c];
+      }
+      const uint32_t w0 = __float_as_uint(B.z), w1 = __float_as_uint(B.w);
+      {
+        const bool lf = (w1 & kLeafBit) != 0u;
+        const uint32_t k = w1 & ~kLeafBit;
+        const bool bad_n = has && (lf ? (w0 > npart || k > npart - w0)
+                                      : (k > 8u || w0 > ncell || k > ncell - w0));
+        if (__ballot(bad_c || bad_n)) {
+          corrupt = true;
+          break;
+        }
+      }
+      bool accept = false;
+      if (has) {
+        const float tx = fmaxf(fmaxf(glo.x - A.x, A.x - ghi.x), 0.0f);
+        const float ty = fmaxf(fmaxf(glo.y - A.y, A.y - ghi.y), 0.0f);
+        const float tz = fmaxf(fmaxf(glo.z - A.z, A.z - ghi.z), 0.0f);
+        const float d2 = __builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx));
+        if (d2 > A.w) {
+          if (a.bootstrap) {
+            const float four_b2 = 4.0f * A.w;
+            accept = d2 > four_b2;
+          } else {
+            const float d4 = d2 * d2;
+            const float lhs = dA * d4;
+            accept = lhs >= B.y;
+          }
+        }
+      }
+      const bool leaf = (w1 & kLeafBit) != 0u;
+      const uint32_t ne = !has ? 0u : accept ? 1u : leaf ? (w1 & ~kLeafBit) : 0u;
+      const uint32_t nch = (has && !accept && !leaf) ? w1 : 0u;
+      // children -> frontier ring
+      const uint32_t chi = wave_incl_scan(nch);
+      const uint32_t chtot = __builtin_amdgcn_readfirstlane(wave_bcast_last(chi));
+      if (tail - head + chtot > F) {
+        overflow = true;
+        break;
+      }
+      for (uint32_t k = 0; k < nch; ++k) ring[(tail + chi - nch + k) & a.fmask] = w0 + k;
+      tail += chtot;
+      // entries -> LDS list (flushing full tiles)
+      const uint32_t ei = wave_incl_scan(ne);
+      const uint32_t etot = __builtin_amdgcn_readfirstlane(wave_bcast_last(ei));
+      const uint32_t eoff = ei - ne;
+      if (kHash) {
+        if (accept) hsum += mix64((uint64_t)c);
+        else if (ne)
+          for (uint32_t k = 0; k < ne; ++k) hsum += mix64((1ull << 40) + w0 + k);
+      }
+      uint32_t done = 0;
+      while (done < etot) {
+        const uint32_t take = min(a.tile - cnt, etot - done);
+        const uint32_t jlo = max(eoff, done), jhi = min(eoff + ne, done + take);
+        for (uint32_t j = jlo; j < jhi; ++j) {
+          const float4 e = accept ? make_float4(A.x, A.y, A.z, B.x) : a.xyzm[w0 + (j - eoff)];
+          list[cnt + (j - done)] = e;
+        }
+        cnt += take;
+        done += take;
+        if (cnt == a.tile) {
+          __builtin_amdgcn_wave_barrier();
+          flush_tile<kComp>(list, cnt, stream, S, pi, a.eps2, acc);
+          __builtin_amdgcn_wave_barrier();
+          cnt = 0;
+        }
+      }
+      entries += etot;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (overflow || corrupt) {
+      if (lane == 0) atomicOr(&a.sc->status, overflow ? kStOverflow : kStCorrupt);
+      cnt = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    flush_tile<kComp>(list, cnt, stream, S, pi, a.eps2, acc);
+    __builtin_amdgcn_wave_barrier();
+    float sx, sy, sz;
+    acc.total(sx, sy, sz);
+    for (uint32_t d = Wd; d < 64u; d <<= 1) {
+      sx += __shfl_xor(sx, (int)d, 64);
+      sy += __shfl_xor(sy, (int)d, 64);
+      sz += __shfl_xor(sz, (int)d, 64);
+    }
+    if (lane < gc) {  // lane == member here (stream 0)
+      const uint32_t o = a.perm[gb + lane];
+      a.ax[o] = a.G * sx;
+      a.ay[o] = a.G * sy;
+      a.az[o] = a.G * sz;
+    }
+    if (kHash) {
+      uint32_t lo = (uint32_t)hsum, hi = (uint32_t)(hsum >> 32);
+      // 64-bit wave sum by 32-bit halves with carries
+      for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t olo = __shfl_xor(lo, d, 64), ohi = __shfl_xor(hi, d, 64);
+        const uint32_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1u : 0u);
+        lo = nlo;
+      }
+      if (lane == 0) a.ghash[g] = ((uint64_t)hi << 32) | lo;
+    }
+    if (lane == 0) a.gent[g] = (overflow || corrupt) ? 0xffffffffu : entries;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+  int64_t g = cdiv(n, 256);
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, v, n);
+}
+
+void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
+                         const uint32_t *perm, int64_t n, float delta_acc, const Ptrs &P,
+                         hipStream_t st) {
+  int64_t g = cdiv(n, 4 * 8);  // up to n groups, 4 waves per block
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_group_bounds, dim3(g), dim3(256), 0, st, P.sc, P.gbegin, P.gcount,
+                     P.xyzm, perm, axo, ayo, azo, delta_acc, P.gbox);
+}
+
+void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, float *ay,
+                 float *az, const Ptrs &P, hipStream_t st) {
+  (void)n;
+  WalkArgs a;
+  a.nodeA = P.nodeA;
+  a.nodeB = P.nodeB;
+  a.xyzm = P.xyzm;
+  a.gbegin = P.gbegin;
+  a.gcount = P.gcount;
+  a.gbox = P.gbox;
+  a.perm = perm;
+  a.order = c.use_order ? P.order : nullptr;
+  a.frontier = P.frontier;
+  a.gent = P.gent;
+  a.ghash = P.ghash;
+  a.sc = P.sc;
+  a.ax = ax;
+  a.ay = ay;
+  a.az = az;
+  a.G = c.G;
+  a.eps2 = c.eps * c.eps;
+  a.n = (uint32_t)n;
+  a.tile = (uint32_t)c.list_tile;
+  a.fmask = (uint32_t)c.frontier_cap - 1u;
+  a.bootstrap = c.bootstrap;
+  const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
+  const size_t lds = (size_t)kWalkWavesPerWG * c.list_tile * sizeof(float4);
+  launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
+  if (c.compensated)
+    hipLaunchKernelGGL((k_walk<true, true>), dim3(blocks), dim3(64 * kWalkWavesPerWG), lds,
+                       st, a);
+  else
+    hipLaunchKernelGGL((k_walk<false, true>), dim3(blocks), dim3(64 * kWalkWavesPerWG), lds,
+                       st, a);
+}
+
+}  // namespace nb

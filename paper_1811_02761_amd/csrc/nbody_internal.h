@@ -1,0 +1,180 @@
+// nbody_internal.h -- shared definitions of the gfx950 library (not public).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nbody.h"
+
+namespace nb {
+
+constexpr int kMaxLevel = 21;       // 3 x 21-bit Morton keys
+constexpr int kLevels = kMaxLevel + 1;
+constexpr uint32_t kLeafBit = 0x80000000u;  // node word w1: leaf flag
+constexpr int kSortBits = 8;
+constexpr int kSortRadix = 1 << kSortBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per workgroup
+constexpr int kBuildThreads = 256;                   // particles per build block
+constexpr int kBuildHalo = 64;                       // >= max(leaf_max, group_max)
+constexpr int kWalkWavesPerWG = 4;
+
+// device status bits (sticky)
+constexpr int32_t kStNonFinite = 1;
+constexpr int32_t kStOverflow = 2;
+constexpr int32_t kStCapacity = 4;
+constexpr int32_t kStCorrupt = 8;  // internal consistency check failed
+
+// Device scalars kept in the workspace.
+struct DevScalars {
+  uint32_t bbox[6];        // ordered-int min x,y,z then max x,y,z
+  int32_t status;          // sticky error bits
+  uint32_t ncell;
+  uint32_t ngroup;
+  uint32_t queue_head;     // walk work queue
+  uint32_t lvl_off[kLevels + 1];
+  double box[4];           // lo x,y,z and side L
+  unsigned long long entries_total;
+  unsigned long long inter_total;
+  uint32_t pad[8];
+};
+
+// Offsets of the workspace, all 256-byte aligned.
+struct Layout {
+  int64_t n_max = 0;
+  int64_t cell_cap = 0;
+  int64_t sort_blocks = 0;
+  int64_t build_blocks = 0;
+  int64_t walk_waves = 0;
+  int64_t frontier_cap = 0;
+  size_t off_scalars, off_keysA, off_keysB, off_valsA, off_valsB, off_hist,
+      off_xyzm, off_x32, off_pinfo, off_leafof, off_blkcnt, off_clevel,
+      off_cpbegin, off_cpcount, off_cfchild, off_cnchild, off_cparent,
+      off_mom64, off_nodeA, off_nodeB, off_gbegin, off_gcount, off_gbox,
+      off_gent, off_ghash, off_order, off_frontier, off_prevcnt;
+  size_t total = 0;
+};
+
+struct Ptrs {
+  DevScalars *sc;
+  uint64_t *keysA, *keysB;
+  uint32_t *valsA, *valsB;
+  uint32_t *hist;       // sort histograms [radix][blocks] + totals[radix]
+  float4 *xyzm;         // sorted x, y, z, m
+  float *x32;           // FP32 image of state positions [3][n] (caller order)
+  uint32_t *pinfo;      // per sorted particle: s | D << 5 | gflag << 10
+  uint32_t *leafof;     // per sorted particle: its leaf cell
+  uint32_t *blkcnt;     // build block counts [kLevels + 1][blocks]
+  int32_t *clevel;
+  uint32_t *cpbegin, *cpcount;
+  int32_t *cfchild, *cnchild, *cparent;
+  double4 *mom64;       // M, Sx, Sy, Sz
+  float4 *nodeA;        // com x, y, z, b2
+  float4 *nodeB;        // m32, q, w0, w1 (bit patterns for w0/w1)
+  uint32_t *gbegin, *gcount;
+  float4 *gbox;         // [2g] = lo xyz, dA; [2g+1] = hi xyz, amin
+  uint32_t *gent;       // per group: list entries of the last walk
+  unsigned long long *ghash;
+  uint32_t *order;      // walk queue order
+  uint32_t *frontier;   // per wave ring
+  uint32_t *prevcnt;    // per group: entries of the previous walk (ordering)
+};
+
+Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
+Ptrs carve(void *base, const Layout &L);
+
+// ---- launchers (each enqueues on `st`; grid sizes depend only on n) ----
+void launch_bbox(const float *x, const float *y, const float *z, int64_t n,
+                 DevScalars *sc, hipStream_t st);
+void launch_keys(const float *x, const float *y, const float *z, int64_t n,
+                 DevScalars *sc, uint64_t *keys, uint32_t *vals, hipStream_t st);
+// returns pointer (A or B) holding the sorted result
+void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
+                 uint32_t *valsB, uint32_t *hist, int64_t blocks, hipStream_t st,
+                 uint64_t **keys_out, uint32_t **vals_out);
+void launch_gather(const float *x, const float *y, const float *z, const float *m,
+                   const uint32_t *perm, int64_t n, float4 *xyzm, hipStream_t st);
+void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
+                  const Ptrs &P, const Layout &L, hipStream_t st);
+void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L,
+                    hipStream_t st);
+void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
+                         const uint32_t *perm, int64_t n, float delta_acc,
+                         const Ptrs &P, hipStream_t st);
+struct WalkCfg {
+  float G, eps;
+  int bootstrap;
+  int compensated;
+  int list_tile;
+  int frontier_cap;
+  int waves_per_cu;
+  int num_cu;
+  int use_order;
+};
+void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
+                 float *ay, float *az, const Ptrs &P, hipStream_t st);
+void launch_direct(int64_t n, const float *x, const float *y, const float *z,
+                   const float *m, float G, float eps, float *ax, float *ay,
+                   float *az, hipStream_t st);
+void launch_kick(int64_t n, float *vx, float *vy, float *vz, const float *ax,
+                 const float *ay, const float *az, float hdt, hipStream_t st);
+void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
+                  const float *vy, const float *vz, double dt, float *x32,
+                  hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+void launch_order_by_count(int64_t n, const Ptrs &P, hipStream_t st);
+
+// ---- device helpers ----
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// wave-wide inclusive prefix sum of an unsigned value (all 64 lanes must be
+// active; inactive contributions are passed as 0)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if ((int)__lane_id() >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_bcast_last(uint32_t v) {
+  return __shfl(v, 63, 64);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t o = __shfl_xor(v, d, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// order-preserving float <-> uint map (for atomic min/max of floats)
+__device__ __forceinline__ uint32_t f2ord(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace nb
