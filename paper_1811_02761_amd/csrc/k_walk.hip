@@ -37,9 +37,12 @@ __global__ __launch_bounds__(256) void k_group_bounds(
     const float *__restrict__ ayo, const float *__restrict__ azo, float delta_acc,
     float4 *__restrict__ gbox) {
   const uint32_t ng = sc->ngroup;
-  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < ng;
-       g += wstride) {
+  const uint32_t wstride = gridDim.x * (blockDim.x >> 6);
+  // wave-uniform loop (scalar index): the wave reductions below run with
+  // every lane active, and the results are stored by every lane
+  const uint32_t g0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+                                                     (threadIdx.x >> 6));
+  for (uint32_t g = g0; g < ng; g += wstride) {
     const uint32_t b = gbegin[g], c = gcount[g];
     const uint32_t k = lane_id();
     const bool ok = k < c;
@@ -56,11 +59,9 @@ __global__ __launch_bounds__(256) void k_group_bounds(
     ly = wave_min(ly);
     lz = wave_min(lz);
     amin = axo ? wave_min(amin) : 0.0f;
-    if (k == 0) {
-      const float dA = delta_acc * amin;
-      gbox[2 * g] = make_float4(lx, ly, lz, dA);
-      gbox[2 * g + 1] = make_float4(hx, hy, hz, amin);
-    }
+    const float dA = delta_acc * amin;
+    gbox[2 * g] = make_float4(lx, ly, lz, dA);
+    gbox[2 * g + 1] = make_float4(hx, hy, hz, amin);
   }
 }
 
@@ -158,10 +159,14 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
   const uint32_t ng = a.sc->ngroup;
   const uint32_t ncell = a.sc->ncell;
   const uint32_t npart = a.n;
+  // No lane-predicated region may sit in this loop: the compiler threads such
+  // regions across the back-edge, and a wave that re-enters with lane 0 masked
+  // off reads a stale queue index. Every lane joins the queue atomic (lane 0
+  // adds 1, the rest 0) and the per-group results below are stored by every
+  // lane (same value, same address).
   for (;;) {
-    uint32_t qi = 0;
-    if (lane == 0) qi = atomicAdd(&a.sc->queue_head, 1u);
-    qi = __builtin_amdgcn_readfirstlane(qi);
+    const uint32_t claim = atomicAdd(&a.sc->queue_head, lane == 0 ? 1u : 0u);
+    const uint32_t qi = __builtin_amdgcn_readfirstlane(claim);
     if (qi >= ng) break;
     const uint32_t g = a.order ? a.order[qi] : qi;
     const uint32_t gb = a.gbegin[g], gc = a.gcount[g];
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
     const float4 pi = a.xyzm[gb + (mem_ok ? member : 0u)];
     Acc3<kComp> acc;
     uint64_t hsum = 0;
-    if (lane == 0) ring[0] = 0u;  // the root
+    ring[0] = 0u;  // the root (every lane stores the same value)
     uint32_t head = 0, tail = 1, cnt = 0;
     uint32_t entries = 0;
     bool overflow = false, corrupt = false;
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (overflow || corrupt) {
-      if (lane == 0) atomicOr(&a.sc->status, overflow ? kStOverflow : kStCorrupt);
+      atomicOr(&a.sc->status, overflow ? kStOverflow : kStCorrupt);
       cnt = 0;
     }
     __builtin_amdgcn_wave_barrier();
@@ -294,9 +299,9 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
         hi = hi + ohi + (nlo < lo ? 1u : 0u);
         lo = nlo;
       }
-      if (lane == 0) a.ghash[g] = ((uint64_t)hi << 32) | lo;
+      a.ghash[g] = ((uint64_t)hi << 32) | lo;  // butterfly: every lane holds the sum
     }
-    if (lane == 0) a.gent[g] = (overflow || corrupt) ? 0xffffffffu : entries;
+    a.gent[g] = (overflow || corrupt) ? 0xffffffffu : entries;
   }
 }
 
