@@ -1,0 +1,210 @@
+"""Benchmark: leapfrog steps of the octree gravity hot path on one MI355X.
+
+Workload (default): three-component galaxy, N = 2^23 equal-mass particles
+(80 % NFW halo truncated at 30 scale radii, 5 % Hernquist bulge, 15 %
+exponential disc with scale height 0.1 scale length), softening 2^-6, Eq. 2
+accuracy parameter 2^-9, kick-drift-kick steps of dt = 2^-7 with every
+particle active each step and the tree rebuild interval chosen by the
+library's build/walk timing rule. A step = kick, drift (FP64), tree rebuild
+or refit (keys, sort, build, moments), group boxes, group-wise walk, kick.
+
+Prints one JSON line with s/step, interactions/s, the walk's fraction of the
+MI355X FP32 vector peak (22 Flop per interaction, rsqrt counted as 4), the
+walk's roofline record and the CPU oracle baseline on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_INTERACTION = 22  # 3 sub, 3 fma (r^2), rsqrt (4), 3 mul, 3 fma
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (dense, packed) peak
+FP32_NONPACKED_TFLOPS = 78.6
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pos32, m, eps, dacc, seconds=12.0):
+    """The oracle (FP64 C, OpenMP) on this host: the full tree pipeline on all
+    particles, then the walk on a random sample of groups sized to about
+    `seconds`; the step time is build + walk scaled to all groups."""
+    import oracle
+
+    x, y, z = (np.ascontiguousarray(pos32[:, k]) for k in range(3))
+    nth = oracle.nthreads_default()
+    t0 = time.perf_counter()
+    k, box = oracle.keys(x, y, z)
+    perm, ks = oracle.sort(k)
+    sx, sy, sz, sm = x[perm], y[perm], z[perm], m[perm]
+    cells = oracle.build_tree(ks, 16)
+    mom = oracle.moments(cells, sx, sy, sz, sm, 1.0)
+    grp = oracle.groups(cells, 64)
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(7)
+    n = len(x)
+
+    def walk(sel, sa):
+        """Walk the selected groups; sa = previous accelerations (sorted order)
+        or None for the bootstrap criterion. Returns time, interactions, acc."""
+        g = oracle.Groups(grp.begin[sel], grp.count[sel], grp.cell[sel])
+        lo, hi, amin, dA = oracle.group_bounds(g, sx, sy, sz, sa, dacc)
+        ax, ay, az = (np.zeros(n) for _ in range(3))
+        ent = np.empty(g.n, np.int64)
+        gh = np.empty(g.n, np.uint64)
+        t = time.perf_counter()
+        oracle.lib().orc_walk(n, sx, sy, sz, sm, cells.n, cells.pbegin, cells.pcount,
+                              cells.first_child, cells.n_child, mom.m32,
+                              np.ascontiguousarray(mom.com[:, 0]),
+                              np.ascontiguousarray(mom.com[:, 1]),
+                              np.ascontiguousarray(mom.com[:, 2]), mom.b2, mom.q, g.n,
+                              g.begin, g.count, np.ascontiguousarray(lo.reshape(-1)),
+                              np.ascontiguousarray(hi.reshape(-1)), dA, int(sa is None),
+                              1.0, eps, ax, ay, az, ent, gh, nth)
+        return (time.perf_counter() - t, int((ent * g.count).sum()),
+                np.stack([ax, ay, az], 1).astype(np.float32))
+
+    def mac_walk(sel):
+        # a_old of the sampled members from the oracle's own bootstrap walk
+        _, _, a0 = walk(sel, None)
+        return walk(sel, a0)
+
+    probe = rng.choice(grp.n, size=min(64, grp.n), replace=False)
+    tp, _, _ = mac_walk(probe)
+    per_group = max(tp / len(probe), 1e-7)
+    ns = int(min(grp.n, max(64, seconds / per_group)))
+    sel = np.sort(rng.choice(grp.n, size=ns, replace=False))
+    tw, inter, _ = mac_walk(sel)
+    t_walk_full = tw * grp.n / ns
+    return {
+        "value": t_build + t_walk_full,
+        "unit": "s/step",
+        "cores": nth,
+        "kind": "oracle",
+        "sample": ("FP64 oracle: full tree build of all %d particles (%.1f s, 1 thread) + "
+                   "walk of %d of %d groups (%.1f s, %d threads), walk scaled to all groups"
+                   % (len(x), t_build, ns, grp.n, tw, nth)),
+        "interactions_per_s": inter / tw if tw > 0 else None,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--n", type=int, default=1 << 23)
+    ap.add_argument("--delta", type=float, default=2.0 ** -9)
+    ap.add_argument("--eps", type=float, default=2.0 ** -6)
+    ap.add_argument("--dt", type=float, default=2.0 ** -7)
+    ap.add_argument("--rebuild", type=int, default=0, help="0 = automatic interval")
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import nbody_inputs as I
+    import paper_1811_02761_amd as nb
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    log("generating galaxy n=%d seed=%d" % (args.n, args.seed))
+    gal = I.galaxy(args.n, args.seed)
+    m32 = gal.mass.astype(np.float32)
+    params = nb.Params(eps=args.eps, delta_acc=args.delta)
+    ctx = nb.Context(params, n_max=args.n)
+    st = nb.State.from_numpy(gal.pos, gal.vel, gal.mass, dt=args.dt,
+                             rebuild_interval=args.rebuild)
+    log("warmup %d steps" % args.warmup)
+    ctx.step(st, max(args.warmup, 1))
+    ctx.sync()
+    ctx.timing(True)
+    s0 = ctx.stats()
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    ctx.step(st, args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = ctx.stats()
+    sec_per_step = (t1 - t0) / args.steps
+    walks = s1["walk_calls"]
+    walk_ms = s1["walk_ms_sum"] / max(walks, 1)
+    inter_per_walk = s1["interactions_sum"] / max(walks, 1)
+    entries_per_walk = s1["entries_sum"] / max(walks, 1)
+    achieved = FLOP_PER_INTERACTION * inter_per_walk / (walk_ms * 1e-3) / 1e12
+    rebuilds = s1["rebuilds"] - s0["rebuilds"]
+    log("s/step %.4g, walk %.3f ms x %d, %.3g interactions/walk, rebuilds %d, build %.3f ms"
+        % (sec_per_step, walk_ms, walks, inter_per_walk, rebuilds,
+           s1["build_ms_sum"] / max(s1["build_calls"], 1)))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline (bounded sample)")
+        xyz = np.stack([st.x.cpu().numpy(), st.y.cpu().numpy(), st.z.cpu().numpy()], 1)
+        cpu = cpu_baseline(xyz.astype(np.float32), m32, args.eps, args.delta)
+        log(cpu["sample"])
+
+    rec = {
+        "metric": "s/step and particle-cell interactions/s at N=2^23; % FP32 vector peak; "
+                  "plain vs learned",
+        "value": sec_per_step,
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("galaxy N=%d (NFW halo 80%%, Hernquist bulge 5%%, exponential disc "
+                         "15%%, z_d=0.1 R_d), eps=2^%d, delta_acc=2^%d, KDK dt=2^%d, all "
+                         "particles active every step, rebuild interval %s"
+                         % (args.n, round(np.log2(args.eps)), round(np.log2(args.delta)),
+                            round(np.log2(args.dt)),
+                            "automatic" if args.rebuild == 0 else str(args.rebuild))),
+            "n": args.n,
+            "leaf_max": params.leaf_max,
+            "group_max": params.group_max,
+            "order": "plain",
+        },
+        "interactions_per_s": inter_per_walk / (walk_ms * 1e-3),
+        "interactions_per_step": inter_per_walk,
+        "list_entries_per_step": entries_per_walk,
+        "walk_ms": walk_ms,
+        "build_ms": s1["build_ms_sum"] / max(s1["build_calls"], 1),
+        "rebuilds_in_timed_steps": rebuilds,
+        "pct_fp32_vector_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_walk",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": None,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,13 +105,25 @@ typedef struct {
   int32_t rebuild_interval;
 } nbody_state;
 
-/* Per-call statistics (host struct filled by nbody_get_stats, BLOCKING). */
+/* Statistics (host struct filled by nbody_get_stats, BLOCKING).
+ *  list_entries, interactions: of the last walk (interaction = one pair of a
+ *  group member and a list entry);
+ *  t_build_ms, t_walk_ms: latest measured tree build / walk kernel time;
+ *  walk_ms_sum/walk_calls, build_ms_sum/build_calls, entries_sum and
+ *  interactions_sum: totals since the last nbody_timing call (HIP events on
+ *  the context's stream around each walk launch and each build). */
 typedef struct {
   int64_t n, ncell, ngroup;
-  int64_t list_entries;  /* sum over groups of interaction-list entries */
-  int64_t interactions;  /* sum over groups of entries x group size */
+  int64_t list_entries;
+  int64_t interactions;
   int64_t steps, rebuilds;
-  double t_build_ms, t_walk_ms, t_step_ms; /* last measured (events) */
+  double t_build_ms, t_walk_ms;
+  double walk_ms_sum;
+  int64_t walk_calls;
+  double build_ms_sum;
+  int64_t build_calls;
+  int64_t entries_sum;
+  int64_t interactions_sum;
 } nbody_stats;
 
 /* What nbody_export copies (element type, length). */
@@ -206,6 +218,11 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
 
 /* BLOCKING: synchronise the stream and return the sticky status. */
 nbody_status nbody_sync(nbody_ctx *ctx);
+
+/* BLOCKING: zero the timing totals of nbody_stats; with enable != 0 also
+ * accumulate the interaction count of every later walk on the device (one
+ * small reduction kernel after each walk). */
+nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable);
 
 /* Host-only rebuild rule used by nbody_step when rebuild_interval == 0
  * (the paper tunes the rebuild interval to minimise tree-construction plus

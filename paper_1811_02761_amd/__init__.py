@@ -65,7 +65,10 @@ class _Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("ncell", C.c_int64), ("ngroup", C.c_int64),
                 ("list_entries", C.c_int64), ("interactions", C.c_int64),
                 ("steps", C.c_int64), ("rebuilds", C.c_int64), ("t_build_ms", C.c_double),
-                ("t_walk_ms", C.c_double), ("t_step_ms", C.c_double)]
+                ("t_walk_ms", C.c_double), ("walk_ms_sum", C.c_double),
+                ("walk_calls", C.c_int64), ("build_ms_sum", C.c_double),
+                ("build_calls", C.c_int64), ("entries_sum", C.c_int64),
+                ("interactions_sum", C.c_int64)]
 
 
 # every function declared in include/nbody.h (checked by the tests)
@@ -73,7 +76,7 @@ HEADER_FUNCTIONS = [
     "nbody_abi_version", "nbody_strerror", "nbody_params_default", "nbody_create",
     "nbody_destroy", "nbody_workspace_query", "nbody_bind_workspace", "nbody_build_tree",
     "nbody_refit", "nbody_calc_acc", "nbody_step", "nbody_direct", "nbody_export",
-    "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide",
+    "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide", "nbody_timing",
 ]
 
 _lib = None
@@ -105,6 +108,7 @@ def lib():
         L.nbody_export.argtypes = [vp, i32, vp, i64]
         L.nbody_get_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.nbody_sync.argtypes = [vp]
+        L.nbody_timing.argtypes = [vp, i32]
         L.nbody_rebuild_decide.argtypes = [C.c_double, C.c_double, C.c_double, i32, i32]
         L.nbody_rebuild_decide.restype = i32
         for f in HEADER_FUNCTIONS:
@@ -251,6 +255,10 @@ class Context:
 
     def sync(self):
         _check(lib().nbody_sync(self._h), "nbody_sync")
+
+    def timing(self, enable: bool = True):
+        """Zero the timing totals; with enable, count interactions of every walk."""
+        _check(lib().nbody_timing(self._h, int(bool(enable))), "nbody_timing")
 
     def stats(self) -> dict:
         s = _Stats()

@@ -29,10 +29,16 @@ struct nbody_ctx {
   int64_t steps = 0, rebuilds = 0;
   int32_t since_rebuild = 0;
   double walk_sum_ms = 0.0;  // walk time since the last rebuild
-  double t_build_ms = 0.0, t_walk_ms = 0.0, t_step_ms = 0.0;
-  hipEvent_t ev[6] = {};
-  bool ev_pending = false;
-  bool ev_had_build = false;
+  double t_build_ms = 0.0, t_walk_ms = 0.0;  // latest measured (events)
+  // timed spans: a ring of (start, end) event pairs around each tree build
+  // and each walk launch, harvested without blocking
+  static constexpr int kSpans = 64;
+  hipEvent_t ev_a[kSpans] = {}, ev_b[kSpans] = {};
+  int span_kind[kSpans] = {};
+  int sp_head = 0, sp_count = 0;
+  double walk_ms_sum = 0.0, build_ms_sum = 0.0;
+  int64_t walk_calls = 0, build_calls = 0;
+  bool counting = false;  // accumulate interactions of every walk on the device
 };
 
 namespace {
@@ -196,6 +202,32 @@ __global__ __launch_bounds__(256) void k_stats(DevScalars *sc, const uint32_t *g
   }
 }
 
+// Running totals over walks while counting is on (nbody_timing).
+__global__ __launch_bounds__(256) void k_stats_accum(DevScalars *sc, const uint32_t *gent,
+                                                     const uint32_t *gcount) {
+  const uint32_t ng = sc->ngroup;
+  unsigned long long e = 0, it = 0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = gent[g] == 0xffffffffu ? 0u : gent[g];
+    e += v;
+    it += (unsigned long long)v * gcount[g];
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    e += __shfl_xor(e, d, 64);
+    it += __shfl_xor(it, d, 64);
+  }
+  if (lane_id() == 0) {
+    atomicAdd(&sc->entries_acc, e);
+    atomicAdd(&sc->inter_acc, it);
+  }
+}
+
+__global__ void k_acc_zero(DevScalars *sc) {
+  sc->entries_acc = 0;
+  sc->inter_acc = 0;
+}
+
 __global__ void k_stats_zero(DevScalars *sc) {
   sc->entries_total = 0;
   sc->inter_total = 0;
@@ -209,6 +241,8 @@ __global__ void k_scalars_init(DevScalars *sc) {
   for (int l = 0; l <= kLevels; ++l) sc->lvl_off[l] = 0;
   sc->entries_total = 0;
   sc->inter_total = 0;
+  sc->entries_acc = 0;
+  sc->inter_acc = 0;
 }
 
 // FP32 image of FP64 positions (caller order) into x32[3][n].
@@ -245,9 +279,54 @@ WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap) {
   return c;
 }
 
+void harvest(nbody_ctx *ctx, bool block);
+
+int span_begin(nbody_ctx *ctx, int kind) {
+  if (ctx->sp_count == nbody_ctx::kSpans) harvest(ctx, true);
+  const int i = (ctx->sp_head + ctx->sp_count) % nbody_ctx::kSpans;
+  ctx->span_kind[i] = kind;
+  (void)hipEventRecord(ctx->ev_a[i], ctx->st);
+  return i;
+}
+
+void span_end(nbody_ctx *ctx, int i) {
+  (void)hipEventRecord(ctx->ev_b[i], ctx->st);
+  ctx->sp_count++;
+}
+
+// Fold finished spans into the timers (oldest first); with block, wait for
+// the oldest pending span only.
+void harvest(nbody_ctx *ctx, bool block) {
+  bool first = true;
+  while (ctx->sp_count > 0) {
+    const int i = ctx->sp_head;
+    if (block && first) {
+      if (hipEventSynchronize(ctx->ev_b[i]) != hipSuccess) return;
+    } else if (hipEventQuery(ctx->ev_b[i]) != hipSuccess) {
+      return;
+    }
+    first = false;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev_a[i], ctx->ev_b[i]) == hipSuccess) {
+      if (ctx->span_kind[i] == 0) {
+        ctx->t_build_ms = ms;
+        ctx->build_ms_sum += ms;
+        ctx->build_calls++;
+      } else {
+        ctx->t_walk_ms = ms;
+        ctx->walk_ms_sum += ms;
+        ctx->walk_calls++;
+      }
+    }
+    ctx->sp_head = (ctx->sp_head + 1) % nbody_ctx::kSpans;
+    ctx->sp_count--;
+  }
+}
+
 nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
                       const float *z, const float *m) {
   const Ptrs &P = ctx->P;
+  const int sp = span_begin(ctx, 0);
   launch_bbox(x, y, z, n, P.sc, ctx->st);
   launch_keys(x, y, z, n, P.sc, P.keysA, P.valsA, ctx->st);
   uint64_t *ks;
@@ -257,6 +336,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
   launch_gather(x, y, z, m, pm, n, P.xyzm, ctx->st);
   launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, P, ctx->L, ctx->st);
   launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
+  span_end(ctx, sp);
   ctx->keys = ks;
   ctx->perm = pm;
   ctx->n = n;
@@ -275,7 +355,13 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
                      float *ax, float *ay, float *az) {
   const bool boot = axo == nullptr;
   launch_group_bounds(axo, ayo, azo, ctx->perm, ctx->n, ctx->p.delta_acc, ctx->P, ctx->st);
+  launch_fill_u32(&ctx->P.sc->queue_head, 0u, 1, ctx->st);
+  const int sp = span_begin(ctx, 1);
   launch_walk(walk_cfg(ctx, boot), ctx->perm, ctx->n, ax, ay, az, ctx->P, ctx->st);
+  span_end(ctx, sp);
+  if (ctx->counting)
+    hipLaunchKernelGGL(k_stats_accum, dim3(256), dim3(256), 0, ctx->st, ctx->P.sc,
+                       ctx->P.gent, ctx->P.gcount);
   return hip_status();
 }
 
@@ -285,18 +371,6 @@ nbody_status read_scalars(nbody_ctx *ctx, DevScalars *h) {
     return NBODY_EHIP;
   if (hipStreamSynchronize(ctx->st) != hipSuccess) return NBODY_EHIP;
   return NBODY_OK;
-}
-
-// Non-blocking harvest of the last step's event timings.
-void harvest_events(nbody_ctx *ctx) {
-  if (!ctx->ev_pending) return;
-  if (hipEventQuery(ctx->ev[5]) != hipSuccess) return;
-  float tb = 0.f, tw = 0.f, ts = 0.f;
-  if (ctx->ev_had_build && hipEventElapsedTime(&tb, ctx->ev[1], ctx->ev[2]) == hipSuccess)
-    ctx->t_build_ms = tb;
-  if (hipEventElapsedTime(&tw, ctx->ev[3], ctx->ev[4]) == hipSuccess) ctx->t_walk_ms = tw;
-  if (hipEventElapsedTime(&ts, ctx->ev[0], ctx->ev[5]) == hipSuccess) ctx->t_step_ms = ts;
-  ctx->ev_pending = false;
 }
 
 }  // namespace
@@ -356,9 +430,10 @@ nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **o
     delete c;
     return NBODY_EHIP;
   }
-  for (auto &e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
-      delete c;
+  for (int i = 0; i < nbody_ctx::kSpans; ++i)
+    if (hipEventCreate(&c->ev_a[i]) != hipSuccess ||
+        hipEventCreate(&c->ev_b[i]) != hipSuccess) {
+      nbody_destroy(c);
       return NBODY_EHIP;
     }
   *out = c;
@@ -367,8 +442,10 @@ nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **o
 
 void nbody_destroy(nbody_ctx *ctx) {
   if (!ctx) return;
-  for (auto &e : ctx->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < nbody_ctx::kSpans; ++i) {
+    if (ctx->ev_a[i]) (void)hipEventDestroy(ctx->ev_a[i]);
+    if (ctx->ev_b[i]) (void)hipEventDestroy(ctx->ev_b[i]);
+  }
   delete ctx;
 }
 
@@ -452,7 +529,7 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   }
   const float hdt = (float)(0.5 * st->dt);
   for (int32_t k = 0; k < n_steps; ++k) {
-    harvest_events(ctx);
+    harvest(ctx, false);
     bool rebuild;
     if (st->rebuild_interval > 0)
       rebuild = ctx->since_rebuild >= st->rebuild_interval;
@@ -460,11 +537,8 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       rebuild = nbody_rebuild_decide(ctx->t_build_ms, ctx->walk_sum_ms, ctx->t_walk_ms,
                                      ctx->since_rebuild, 64) != 0;
     if (ctx->n != n) rebuild = true;
-    const bool time_it = !ctx->ev_pending;
-    if (time_it) (void)hipEventRecord(ctx->ev[0], ctx->st);
     launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
     launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32, ctx->st);
-    if (time_it) (void)hipEventRecord(ctx->ev[1], ctx->st);
     if (rebuild) {
       if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
       ctx->rebuilds++;
@@ -473,20 +547,11 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     } else {
       if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
     }
-    if (time_it) {
-      (void)hipEventRecord(ctx->ev[2], ctx->st);
-      (void)hipEventRecord(ctx->ev[3], ctx->st);
-    }
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
-    if (time_it) (void)hipEventRecord(ctx->ev[4], ctx->st);
     launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
-    if (time_it) {
-      (void)hipEventRecord(ctx->ev[5], ctx->st);
-      ctx->ev_pending = true;
-      ctx->ev_had_build = rebuild;
-    }
     ctx->since_rebuild++;
+    // the controller uses the latest walk time that has been measured
     ctx->walk_sum_ms += ctx->t_walk_ms;
     ctx->steps++;
     st->t += st->dt;
@@ -512,8 +577,21 @@ nbody_status nbody_sync(nbody_ctx *ctx) {
   if (hipMemcpy(&bits, &ctx->P.sc->status, sizeof(bits), hipMemcpyDeviceToHost) != hipSuccess)
     return ctx->sticky = NBODY_EHIP;
   ctx->sticky = status_from_bits(bits);
-  harvest_events(ctx);
+  harvest(ctx, false);
   return ctx->sticky;
+}
+
+nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable) {
+  if (!ctx) return NBODY_EINVAL;
+  if (ctx->sticky != NBODY_OK) return ctx->sticky;
+  if (!ctx->bound) return NBODY_ENOMEM;
+  if (hipStreamSynchronize(ctx->st) != hipSuccess) return ctx->sticky = NBODY_EHIP;
+  harvest(ctx, false);
+  ctx->walk_ms_sum = ctx->build_ms_sum = 0.0;
+  ctx->walk_calls = ctx->build_calls = 0;
+  ctx->counting = enable != 0;
+  hipLaunchKernelGGL(k_acc_zero, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
+  return hip_status();
 }
 
 nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
@@ -526,7 +604,10 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
   out->rebuilds = ctx->rebuilds;
   out->t_build_ms = ctx->t_build_ms;
   out->t_walk_ms = ctx->t_walk_ms;
-  out->t_step_ms = ctx->t_step_ms;
+  out->walk_ms_sum = ctx->walk_ms_sum;
+  out->walk_calls = ctx->walk_calls;
+  out->build_ms_sum = ctx->build_ms_sum;
+  out->build_calls = ctx->build_calls;
   if (!ctx->have_tree) return NBODY_OK;
   hipLaunchKernelGGL(k_stats_zero, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
   hipLaunchKernelGGL(k_stats, dim3(256), dim3(256), 0, ctx->st, ctx->P.sc, ctx->P.gent,
@@ -537,6 +618,8 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
   out->ngroup = h.ngroup;
   out->list_entries = (int64_t)h.entries_total;
   out->interactions = (int64_t)h.inter_total;
+  out->entries_sum = (int64_t)h.entries_acc;
+  out->interactions_sum = (int64_t)h.inter_acc;
   return NBODY_OK;
 }
 

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_group_bounds(
     if (axo && ok) {
       const uint32_t o = perm[b + k];
       const float ax = axo[o], ay = ayo[o], az = azo[o];
-      amin = __fsqrt_rn(__builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
+      amin = sqrt_rn(__builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
     }
     const float hx = wave_max(lx), hy = wave_max(ly), hz = wave_max(lz);
     lx = wave_min(lx);
@@ -355,7 +355,6 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   a.bootstrap = c.bootstrap;
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
   const size_t lds = (size_t)kWalkWavesPerWG * c.list_tile * sizeof(float4);
-  launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
   if (c.compensated)
     hipLaunchKernelGGL((k_walk<true, true>), dim3(blocks), dim3(64 * kWalkWavesPerWG), lds,
                        st, a);

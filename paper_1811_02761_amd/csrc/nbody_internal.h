@@ -36,6 +36,8 @@ struct DevScalars {
   double box[4];           // lo x,y,z and side L
   unsigned long long entries_total;
   unsigned long long inter_total;
+  unsigned long long entries_acc;  // running totals while counting
+  unsigned long long inter_acc;
   uint32_t pad[8];
 };
 
@@ -111,6 +113,7 @@ struct WalkCfg {
   int num_cu;
   int use_order;
 };
+// enqueue the walk kernel (the queue head must already be zero)
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
                  float *ay, float *az, const Ptrs &P, hipStream_t st);
 void launch_direct(int64_t n, const float *x, const float *y, const float *z,
@@ -176,5 +179,32 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
 }
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Correctly rounded FP32 square root of a finite x >= 0. The hardware
+// estimate (v_sqrt_f32, within about 1 ulp) is corrected by the midpoint
+// test: y = RN(sqrt x) iff x lies between the squares of the midpoints to
+// y's neighbours. A midpoint has at most 25 significant bits, so its square
+// is exact in FP64, and sqrt(x) is never exactly a midpoint for an FP32 x.
+__device__ __forceinline__ float sqrt_rn(float x) {
+  float y = __builtin_sqrtf(x);
+  if (!(x > 0.0f)) return y;  // 0 (and anything non-positive) as is
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const float yu = __uint_as_float(__float_as_uint(y) + 1u);
+    const double mu = 0.5 * ((double)y + (double)yu);
+    if ((double)x > mu * mu) {
+      y = yu;
+      continue;
+    }
+    const float yl = __uint_as_float(__float_as_uint(y) - 1u);
+    const double ml = 0.5 * ((double)y + (double)yl);
+    if ((double)x < ml * ml) {
+      y = yl;
+      continue;
+    }
+    break;
+  }
+  return y;
+}
 
 }  // namespace nb
