@@ -63,7 +63,7 @@ def lib():
                                   f32p, f32p, C.c_float, f32p, f32p, f32p, f32p,
                                   f32p, f32p] + [C.c_void_p] * 4
         L.orc_groups.argtypes = [C.c_int64, i32p, i64p, i64p, i64p, i32p, C.c_int32,
-                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+                                 C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_groups.restype = C.c_int64
         L.orc_group_bounds.argtypes = [C.c_int64, i64p, i64p, f32p, f32p, f32p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
@@ -211,10 +211,10 @@ class Groups:
         return int(self.begin.shape[0])
 
 
-def groups(cells: Cells, group_max=64) -> Groups:
+def groups(cells: Cells, group_max=64, merge=0) -> Groups:
     nc = cells.n
     args = (nc, cells.level, cells.pbegin, cells.pcount, cells.first_child, cells.n_child,
-            group_max)
+            group_max, int(merge))
     ng = lib().orc_groups(*args, 0, None, None, None)
     g = Groups(np.empty(ng, np.int64), np.empty(ng, np.int64), np.empty(ng, np.int64))
     lib().orc_groups(*args, ng, _ptr(g.begin), _ptr(g.count), _ptr(g.cell))
@@ -270,7 +270,7 @@ class TreeResult:
 
 
 def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 ** -9,
-                leaf_max=16, group_max=64, nthreads=None) -> TreeResult:
+                leaf_max=16, group_max=64, group_merge=0, nthreads=None) -> TreeResult:
     """All steps of the tree method for FP32 inputs in caller order.
 
     ``a_old`` (n, 3) in caller order, or None for the bootstrap pass
@@ -282,7 +282,7 @@ def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 *
     sx, sy, sz, sm = x[perm], y[perm], z[perm], m[perm]
     cells = build_tree(ks, leaf_max)
     mom = moments(cells, sx, sy, sz, sm, G)
-    grp = groups(cells, group_max)
+    grp = groups(cells, group_max, group_merge)
     sa = None if a_old is None else np.asarray(a_old, np.float32)[perm]
     glo, ghi, gamin, gdA = group_bounds(grp, sx, sy, sz, sa, delta_acc)
     ax, ay, az = (np.empty(n) for _ in range(3))

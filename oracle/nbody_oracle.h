@@ -86,12 +86,15 @@ void orc_moments(int64_t ncell, const int64_t *pbegin, const int64_t *pcount,
 /* i-groups: cells holding at most group_max particles (or at level 21)
  * whose parent holds more than group_max particles; the root if n <=
  * group_max. Listed in sorted-particle order; a group cell holding more than
- * group_max particles is cut into consecutive pieces of group_max. Returns
- * the count (query with cap = 0). gcell = the cell of each group. */
+ * group_max particles is cut into consecutive pieces of group_max. With
+ * merge != 0, consecutive sibling group cells are joined greedily (in octant
+ * order) while the joined count stays within group_max. Returns the count
+ * (query with cap = 0). gcell = the group's cell (the parent for a joined
+ * group). */
 int64_t orc_groups(int64_t ncell, const int32_t *level, const int64_t *pbegin,
                    const int64_t *pcount, const int64_t *first_child,
-                   const int32_t *n_child, int32_t group_max, int64_t cap,
-                   int64_t *gbegin, int64_t *gcount, int64_t *gcell);
+                   const int32_t *n_child, int32_t group_max, int32_t merge,
+                   int64_t cap, int64_t *gbegin, int64_t *gcount, int64_t *gcell);
 
 /* Per group: exact FP32 bounding box of the members, amin = min over members
  * of sqrtf(fmaf(az,az,fmaf(ay,ay,ax*ax))) of the previous acceleration, and
