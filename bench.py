@@ -34,7 +34,7 @@ def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pos32, m, eps, dacc, seconds=12.0):
+def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, seconds=12.0):
     """The oracle (FP64 C, OpenMP) on this host: the full tree pipeline on all
     particles, then the walk on a random sample of groups sized to about
     `seconds`; the step time is build + walk scaled to all groups."""
@@ -46,9 +46,9 @@ def cpu_baseline(pos32, m, eps, dacc, seconds=12.0):
     k, box = oracle.keys(x, y, z)
     perm, ks = oracle.sort(k)
     sx, sy, sz, sm = x[perm], y[perm], z[perm], m[perm]
-    cells = oracle.build_tree(ks, 16)
+    cells = oracle.build_tree(ks, leaf_max)
     mom = oracle.moments(cells, sx, sy, sz, sm, 1.0)
-    grp = oracle.groups(cells, 64)
+    grp = oracle.groups(cells, group_max, group_merge)
     t_build = time.perf_counter() - t0
     rng = np.random.default_rng(7)
     n = len(x)
@@ -108,6 +108,12 @@ def main():
     ap.add_argument("--dt", type=float, default=2.0 ** -7)
     ap.add_argument("--rebuild", type=int, default=0, help="0 = automatic interval")
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--waves", type=int, default=0, help="walk wavefronts per CU (0 = library)")
+    ap.add_argument("--tile", type=int, default=0, help="LDS list tile entries (0 = library)")
+    ap.add_argument("--frontier", type=int, default=0, help="frontier cells per wave")
+    ap.add_argument("--group-max", type=int, default=64)
+    ap.add_argument("--group-merge", type=int, default=1, choices=(0, 1))
+    ap.add_argument("--leaf-max", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -124,7 +130,10 @@ def main():
     log("generating galaxy n=%d seed=%d" % (args.n, args.seed))
     gal = I.galaxy(args.n, args.seed)
     m32 = gal.mass.astype(np.float32)
-    params = nb.Params(eps=args.eps, delta_acc=args.delta)
+    params = nb.Params(eps=args.eps, delta_acc=args.delta, waves_per_cu=args.waves,
+                       list_tile=args.tile, frontier_cap=args.frontier,
+                       group_max=args.group_max, leaf_max=args.leaf_max,
+                       group_merge=args.group_merge)
     ctx = nb.Context(params, n_max=args.n)
     st = nb.State.from_numpy(gal.pos, gal.vel, gal.mass, dt=args.dt,
                              rebuild_interval=args.rebuild)
@@ -156,7 +165,8 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (bounded sample)")
         xyz = np.stack([st.x.cpu().numpy(), st.y.cpu().numpy(), st.z.cpu().numpy()], 1)
-        cpu = cpu_baseline(xyz.astype(np.float32), m32, args.eps, args.delta)
+        cpu = cpu_baseline(xyz.astype(np.float32), m32, args.eps, args.delta, params.leaf_max,
+                           params.group_max, params.group_merge)
         log(cpu["sample"])
 
     rec = {
@@ -183,6 +193,7 @@ def main():
             "n": args.n,
             "leaf_max": params.leaf_max,
             "group_max": params.group_max,
+            "group_merge": params.group_merge,
             "order": "plain",
         },
         "interactions_per_s": inter_per_walk / (walk_ms * 1e-3),

@@ -64,11 +64,20 @@ enum {
  *                first), 2 by a learned cost model (nbody_set_cost_model).
  *                The order never changes the results (bit-identical).
  *  frontier_cap: cells per wavefront in the walk's breadth-first frontier
- *                buffer (power of two; 0 = 65536).
+ *                buffer (power of two >= 64; 0 = the cell capacity rounded
+ *                up to a power of two, at most 65536).
  *  list_tile   : interaction-list entries held in LDS per wavefront before a
  *                flush (multiple of 8, 64..2048; 0 = 256).
  *  waves_per_cu: resident wavefronts per compute unit of the persistent walk
- *                (1..32; 0 = 8).
+ *                (1..32; 0 = 32).
+ *  checks      : 0 none; 1 also record, per group, an order-independent hash
+ *                of the identities of its interaction-list entries
+ *                (NBODY_X_GHASH), for bit-exact checks of every MAC decision.
+ *  group_merge : 0 the i-groups are the group cells; 1 consecutive sibling
+ *                group cells are joined, in octant order, while the joined
+ *                count stays within group_max (fewer, fuller groups, hence
+ *                fewer interaction lists; results change only through the
+ *                grouping).
  */
 typedef struct {
   float G;
@@ -81,6 +90,8 @@ typedef struct {
   int32_t frontier_cap;
   int32_t list_tile;
   int32_t waves_per_cu;
+  int32_t checks;
+  int32_t group_merge;
 } nbody_params;
 
 typedef struct nbody_ctx nbody_ctx; /* opaque; one per HIP stream */
@@ -152,7 +163,8 @@ int32_t nbody_abi_version(void);
 const char *nbody_strerror(nbody_status s);
 
 /* Fill *p with defaults: G = 1, eps = 2^-7, delta_acc = 2^-9, leaf_max 16,
- * group_max 64, compensated 0, order 0, and the autotunable sizes 0. */
+ * group_max 64, compensated 0, order 0, checks 0, group_merge 1 and the
+ * autotunable sizes 0. */
 nbody_status nbody_params_default(nbody_params *p);
 
 /* Create a context bound to `hip_stream` (a hipStream_t, NULL = default

@@ -50,7 +50,8 @@ class _Params(C.Structure):
                 ("leaf_max", C.c_int32), ("group_max", C.c_int32),
                 ("compensated", C.c_int32), ("order", C.c_int32),
                 ("frontier_cap", C.c_int32), ("list_tile", C.c_int32),
-                ("waves_per_cu", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("checks", C.c_int32),
+                ("group_merge", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -142,6 +143,8 @@ class Params:
     frontier_cap: int = 0
     list_tile: int = 0
     waves_per_cu: int = 0
+    checks: int = 0
+    group_merge: int = 1
 
     def c(self) -> _Params:
         return _Params(*[getattr(self, f.name) for f in fields(self)])

@@ -70,16 +70,27 @@ nbody_status check_params(const nbody_params *p) {
   if (p->list_tile != 0 && (p->list_tile < 64 || p->list_tile > 2048 || p->list_tile % 8))
     return NBODY_EINVAL;
   if (p->waves_per_cu < 0 || p->waves_per_cu > 32) return NBODY_EINVAL;
+  if (p->checks != 0 && p->checks != 1) return NBODY_EINVAL;
+  if (p->group_merge != 0 && p->group_merge != 1) return NBODY_EINVAL;
   return NBODY_OK;
 }
 
 int eff_waves(const nbody_params &p) {
-  int w = p.waves_per_cu ? p.waves_per_cu : 8;
+  int w = p.waves_per_cu ? p.waves_per_cu : 32;
   w = (w + kWalkWavesPerWG - 1) / kWalkWavesPerWG * kWalkWavesPerWG;
   return w;
 }
-int eff_tile(const nbody_params &p) { return p.list_tile ? p.list_tile : 256; }
-int eff_frontier(const nbody_params &p) { return p.frontier_cap ? p.frontier_cap : 65536; }
+// 192 entries: with the owner table, 4.5 KiB of LDS per wave lets 32 waves
+// share one compute unit's 160 KiB
+int eff_tile(const nbody_params &p) { return p.list_tile ? p.list_tile : 192; }
+// A breadth-first walk holds at most every cell once, so the ring never needs
+// more than the cell capacity (rounded up to a power of two).
+int64_t eff_frontier(const nbody_params &p, int64_t cell_cap) {
+  if (p.frontier_cap) return p.frontier_cap;
+  int64_t f = 64;
+  while (f < cell_cap && f < 65536) f <<= 1;
+  return f;
+}
 
 nbody_status hip_status() {
   const hipError_t e = hipGetLastError();
@@ -105,7 +116,7 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.sort_blocks = cdiv(n, kSortTile);
   L.build_blocks = cdiv(n, kBuildThreads);
   L.walk_waves = (int64_t)num_cu * eff_waves(p);
-  L.frontier_cap = eff_frontier(p);
+  L.frontier_cap = eff_frontier(p, L.cell_cap);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -272,7 +283,8 @@ WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap) {
   c.bootstrap = bootstrap ? 1 : 0;
   c.compensated = ctx->p.compensated;
   c.list_tile = eff_tile(ctx->p);
-  c.frontier_cap = eff_frontier(ctx->p);
+  c.frontier_cap = (int)ctx->L.frontier_cap;
+  c.hash = ctx->p.checks != 0;
   c.waves_per_cu = eff_waves(ctx->p);
   c.num_cu = ctx->num_cu;
   c.use_order = 0;
@@ -334,7 +346,8 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
   launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
               &ks, &pm);
   launch_gather(x, y, z, m, pm, n, P.xyzm, ctx->st);
-  launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, P, ctx->L, ctx->st);
+  launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, P, ctx->L,
+               ctx->st);
   launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
   span_end(ctx, sp);
   ctx->keys = ks;
@@ -401,6 +414,7 @@ nbody_status nbody_params_default(nbody_params *p) {
   p->delta_acc = 0.001953125f;  // 2^-9
   p->leaf_max = 16;
   p->group_max = 64;
+  p->group_merge = 1;
   return NBODY_OK;
 }
 

@@ -4,10 +4,7 @@
 // a cell at level l holds the particles whose key >> 3(21-l) equals its
 // prefix; it is split iff it holds more than leaf_max particles and l < 21;
 // only non-empty octants become children, consecutive in octant order; cells
-// are numbered by level, then by prefix. i-groups (the particles sharing one
-// interaction list, Sec. 1) are the cells holding at most group_max
-// particles whose parent holds more; an oversized level-21 cell is cut into
-// consecutive pieces of group_max.
+// are numbered by level, then by prefix.
 //
 // Construction without a per-level host loop. For sorted keys K and
 // cpl(a, b) = number of leading octant digits K[a] and K[b] share:
@@ -17,19 +14,28 @@
 //    W+1 consecutive particles containing i shares its level-l prefix, i.e.
 //    iff l <= M_i(W) = max over s in [i-W, i] of cpl(s, s+W);
 //  * cells containing i exist at levels 0..D_i with D_i = min(M_i(leaf_max)
-//    + 1, 21); its group cell is at level min(M_i(group_max) + 1, D_i).
+//    + 1, 21).
 // So particle i starts the cells (l, i) for s_i <= l <= D_i. The level-order
 // index of (l, i) is the number of cells of lower level plus the number of
 // level-l cells starting before i: per-level block counts, a scan over
 // blocks, and ballots inside the block give it. The window maxima use a
 // sparse table (doubling) in LDS.
+//
+// i-groups (the particles sharing one interaction list, Sec. 1) are the cells
+// holding at most group_max particles whose parent holds more (the root if
+// it holds at most group_max); an oversized level-21 cell is cut into pieces
+// of group_max. With group_merge, consecutive sibling group cells are joined
+// greedily in octant order while the joined count stays within group_max.
+// Each cell holding more than group_max particles marks the group starts
+// among its children; a scan over the marked particles lists the groups in
+// particle order.
 #include "nbody_internal.h"
 
 namespace nb {
 
 constexpr int kB = kBuildThreads;
 constexpr int kH = kBuildHalo;
-constexpr int kRows = kLevels + 1;  // 22 levels + groups
+constexpr uint32_t kGroupMark = 1u << 15;  // pinfo: particle starts a group
 
 __device__ __forceinline__ int cpl_keys(uint64_t a, uint64_t b) {
   const uint64_t x = a ^ b;
@@ -66,32 +72,6 @@ __device__ uint32_t run_end(const uint64_t *__restrict__ K, uint32_t n, uint32_t
   return hi;
 }
 
-// First index of the run of keys equal to K[i] (galloping backwards).
-__device__ uint32_t run_begin_equal(const uint64_t *__restrict__ K, uint32_t i) {
-  const uint64_t p = K[i];
-  uint32_t hi = i;  // K[hi] == p
-  int64_t lo = -1;  // K[lo] != p or lo == -1
-  uint32_t step = 1;
-  while (true) {
-    const int64_t j = (int64_t)hi - step;
-    if (j < 0) break;
-    if (K[j] != p) {
-      lo = j;
-      break;
-    }
-    hi = (uint32_t)j;
-    step <<= 1;
-  }
-  while ((int64_t)hi - lo > 1) {
-    const int64_t mid = lo + ((int64_t)hi - lo) / 2;
-    if (K[mid] == p)
-      hi = (uint32_t)mid;
-    else
-      lo = mid;
-  }
-  return hi;
-}
-
 // In-place doubling: t[s] <- max(t[s .. s + 2^k - 1]) for the valid prefix.
 __device__ void lds_window_max(int *t, int len, int k) {
   for (int j = 0; j < k; ++j) {
@@ -109,17 +89,16 @@ __device__ void lds_window_max(int *t, int len, int k) {
 
 __device__ __forceinline__ int ilog2_floor(int v) { return 31 - __clz(v); }
 
-// Pass A: per sorted particle s_i, D_i, group level and group-start flag;
-// per block and row (levels 0..21, groups) the count of starts.
+// Pass A: per sorted particle s_i and D_i; per block and level the number of
+// cells starting in the block.
 __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
-                                                uint32_t n, int leaf_max, int group_max,
+                                                uint32_t n, int leaf_max,
                                                 uint32_t *__restrict__ pinfo,
                                                 uint32_t *__restrict__ blkcnt,
                                                 uint32_t nblk) {
   __shared__ uint64_t sk[kB + 2 * kH];
   __shared__ int tL[kB + kH];
-  __shared__ int tG[kB + kH];
-  __shared__ uint32_t wc[kRows][kB / 64];
+  __shared__ uint32_t wc[kLevels][kB / 64];
   const int64_t b0 = (int64_t)blockIdx.x * kB;
   for (int t = threadIdx.x; t < kB + 2 * kH; t += kB) {
     const int64_t pos = b0 - kH + t;
@@ -129,51 +108,40 @@ __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
   for (int t = threadIdx.x; t < kB + kH; t += kB) {
     const int64_t s = b0 - kH + t;
     tL[t] = (s >= 0 && s + leaf_max < n) ? cpl_keys(sk[t], sk[t + leaf_max]) : -1;
-    tG[t] = (s >= 0 && s + group_max < n) ? cpl_keys(sk[t], sk[t + group_max]) : -1;
   }
   __syncthreads();
-  const int kLw = ilog2_floor(leaf_max + 1), kGw = ilog2_floor(group_max + 1);
+  const int kLw = ilog2_floor(leaf_max + 1);
   lds_window_max(tL, kB + kH, kLw);
-  lds_window_max(tG, kB + kH, kGw);
   const int64_t i = b0 + threadIdx.x;
   const bool valid = i < n;
   const int li = threadIdx.x + kH;
-  int s = 0, D = 0, g = 0, gflag = 0;
+  int s = 0, D = 0;
   if (valid) {
     s = (i == 0) ? 0 : cpl_keys(sk[li - 1], sk[li]) + 1;
     const int M = max(tL[li - leaf_max], tL[li - (1 << kLw) + 1]);
-    const int MG = max(tG[li - group_max], tG[li - (1 << kGw) + 1]);
     D = min(M + 1, kMaxLevel);
-    g = min(MG + 1, D);
-    if (MG >= kMaxLevel) {
-      const uint32_t a = run_begin_equal(K, (uint32_t)i);
-      gflag = (((uint32_t)i - a) % (uint32_t)group_max) == 0;
-    } else {
-      gflag = s <= g;
-    }
-    pinfo[i] = (uint32_t)s | ((uint32_t)D << 5) | ((uint32_t)g << 10) |
-               ((uint32_t)gflag << 15);
+    pinfo[i] = (uint32_t)s | ((uint32_t)D << 5);  // group mark (bit 15) clear
   }
   const int w = threadIdx.x >> 6;
-  for (int l = 0; l < kRows; ++l) {
-    const bool bit = valid && (l < kLevels ? (s <= l && l <= D) : gflag);
-    const uint64_t b = __ballot(bit);
+  for (int l = 0; l < kLevels; ++l) {
+    const uint64_t b = __ballot(valid && s <= l && l <= D);
     if (lane_id() == 0) wc[l][w] = (uint32_t)__popcll(b);
   }
   __syncthreads();
-  if (threadIdx.x < kRows) {
+  if (threadIdx.x < kLevels) {
     uint32_t t = 0;
     for (int q = 0; q < kB / 64; ++q) t += wc[threadIdx.x][q];
     blkcnt[threadIdx.x * nblk + blockIdx.x] = t;
   }
 }
 
-// Pass B: exclusive scan of every row of blkcnt over the blocks; row totals
-// go to blkcnt[kRows * nblk + row].
-__global__ __launch_bounds__(256) void k_build_b(uint32_t *__restrict__ blkcnt,
-                                                 uint32_t nblk) {
+// Exclusive scan of each row (one workgroup per row) of rows[row][0..nblk);
+// the row total goes to totals[row].
+__global__ __launch_bounds__(256) void k_scan_rows(uint32_t *__restrict__ rows,
+                                                   uint32_t nblk,
+                                                   uint32_t *__restrict__ totals) {
   __shared__ uint32_t wsum[4];
-  uint32_t *row = blkcnt + (int64_t)blockIdx.x * nblk;
+  uint32_t *row = rows + (int64_t)blockIdx.x * nblk;
   const uint32_t per = (nblk + 255) / 256;
   const uint32_t k0 = threadIdx.x * per;
   uint32_t s = 0;
@@ -193,19 +161,17 @@ __global__ __launch_bounds__(256) void k_build_b(uint32_t *__restrict__ blkcnt,
     row[k] = run;
     run += v;
   }
-  if (threadIdx.x == 0) blkcnt[(int64_t)kRows * nblk + blockIdx.x] = tot;
+  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-// Pass C: level offsets, cell and group counts, group sentinel.
-__global__ void k_build_c(const uint32_t *__restrict__ blkcnt, uint32_t nblk, uint32_t n,
-                          DevScalars *sc, uint32_t *__restrict__ gbegin,
+// Pass C: level offsets and the cell count.
+__global__ void k_build_c(const uint32_t *__restrict__ totals, DevScalars *sc,
                           int64_t cell_cap) {
   if (threadIdx.x != 0) return;
-  const uint32_t *tot = blkcnt + (int64_t)kRows * nblk;
   uint32_t o = 0;
   for (int l = 0; l < kLevels; ++l) {
     sc->lvl_off[l] = o;
-    o += tot[l];
+    o += totals[l];
   }
   sc->lvl_off[kLevels] = o;
   if ((int64_t)o > cell_cap) {
@@ -213,34 +179,30 @@ __global__ void k_build_c(const uint32_t *__restrict__ blkcnt, uint32_t nblk, ui
     o = 0;
   }
   sc->ncell = o;
-  sc->ngroup = tot[kLevels];
-  gbegin[tot[kLevels]] = n;
 }
 
-// Pass D: write every cell (l, i) and every group start.
+// Pass D: write every cell (l, i).
 __global__ __launch_bounds__(kB) void k_build_d(
     const uint64_t *__restrict__ K, uint32_t n, const uint32_t *__restrict__ pinfo,
     const uint32_t *__restrict__ blkcnt, uint32_t nblk, const DevScalars *__restrict__ sc,
     int64_t cell_cap, int32_t *__restrict__ clevel, uint32_t *__restrict__ cpbegin,
     uint32_t *__restrict__ cpcount, int32_t *__restrict__ cfchild,
     int32_t *__restrict__ cnchild, float4 *__restrict__ nodeB,
-    uint32_t *__restrict__ leafof, uint32_t *__restrict__ gbegin) {
-  __shared__ uint32_t wpre[kRows][kB / 64];
+    uint32_t *__restrict__ leafof) {
+  __shared__ uint32_t wpre[kLevels][kB / 64];
   __shared__ uint32_t lvl_off[kLevels + 1];
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   const bool valid = i < n;
   const uint32_t pi = valid ? pinfo[i] : 0u;
   const int s = pi & 31, D = (pi >> 5) & 31;
-  const bool gflag = valid && ((pi >> 15) & 1u);
   const int w = threadIdx.x >> 6;
   if (threadIdx.x <= kLevels) lvl_off[threadIdx.x] = sc->lvl_off[threadIdx.x];
-  for (int l = 0; l < kRows; ++l) {
-    const bool bit = valid && (l < kLevels ? (s <= l && l <= D) : gflag);
-    const uint64_t b = __ballot(bit);
+  for (int l = 0; l < kLevels; ++l) {
+    const uint64_t b = __ballot(valid && s <= l && l <= D);
     if (lane_id() == 0) wpre[l][w] = (uint32_t)__popcll(b);
   }
   __syncthreads();
-  if (threadIdx.x < kRows) {
+  if (threadIdx.x < kLevels) {
     uint32_t o = 0;
     for (int q = 0; q < kB / 64; ++q) {
       const uint32_t t = wpre[threadIdx.x][q];
@@ -251,16 +213,12 @@ __global__ __launch_bounds__(kB) void k_build_d(
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   uint32_t idx_prev = 0;
-  for (int l = 0; l < kRows; ++l) {
-    const bool bit = valid && (l < kLevels ? (s <= l && l <= D) : gflag);
+  for (int l = 0; l < kLevels; ++l) {
+    const bool bit = valid && s <= l && l <= D;
     const uint64_t b = __ballot(bit);
     if (!bit) continue;
     const uint32_t rank = blkcnt[(int64_t)l * nblk + blockIdx.x] + wpre[l][w] +
                           (uint32_t)__popcll(b & lt);
-    if (l == kLevels) {  // group start
-      gbegin[rank] = (uint32_t)i;
-      continue;
-    }
     const uint32_t idx = lvl_off[l] + rank;
     if ((int64_t)idx >= cell_cap) continue;
     if (l > s) cfchild[idx_prev] = (int32_t)idx;  // (l-1, i) is internal
@@ -285,21 +243,19 @@ __global__ __launch_bounds__(kB) void k_build_d(
       }
       cnchild[idx] = nc;
       wB[3] = (uint32_t)nc;
-      // wB[2] (first child) is written with cfchild below
+      // wB[2] (first child) is written by pass E
     }
     idx_prev = idx;
   }
 }
 
-// Pass E: parents, node first-child words, group sizes.
+// Pass E: parents and the first-child word of internal walk nodes.
 __global__ __launch_bounds__(256) void k_build_e(DevScalars *__restrict__ sc,
                                                  const int32_t *__restrict__ cfchild,
                                                  const int32_t *__restrict__ cnchild,
                                                  int32_t *__restrict__ cparent,
-                                                 float4 *__restrict__ nodeB,
-                                                 const uint32_t *__restrict__ gbegin,
-                                                 uint32_t *__restrict__ gcount) {
-  const uint32_t nc = sc->ncell, ng = sc->ngroup;
+                                                 float4 *__restrict__ nodeB) {
+  const uint32_t nc = sc->ncell;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += stride) {
     if (c == 0) cparent[0] = -1;
@@ -314,25 +270,130 @@ __global__ __launch_bounds__(256) void k_build_e(DevScalars *__restrict__ sc,
       for (int q = 0; q < k; ++q) cparent[f + q] = (int32_t)c;
     }
   }
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng; g += stride)
+}
+
+__device__ __forceinline__ void mark_chunks(uint32_t *__restrict__ pinfo, uint32_t b,
+                                            uint32_t cnt, uint32_t gmax) {
+  for (uint32_t s = 0; s < cnt; s += gmax) pinfo[b + s] |= kGroupMark;
+}
+
+// Group starts: the root if it holds at most group_max particles (or is a
+// leaf); otherwise every cell holding more than group_max particles marks
+// the starts among its children (joining consecutive small siblings when
+// `merge`). Every particle is marked at most once.
+__global__ __launch_bounds__(256) void k_group_mark(DevScalars *__restrict__ sc,
+                                                    const uint32_t *__restrict__ cpbegin,
+                                                    const uint32_t *__restrict__ cpcount,
+                                                    const int32_t *__restrict__ cfchild,
+                                                    const int32_t *__restrict__ cnchild,
+                                                    uint32_t gmax, int merge,
+                                                    uint32_t *__restrict__ pinfo) {
+  const uint32_t nc = sc->ncell;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t cnt = cpcount[c];
+    const int k = cnchild[c];
+    if (c == 0 && (cnt <= gmax || k == 0)) {
+      mark_chunks(pinfo, cpbegin[0], cnt, gmax);
+      continue;
+    }
+    if (cnt <= gmax || k == 0) continue;
+    const int32_t f = cfchild[c];
+    uint32_t run = 0;  // particles in the open joined group (0: none open)
+    for (int q = 0; q < k; ++q) {
+      const uint32_t cb = cpbegin[f + q], cc = cpcount[f + q];
+      if (cc <= gmax) {
+        if (merge && run > 0 && run + cc <= gmax) {
+          run += cc;
+        } else {
+          pinfo[cb] |= kGroupMark;
+          run = cc;
+        }
+      } else {
+        run = 0;
+        if (cnchild[f + q] == 0) mark_chunks(pinfo, cb, cc, gmax);  // level-21 leaf
+      }
+    }
+  }
+}
+
+// Group marks per block of kB particles.
+__global__ __launch_bounds__(kB) void k_group_count(uint32_t n,
+                                                    const uint32_t *__restrict__ pinfo,
+                                                    uint32_t *__restrict__ gblk) {
+  __shared__ uint32_t wc[kB / 64];
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const bool mk = i < n && (pinfo[i] & kGroupMark);
+  const uint64_t b = __ballot(mk);
+  if (lane_id() == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int q = 0; q < kB / 64; ++q) t += wc[q];
+    gblk[blockIdx.x] = t;
+  }
+}
+
+// Group begins in particle order (gblk holds exclusive block offsets).
+__global__ __launch_bounds__(kB) void k_group_emit(uint32_t n,
+                                                   const uint32_t *__restrict__ pinfo,
+                                                   const uint32_t *__restrict__ gblk,
+                                                   uint32_t *__restrict__ gbegin) {
+  __shared__ uint32_t wc[kB / 64];
+  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const bool mk = i < n && (pinfo[i] & kGroupMark);
+  const uint64_t b = __ballot(mk);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) wc[w] = (uint32_t)__popcll(b);
+  __syncthreads();
+  uint32_t off = gblk[blockIdx.x];
+  for (int q = 0; q < w; ++q) off += wc[q];
+  if (mk) gbegin[off + (uint32_t)__popcll(b & lanemask_lt())] = (uint32_t)i;
+}
+
+__global__ void k_group_total(const uint32_t *__restrict__ total, uint32_t n,
+                              DevScalars *sc, uint32_t *__restrict__ gbegin) {
+  if (threadIdx.x != 0) return;
+  sc->ngroup = total[0];
+  gbegin[total[0]] = n;
+}
+
+__global__ __launch_bounds__(256) void k_group_size(const DevScalars *__restrict__ sc,
+                                                    const uint32_t *__restrict__ gbegin,
+                                                    uint32_t *__restrict__ gcount) {
+  const uint32_t ng = sc->ngroup;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x)
     gcount[g] = gbegin[g + 1] - gbegin[g];
 }
 
 void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
-                  const Ptrs &P, const Layout &L, hipStream_t st) {
+                  int group_merge, const Ptrs &P, const Layout &L, hipStream_t st) {
   const uint32_t nblk = (uint32_t)cdiv(n, kB);
-  hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n,
-                     leaf_max, group_max, P.pinfo, P.blkcnt, nblk);
-  hipLaunchKernelGGL(k_build_b, dim3(kRows), dim3(256), 0, st, P.blkcnt, nblk);
-  hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, P.blkcnt, nblk, (uint32_t)n,
-                     P.sc, P.gbegin, L.cell_cap);
+  // block rows [kLevels][nblk], then kLevels totals
+  uint32_t *totals = P.blkcnt + (int64_t)kLevels * nblk;
+  hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, leaf_max,
+                     P.pinfo, P.blkcnt, nblk);
+  hipLaunchKernelGGL(k_scan_rows, dim3(kLevels), dim3(256), 0, st, P.blkcnt, nblk, totals);
+  hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
   hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, P.pinfo,
                      P.blkcnt, nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount,
-                     P.cfchild, P.cnchild, P.nodeB, P.leafof, P.gbegin);
+                     P.cfchild, P.cnchild, P.nodeB, P.leafof);
   int64_t ge = cdiv(n, 256);
   if (ge > 4096) ge = 4096;
   hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.cfchild, P.cnchild,
-                     P.cparent, P.nodeB, P.gbegin, P.gcount);
+                     P.cparent, P.nodeB);
+  // groups (the block rows are free again: reuse them for the group scan)
+  uint32_t *gblk = P.blkcnt, *gtot = P.blkcnt + nblk;
+  hipLaunchKernelGGL(k_group_mark, dim3(ge), dim3(256), 0, st, P.sc, P.cpbegin, P.cpcount,
+                     P.cfchild, P.cnchild, (uint32_t)group_max, group_merge, P.pinfo);
+  hipLaunchKernelGGL(k_group_count, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk);
+  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, st, gblk, nblk, gtot);
+  hipLaunchKernelGGL(k_group_emit, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk,
+                     P.gbegin);
+  hipLaunchKernelGGL(k_group_total, dim3(1), dim3(64), 0, st, gtot, (uint32_t)n, P.sc,
+                     P.gbegin);
+  hipLaunchKernelGGL(k_group_size, dim3(ge), dim3(256), 0, st, P.sc, P.gbegin, P.gcount);
 }
 
 }  // namespace nb

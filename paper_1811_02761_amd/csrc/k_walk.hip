@@ -152,7 +152,12 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
   HIP_DYNAMIC_SHARED(float4, lds_list)
   const uint32_t wv = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
+  // LDS: per wave a list tile, then per wave the chunk's owner table
   float4 *list = lds_list + wv * a.tile;
+  float4 *s_ent = lds_list + kWalkWavesPerWG * a.tile + wv * 64;
+  uint32_t *s_incl =
+      reinterpret_cast<uint32_t *>(lds_list + kWalkWavesPerWG * (a.tile + 64)) + wv * 128;
+  uint32_t *s_src = s_incl + 64;
   uint32_t *ring =
       a.frontier + (size_t)(blockIdx.x * kWalkWavesPerWG + wv) * (size_t)(a.fmask + 1);
   const uint32_t F = a.fmask + 1;
@@ -232,30 +237,40 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
       const uint32_t ne = !has ? 0u : accept ? 1u : leaf ? (w1 & ~kLeafBit) : 0u;
       const uint32_t nch = (has && !accept && !leaf) ? w1 : 0u;
       // children -> frontier ring
-      const uint32_t chi = wave_incl_scan(nch);
-      const uint32_t chtot = __builtin_amdgcn_readfirstlane(wave_bcast_last(chi));
+      const uint32_t chi = wave_incl_scan_dpp(nch);
+      const uint32_t chtot = wave_last(chi);
       if (tail - head + chtot > F) {
         overflow = true;
         break;
       }
       for (uint32_t k = 0; k < nch; ++k) ring[(tail + chi - nch + k) & a.fmask] = w0 + k;
       tail += chtot;
-      // entries -> LDS list (flushing full tiles)
-      const uint32_t ei = wave_incl_scan(ne);
-      const uint32_t etot = __builtin_amdgcn_readfirstlane(wave_bcast_last(ei));
-      const uint32_t eoff = ei - ne;
+      // entries -> LDS list (flushing full tiles). Lane k owns entries
+      // [incl_k - ne_k, incl_k); the copy is cooperative: lane r of the wave
+      // fetches entry done + r, finding its owner by binary search.
+      const uint32_t ei = wave_incl_scan_dpp(ne);
+      const uint32_t etot = wave_last(ei);
       if (kHash) {
         if (accept) hsum += mix64((uint64_t)c);
         else if (ne)
           for (uint32_t k = 0; k < ne; ++k) hsum += mix64((1ull << 40) + w0 + k);
       }
+      s_incl[lane] = ei;
+      s_src[lane] = accept ? 0xffffffffu : w0;
+      if (accept) s_ent[lane] = make_float4(A.x, A.y, A.z, B.x);
+      __builtin_amdgcn_wave_barrier();
       uint32_t done = 0;
       while (done < etot) {
         const uint32_t take = min(a.tile - cnt, etot - done);
-        const uint32_t jlo = max(eoff, done), jhi = min(eoff + ne, done + take);
-        for (uint32_t j = jlo; j < jhi; ++j) {
-          const float4 e = accept ? make_float4(A.x, A.y, A.z, B.x) : a.xyzm[w0 + (j - eoff)];
-          list[cnt + (j - done)] = e;
+        for (uint32_t r = lane; r < take; r += 64u) {
+          const uint32_t j = done + r;
+          uint32_t k = 0;
+#pragma unroll
+          for (uint32_t s = 32; s >= 1; s >>= 1)
+            if (s_incl[k + s - 1] <= j) k += s;
+          const uint32_t src = s_src[k];
+          const uint32_t first = k ? s_incl[k - 1] : 0u;
+          list[cnt + r] = (src == 0xffffffffu) ? s_ent[k] : a.xyzm[src + (j - first)];
         }
         cnt += take;
         done += take;
@@ -266,6 +281,7 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
           cnt = 0;
         }
       }
+      __builtin_amdgcn_wave_barrier();  // owner table is rewritten next chunk
       entries += etot;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -354,13 +370,20 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   a.fmask = (uint32_t)c.frontier_cap - 1u;
   a.bootstrap = c.bootstrap;
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
-  const size_t lds = (size_t)kWalkWavesPerWG * c.list_tile * sizeof(float4);
-  if (c.compensated)
-    hipLaunchKernelGGL((k_walk<true, true>), dim3(blocks), dim3(64 * kWalkWavesPerWG), lds,
-                       st, a);
-  else
-    hipLaunchKernelGGL((k_walk<false, true>), dim3(blocks), dim3(64 * kWalkWavesPerWG), lds,
-                       st, a);
+  // per wave: list tile (16 B/entry) + owner table (64 x (16 + 4 + 4) B)
+  const size_t lds = (size_t)kWalkWavesPerWG * (c.list_tile * sizeof(float4) + 64 * 24);
+  const dim3 grid(blocks), block(64 * kWalkWavesPerWG);
+  if (c.compensated) {
+    if (c.hash)
+      hipLaunchKernelGGL((k_walk<true, true>), grid, block, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_walk<true, false>), grid, block, lds, st, a);
+  } else {
+    if (c.hash)
+      hipLaunchKernelGGL((k_walk<false, true>), grid, block, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_walk<false, false>), grid, block, lds, st, a);
+  }
 }
 
 }  // namespace nb

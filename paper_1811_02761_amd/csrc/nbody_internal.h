@@ -64,9 +64,9 @@ struct Ptrs {
   uint32_t *hist;       // sort histograms [radix][blocks] + totals[radix]
   float4 *xyzm;         // sorted x, y, z, m
   float *x32;           // FP32 image of state positions [3][n] (caller order)
-  uint32_t *pinfo;      // per sorted particle: s | D << 5 | gflag << 10
+  uint32_t *pinfo;      // per sorted particle: s | D << 5 | group start << 15
   uint32_t *leafof;     // per sorted particle: its leaf cell
-  uint32_t *blkcnt;     // build block counts [kLevels + 1][blocks]
+  uint32_t *blkcnt;     // build block counts [kLevels][blocks] + totals
   int32_t *clevel;
   uint32_t *cpbegin, *cpcount;
   int32_t *cfchild, *cnchild, *cparent;
@@ -97,7 +97,7 @@ void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
 void launch_gather(const float *x, const float *y, const float *z, const float *m,
                    const uint32_t *perm, int64_t n, float4 *xyzm, hipStream_t st);
 void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
-                  const Ptrs &P, const Layout &L, hipStream_t st);
+                  int group_merge, const Ptrs &P, const Layout &L, hipStream_t st);
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L,
                     hipStream_t st);
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
@@ -112,6 +112,7 @@ struct WalkCfg {
   int waves_per_cu;
   int num_cu;
   int use_order;
+  bool hash;  // record the per-group entry hash
 };
 // enqueue the walk kernel (the queue head must already be zero)
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
@@ -148,6 +149,26 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 __device__ __forceinline__ uint32_t wave_bcast_last(uint32_t v) {
   return __shfl(v, 63, 64);
+}
+
+// Wave64 inclusive prefix sum with DPP (all 64 lanes active): prefix within
+// each row of 16 lanes by row_shr 1, 2, 4, 8 (zero fill), then row 1 and 3
+// add the last lane of the row before (row_bcast:15), rows 2 and 3 add lane
+// 31 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31
+  return (uint32_t)x;
+}
+
+// value of lane 63, as a wave-uniform scalar
+__device__ __forceinline__ uint32_t wave_last(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ float wave_min(float v) {

@@ -56,7 +56,7 @@ def test_create_rejects_bad_params_without_gpu(nb):
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(delta_acc=-1.0), dict(group_max=65),
                 dict(leaf_max=0), dict(leaf_max=65, group_max=64), dict(compensated=2),
                 dict(order=3), dict(frontier_cap=100), dict(list_tile=60),
-                dict(waves_per_cu=33)):
+                dict(waves_per_cu=33), dict(checks=2), dict(group_merge=2)):
         p = nb.Params(**bad).c()
         h = ctypes.c_void_p()
         assert nb.lib().nbody_create(ctypes.byref(p), None, ctypes.byref(h)) == nb.NBODY_EINVAL

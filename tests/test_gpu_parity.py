@@ -51,6 +51,7 @@ def _np(t):
 
 
 def _run(nb, torch, x, y, z, m, params, a_old=None, n_max=None):
+    params.checks = 1  # record per-group entry hashes
     ctx = nb.Context(params, n_max=n_max or len(x))
     X, Y, Z, M = (_dev(torch, a.astype(np.float32)) for a in (x, y, z, m))
     ctx.build_tree(X, Y, Z, M)
@@ -58,6 +59,13 @@ def _run(nb, torch, x, y, z, m, params, a_old=None, n_max=None):
     acc = ctx.calc_acc(ao)
     ctx.sync()
     return ctx, np.stack([_np(a) for a in acc], 1)
+
+
+def _ref(orc, x, y, z, m, params, a_old=None):
+    """The oracle's tree forces under the same parameters as the HIP call."""
+    return orc.tree_forces(x, y, z, m, a_old=a_old, eps=params.eps,
+                           delta_acc=params.delta_acc, leaf_max=params.leaf_max,
+                           group_max=params.group_max, group_merge=params.group_merge)
 
 
 def _compare_tree(nb, ctx, ref, torch):
@@ -130,25 +138,25 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("merge", [0, 1])
 @pytest.mark.parametrize("model,n,seed,leaf,gmax", CASES)
-def test_tree_and_walk_parity(nb, torch, orc, model, n, seed, leaf, gmax):
-    _say("case", model, n, seed, leaf, gmax)
+def test_tree_and_walk_parity(nb, torch, orc, model, n, seed, leaf, gmax, merge):
+    _say("case", model, n, seed, leaf, gmax, merge)
     p = I.plummer(n, seed) if model == "plummer" else I.galaxy(n, seed)
     x, y, z, _, _, _, m = p.f32()
     eps = 2.0 ** -7
-    params = nb.Params(eps=eps, delta_acc=2.0 ** -9, leaf_max=leaf, group_max=gmax)
+    params = nb.Params(eps=eps, delta_acc=2.0 ** -9, leaf_max=leaf, group_max=gmax,
+                       group_merge=merge)
     # bootstrap pass (no a_old)
     ctx, acc0 = _run(nb, torch, x, y, z, m, params)
-    ref0 = orc.tree_forces(x, y, z, m, a_old=None, eps=eps, delta_acc=2.0 ** -9,
-                           leaf_max=leaf, group_max=gmax)
+    ref0 = _ref(orc, x, y, z, m, params)
     _compare_tree(nb, ctx, ref0, torch)
     e, et = _compare_walk(nb, ctx, ref0, acc0, np.stack([x, y, z], 1), m, eps)
     _assert_rule(e, et)
     # MAC pass with a_old = the oracle's bootstrap acceleration (FP32)
     a_old = ref0.acc.astype(np.float32)
     ctx1, acc1 = _run(nb, torch, x, y, z, m, params, a_old=a_old)
-    ref1 = orc.tree_forces(x, y, z, m, a_old=a_old, eps=eps, delta_acc=2.0 ** -9,
-                           leaf_max=leaf, group_max=gmax)
+    ref1 = _ref(orc, x, y, z, m, params, a_old)
     e, et = _compare_walk(nb, ctx1, ref1, acc1, np.stack([x, y, z], 1), m, eps)
     _say("  max e~ %.3g  p99.9 e %.3g  entries %d" % (et.max(), np.percentile(e, 99.9),
                                                      ref1.gentries.sum()))
@@ -163,7 +171,7 @@ def test_tiny_and_ragged(nb, torch, orc, n):
     params = nb.Params(leaf_max=4, group_max=16)
     a_old = np.ones((n, 3), np.float32)
     ctx, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
-    ref = orc.tree_forces(x, y, z, m, a_old=a_old, leaf_max=4, group_max=16)
+    ref = _ref(orc, x, y, z, m, params, a_old)
     _compare_tree(nb, ctx, ref, torch)
     if n > 1:
         e, et = _compare_walk(nb, ctx, ref, acc, np.stack([x, y, z], 1), m, 2.0 ** -7)
@@ -181,12 +189,13 @@ def test_coincident_particles(nb, torch, orc):
     z = np.concatenate([np.full(300, 0.125), rng.uniform(-1, 1, 700)]).astype(np.float32)
     m = np.full(1000, 1e-3, np.float32)
     a_old = np.ones((1000, 3), np.float32)
-    params = nb.Params(leaf_max=8, group_max=32)
-    ctx, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
-    ref = orc.tree_forces(x, y, z, m, a_old=a_old, leaf_max=8, group_max=32)
-    _compare_tree(nb, ctx, ref, torch)
-    e, et = _compare_walk(nb, ctx, ref, acc, np.stack([x, y, z], 1), m, 2.0 ** -7)
-    _assert_rule(e, et)
+    for merge in (0, 1):
+        params = nb.Params(leaf_max=8, group_max=32, group_merge=merge)
+        ctx, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
+        ref = _ref(orc, x, y, z, m, params, a_old)
+        _compare_tree(nb, ctx, ref, torch)
+        e, et = _compare_walk(nb, ctx, ref, acc, np.stack([x, y, z], 1), m, 2.0 ** -7)
+        _assert_rule(e, et)
 
 
 def test_zero_delta_equals_direct(nb, torch, orc):
@@ -210,7 +219,7 @@ def test_zero_delta_equals_direct(nb, torch, orc):
 def test_results_independent_of_tile_waves_and_frontier(nb, torch, orc):
     g = I.galaxy(30000, 12)
     x, y, z, _, _, _, m = g.f32()
-    a_old = orc.tree_forces(x, y, z, m, a_old=None).acc.astype(np.float32)
+    a_old = _ref(orc, x, y, z, m, nb.Params()).acc.astype(np.float32)
     outs = []
     for tile, waves, fc in ((256, 8, 0), (64, 4, 4096), (2048, 16, 1 << 18), (136, 12, 0)):
         params = nb.Params(list_tile=tile, waves_per_cu=waves, frontier_cap=fc)
@@ -224,9 +233,8 @@ def test_compensated_sum_not_worse(nb, torch, orc):
     g = I.galaxy(20000, 13)
     x, y, z, _, _, _, m = g.f32()
     pos = np.stack([x, y, z], 1)
-    ref = orc.tree_forces(x, y, z, m, a_old=None)
-    a_old = ref.acc.astype(np.float32)
-    ref = orc.tree_forces(x, y, z, m, a_old=a_old, delta_acc=2.0 ** -16)
+    a_old = _ref(orc, x, y, z, m, nb.Params()).acc.astype(np.float32)
+    ref = _ref(orc, x, y, z, m, nb.Params(delta_acc=2.0 ** -16), a_old)
     errs = []
     for comp in (0, 1):
         _, acc = _run(nb, torch, x, y, z, m, nb.Params(delta_acc=2.0 ** -16, compensated=comp),
@@ -288,8 +296,8 @@ def test_kdk_step_matches_oracle(nb, torch, orc):
 
     def force_tree(state={"a": None}):
         def f(p32):
-            r = orc.tree_forces(p32[:, 0], p32[:, 1], p32[:, 2], m,
-                                a_old=state["a"], eps=eps)
+            r = _ref(orc, p32[:, 0], p32[:, 1], p32[:, 2], m, nb.Params(eps=eps),
+                     state["a"])
             state["a"] = r.acc.astype(np.float32)
             return state["a"]
         return f
