@@ -34,10 +34,12 @@ def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, seconds=12.0):
+def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_frac=1.0,
+                 seconds=12.0):
     """The oracle (FP64 C, OpenMP) on this host: the full tree pipeline on all
     particles, then the walk on a random sample of groups sized to about
-    `seconds`; the step time is build + walk scaled to all groups."""
+    `seconds`; the step time is build + walk scaled to all groups times
+    `walk_frac`, the mean share of the groups a step walks."""
     import oracle
 
     x, y, z = (np.ascontiguousarray(pos32[:, k]) for k in range(3))
@@ -86,15 +88,67 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, seconds=
     tw, inter, _ = mac_walk(sel)
     t_walk_full = tw * grp.n / ns
     return {
-        "value": t_build + t_walk_full,
+        "value": t_build + t_walk_full * walk_frac,
         "unit": "s/step",
         "cores": nth,
         "kind": "oracle",
         "sample": ("FP64 oracle: full tree build of all %d particles (%.1f s, 1 thread) + "
-                   "walk of %d of %d groups (%.1f s, %d threads), walk scaled to all groups"
-                   % (len(x), t_build, ns, grp.n, tw, nth)),
+                   "walk of %d of %d groups (%.1f s, %d threads), walk scaled to all groups "
+                   "x %.3f (mean share of groups walked per step)"
+                   % (len(x), t_build, ns, grp.n, tw, nth, walk_frac)),
         "interactions_per_s": inter / tw if tw > 0 else None,
     }
+
+
+def plain_vs_learned(ctx, nb, torch, a_cur, ref_out, train_steps, hidden=32, reps=3):
+    """All-active walks of the same tree in plain (Morton) and learned queue
+    order. The model is trained on the device, by the library's kernels, on
+    statistics the walk itself records (features before, interaction counts
+    after an all-active walk at this state)."""
+    import nbody_inputs as I
+
+    ctx.set_order(1)
+    ctx.calc_acc(a_cur)  # members learn their list length
+    ctx.calc_acc(a_cur)  # features use it; targets measured
+    ctx.sync()
+    feat = ctx.export(nb.X.FEAT).reshape(-1, 4).contiguous()
+    target = ctx.export(nb.X.TARGET).contiguous()
+    w = torch.as_tensor(I.mlp_init(nb.mlp_nparams(hidden), nb.mlp_fan_in(hidden), 1),
+                        device="cuda")
+    t0 = time.perf_counter()
+    losses = ctx.train_cost_model(hidden, w, feat, target, train_steps, 1e-2)
+    t_train = time.perf_counter() - t0
+    ctx.set_cost_model(hidden, w)
+    ms = {0: [], 2: []}
+    same = True
+    for _ in range(reps):
+        for order in (0, 2):
+            ctx.set_order(order)
+            ctx.timing(True)
+            out = ctx.calc_acc(a_cur)
+            ctx.sync()
+            ms[order].append(ctx.stats()["walk_ms_sum"])
+            same &= all(bool(torch.equal(u, v)) for u, v in zip(out, ref_out))
+    pred = ctx.export(nb.X.PRED).cpu().numpy()
+    t = target.cpu().numpy()
+    f = feat.cpu().numpy()
+    ctx.set_order(0)
+    res = {
+        "plain_walk_ms": min(ms[0]),
+        "learned_walk_ms": min(ms[2]),
+        "plain_over_learned": min(ms[0]) / min(ms[2]),
+        "forces_bit_identical": bool(same),
+        "train_rows": int(t.shape[0]),
+        "train_steps": int(train_steps),
+        "train_s": t_train,
+        "train_loss_first_last": [float(losses[0]), float(losses[-1])],
+        "mean_abs_log2_miss_model": float(np.abs(pred - t).mean()),
+        "mean_abs_log2_miss_size_based": float(np.abs(f[:, 0] + f[:, 3] - t).mean()),
+    }
+    log("plain vs learned: %.3f ms vs %.3f ms (x%.3f), bit-identical %s, misses %.3f vs %.3f"
+        % (res["plain_walk_ms"], res["learned_walk_ms"], res["plain_over_learned"], same,
+           res["mean_abs_log2_miss_model"], res["mean_abs_log2_miss_size_based"]))
+    return res
 
 
 def main():
@@ -105,7 +159,11 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 23)
     ap.add_argument("--delta", type=float, default=2.0 ** -9)
     ap.add_argument("--eps", type=float, default=2.0 ** -6)
-    ap.add_argument("--dt", type=float, default=2.0 ** -7)
+    ap.add_argument("--dt", type=float, default=2.0 ** -3,
+                    help="longest block step dt_max (the step itself with --global-steps)")
+    ap.add_argument("--eta", type=float, default=0.025, help="block-step accuracy parameter")
+    ap.add_argument("--global-steps", action="store_true",
+                    help="every particle takes dt (no individual block steps)")
     ap.add_argument("--rebuild", type=int, default=0, help="0 = automatic interval")
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--waves", type=int, default=0, help="walk wavefronts per CU (0 = library)")
@@ -115,6 +173,8 @@ def main():
     ap.add_argument("--group-merge", type=int, default=1, choices=(0, 1))
     ap.add_argument("--leaf-max", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learn-steps", type=int, default=300,
+                    help="Adam steps of the cost model for the plain-vs-learned walks (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,8 +195,9 @@ def main():
                        group_max=args.group_max, leaf_max=args.leaf_max,
                        group_merge=args.group_merge)
     ctx = nb.Context(params, n_max=args.n)
+    block = not args.global_steps
     st = nb.State.from_numpy(gal.pos, gal.vel, gal.mass, dt=args.dt,
-                             rebuild_interval=args.rebuild)
+                             rebuild_interval=args.rebuild, block_steps=block, eta=args.eta)
     log("warmup %d steps" % args.warmup)
     ctx.step(st, max(args.warmup, 1))
     ctx.sync()
@@ -157,16 +218,32 @@ def main():
     entries_per_walk = s1["entries_sum"] / max(walks, 1)
     achieved = FLOP_PER_INTERACTION * inter_per_walk / (walk_ms * 1e-3) / 1e12
     rebuilds = s1["rebuilds"] - s0["rebuilds"]
-    log("s/step %.4g, walk %.3f ms x %d, %.3g interactions/walk, rebuilds %d, build %.3f ms"
-        % (sec_per_step, walk_ms, walks, inter_per_walk, rebuilds,
-           s1["build_ms_sum"] / max(s1["build_calls"], 1)))
+    walk_frac = s1["queued_sum"] / max(s1["ngroup_sum"], 1)
+    walk_share = s1["walk_ms_sum"] * 1e-3 / (t1 - t0)
+    log("s/step %.4g, walk %.3f ms x %d, %.3g interactions/walk, groups walked %.3f, "
+        "rebuilds %d, build %.3f ms, walk share of time %.2f"
+        % (sec_per_step, walk_ms, walks, inter_per_walk, walk_frac, rebuilds,
+           s1["build_ms_sum"] / max(s1["build_calls"], 1), walk_share))
+    levels = None
+    if block:
+        levels = np.bincount(st.level.cpu().numpy(), minlength=11).tolist()
+        log("levels %s, time reached %.6g (tick %d)" % (levels, st.t, st.tick))
+    # one force evaluation with every particle active (context, not the metric)
+    a_cur = (st.ax, st.ay, st.az)
+    ctx.timing(True)
+    full = ctx.calc_acc(a_cur)
+    ctx.sync()
+    s2 = ctx.stats()
+    full_ms = s2["walk_ms_sum"] / max(s2["walk_calls"], 1)
+    log("all-active walk %.3f ms, %.3g interactions" % (full_ms, s2["interactions_sum"]))
+    pvl = plain_vs_learned(ctx, nb, torch, a_cur, full, args.learn_steps) if args.learn_steps else None
 
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (bounded sample)")
         xyz = np.stack([st.x.cpu().numpy(), st.y.cpu().numpy(), st.z.cpu().numpy()], 1)
         cpu = cpu_baseline(xyz.astype(np.float32), m32, args.eps, args.delta, params.leaf_max,
-                           params.group_max, params.group_merge)
+                           params.group_max, params.group_merge, walk_frac)
         log(cpu["sample"])
 
     rec = {
@@ -185,10 +262,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": ("galaxy N=%d (NFW halo 80%%, Hernquist bulge 5%%, exponential disc "
-                         "15%%, z_d=0.1 R_d), eps=2^%d, delta_acc=2^%d, KDK dt=2^%d, all "
-                         "particles active every step, rebuild interval %s"
+                         "15%%, z_d=0.1 R_d), eps=2^%d, delta_acc=2^%d, %s, rebuild interval "
+                         "%s; one step = one smallest block step"
                          % (args.n, round(np.log2(args.eps)), round(np.log2(args.delta)),
-                            round(np.log2(args.dt)),
+                            ("block time steps dt_max=2^%d eta=%g" % (round(np.log2(args.dt)),
+                                                                     args.eta))
+                            if block else "global KDK dt=2^%d" % round(np.log2(args.dt)),
                             "automatic" if args.rebuild == 0 else str(args.rebuild))),
             "n": args.n,
             "leaf_max": params.leaf_max,
@@ -200,6 +279,13 @@ def main():
         "interactions_per_step": inter_per_walk,
         "list_entries_per_step": entries_per_walk,
         "walk_ms": walk_ms,
+        "walk_share_of_step": walk_share,
+        "groups_walked_frac": walk_frac,
+        "levels_end": levels,
+        "all_active_walk_ms": full_ms,
+        "all_active_interactions": s2["interactions_sum"],
+        "all_active_interactions_per_s": s2["interactions_sum"] / (full_ms * 1e-3),
+        "plain_vs_learned": pvl,
         "build_ms": s1["build_ms_sum"] / max(s1["build_calls"], 1),
         "rebuilds_in_timed_steps": rebuilds,
         "pct_fp32_vector_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,

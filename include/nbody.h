@@ -44,7 +44,7 @@ enum {
   NBODY_EINVAL = -1,     /* bad argument (null pointer, eps <= 0, ...) */
   NBODY_ENOMEM = -2,     /* workspace missing or too small for n */
   NBODY_EHIP = -3,       /* a HIP runtime call failed */
-  NBODY_EOVERFLOW = -4,  /* walk frontier buffer overflowed (sticky) */
+  NBODY_EOVERFLOW = -4,  /* walk frontier overflowed even on the retry (sticky) */
   NBODY_ENOTREE = -5,    /* calc_acc/refit/export before build_tree */
   NBODY_ENONFINITE = -6, /* NaN or Inf in particle input (sticky) */
   NBODY_ECORRUPT = -7    /* a kernel's consistency check failed (sticky) */
@@ -59,15 +59,22 @@ enum {
  *  group_max   : largest i-group (particles sharing one interaction list);
  *                1 <= group_max <= 64.
  *  compensated : 0 plain FP32 accumulation; 1 compensated (Neumaier) sum.
- *  order       : group queue order of the walk: 0 group (Morton) order,
- *                1 by the previous walk's per-group list length (longest
- *                first), 2 by a learned cost model (nbody_set_cost_model).
- *                The order never changes the results (bit-identical).
+ *  order       : group queue order of the walk: 0 group (Morton) order;
+ *                1 longest expected work first, estimated from the group's
+ *                size and its members' previous list lengths; 2 by the
+ *                learned cost model (nbody_set_cost_model; plain until one is
+ *                installed). Orders 1 and 2 also record the per-group
+ *                features and targets of the cost model (NBODY_X_FEAT,
+ *                NBODY_X_TARGET). The order never changes the results
+ *                (bit-identical). nbody_set_order changes it later.
  *  frontier_cap: cells per wavefront in the walk's breadth-first frontier
  *                buffer (power of two >= 64; 0 = the cell capacity rounded
- *                up to a power of two, at most 65536).
+ *                up to a power of two, at most 16384). A group whose
+ *                frontier outgrows it is walked again by a few wavefronts
+ *                whose frontier holds any tree (2n cells), so the results
+ *                never depend on it.
  *  list_tile   : interaction-list entries held in LDS per wavefront before a
- *                flush (multiple of 8, 64..2048; 0 = 256).
+ *                flush (multiple of 8, 64..2048; 0 = 192).
  *  waves_per_cu: resident wavefronts per compute unit of the persistent walk
  *                (1..32; 0 = 32).
  *  checks      : 0 none; 1 also record, per group, an order-independent hash
@@ -100,10 +107,20 @@ typedef struct nbody_ctx nbody_ctx; /* opaque; one per HIP stream */
  * x, y, z: FP64 positions; vx, vy, vz: FP32 velocities; m: FP32 masses;
  * ax, ay, az: FP32 accelerations of the last force evaluation (they are the
  * a_old of Eq. 2 and are overwritten by each step); t: simulation time
- * (host); dt: step length; have_acc: 0 if ax..az are not yet valid (the
- * first step then runs a bootstrap force evaluation first);
- * rebuild_interval: rebuild the tree every k steps (k >= 1), or 0 to let
- * the library choose by the measured build and walk times. */
+ * (host); dt: step length (the longest step dt_max with block steps);
+ * have_acc: 0 if ax..az are not yet valid (the first step then runs a
+ * bootstrap force evaluation first); rebuild_interval: rebuild the tree
+ * every k steps (k >= 1), or 0 to let the library choose by the measured
+ * build and walk times (nbody_rebuild_decide).
+ *
+ * Individual block time steps (the paper's integration, Sec. 1): with
+ * level != NULL particle i steps by dt * 2^-level[i]. level (int8, device)
+ * is set from the accelerations when have_acc == 0 and otherwise read as
+ * given (values outside [level_min, level_max] latch NBODY_ECORRUPT); a new
+ * level is the smallest k >= level_min, allowed by the current time, with
+ * dt 2^-k <= sqrt(2 eta eps / |a|) (eta > 0), at most level_max (<= 10).
+ * tick: time since the start in units of dt * 2^-10 (host; must be >= 0;
+ * advanced with t by nbody_step). */
 typedef struct {
   int64_t n;
   double *x, *y, *z;
@@ -114,6 +131,10 @@ typedef struct {
   double dt;
   int32_t have_acc;
   int32_t rebuild_interval;
+  int8_t *level;
+  double eta;
+  int32_t level_min, level_max;
+  int64_t tick;
 } nbody_state;
 
 /* Statistics (host struct filled by nbody_get_stats, BLOCKING).
@@ -122,7 +143,11 @@ typedef struct {
  *  t_build_ms, t_walk_ms: latest measured tree build / walk kernel time;
  *  walk_ms_sum/walk_calls, build_ms_sum/build_calls, entries_sum and
  *  interactions_sum: totals since the last nbody_timing call (HIP events on
- *  the context's stream around each walk launch and each build). */
+ *  the context's stream around each walk launch and each build);
+ *  queued: groups walked by the last walk; active: particles whose step
+ *  ended in the last block step; queued_sum, ngroup_sum: groups walked and
+ *  groups present, summed over the walks counted in walk_calls; retried:
+ *  groups of the last walk that outgrew frontier_cap and were walked again. */
 typedef struct {
   int64_t n, ncell, ngroup;
   int64_t list_entries;
@@ -135,6 +160,9 @@ typedef struct {
   int64_t build_calls;
   int64_t entries_sum;
   int64_t interactions_sum;
+  int64_t queued, active;
+  int64_t queued_sum, ngroup_sum;
+  int64_t retried;
 } nbody_stats;
 
 /* What nbody_export copies (element type, length). */
@@ -156,7 +184,11 @@ enum {
   NBODY_X_GENTRIES = 15, /* uint32[ngroup] list entries of the last walk */
   NBODY_X_GHASH = 16,    /* uint64[ngroup] order-independent entry hash */
   NBODY_X_XYZM = 17,     /* float32[n][4] sorted positions and masses */
-  NBODY_X_BOX = 18       /* float64[4]: root cube lo x, y, z, side L */
+  NBODY_X_BOX = 18,      /* float64[4]: root cube lo x, y, z, side L */
+  NBODY_X_QUEUE = 19,    /* uint32[queued] groups walked by the last walk, in order */
+  NBODY_X_FEAT = 20,     /* float32[ngroup][4] cost-model features (orders 1, 2) */
+  NBODY_X_TARGET = 21,   /* float32[ngroup] log2 interactions of the last walk */
+  NBODY_X_PRED = 22      /* float32[ngroup] the model's prediction (order 2) */
 };
 
 int32_t nbody_abi_version(void);
@@ -210,7 +242,13 @@ nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *ax_old,
 /* Advance the state by n_steps kick-drift-kick leapfrog steps of length
  * st->dt: v += a dt/2 (FP32); x += v dt (FP64); tree rebuild or refit from
  * the FP32 image of x; a = walk(a_old = previous a); v += a dt/2.
- * st->t is advanced on the host. */
+ * st->t is advanced on the host.
+ * With block steps (st->level != NULL) one step ends at the next step
+ * boundary of the finest occupied level: the particles starting a step take
+ * their opening half kick, every particle drifts, the groups holding a
+ * particle whose step ends are walked, and those particles take the closing
+ * half kick and a new level. Only they receive new accelerations. This form
+ * BLOCKS at its end to read the time reached (st->tick, st->t). */
 nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps);
 
 /* Eq. 1 by direct O(N^2) summation in FP32 on the GPU (the tree walk's
@@ -238,13 +276,60 @@ nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable);
 
 /* Host-only rebuild rule used by nbody_step when rebuild_interval == 0
  * (the paper tunes the rebuild interval to minimise tree-construction plus
- * gravity time, Sec. 1 and Sec. 4.1). With A = (t_build_ms + walk_sum_ms) /
- * steps_since the mean cost per step since the last rebuild, returns 1
- * (rebuild) iff steps_since >= max_interval or last_walk_ms >= A; 0 if
- * steps_since <= 0. Pure function, no device access. */
-int32_t nbody_rebuild_decide(double t_build_ms, double walk_sum_ms,
-                             double last_walk_ms, int32_t steps_since,
-                             int32_t max_interval);
+ * gravity time, Sec. 1 and Sec. 4.1). excess_ms is the measured extra walk
+ * time of the current tree: each walk adds t_walk (1 - I_ref / I), with I
+ * the interactions of the groups it walked and I_ref the same groups'
+ * interactions on their first walk of this tree. Returns 1 (rebuild) iff
+ * steps_since >= max_interval or excess_ms >= t_build_ms; 0 if steps_since
+ * <= 0. For an excess growing linearly per step this rebuilds at the interval
+ * that minimises the mean cost per step (the cumulative excess then equals
+ * the build time). nbody_step lets at most one walk go unmeasured before it
+ * decides. Pure function, no device access. */
+int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms,
+                             int32_t steps_since, int32_t max_interval);
+
+/* ---- Cost model of the walk queue (a small MLP: 4 inputs, two tanh layers
+ * of `hidden` units, one output; hidden in {8, 16, 32, 64}). It predicts a
+ * group's log2 interaction count from NBODY_X_FEAT-style features: log2 of
+ * the member count, log2(h + 2^-40) with h half the diagonal of the members'
+ * box, log2 of the group mass minus 3x the previous value, and log2(1 + the
+ * members' mean list length from their last walk). Weights: FP32, row-major
+ * output-major, W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3. All arrays are
+ * device memory; feat is [rows][4] FP32, 16-byte aligned. Calls enqueue on
+ * the context's stream (they need a bound workspace for scratch). */
+
+/* Number of weights for `hidden`, or -1 if hidden is not supported. */
+int64_t nbody_mlp_nparams(int32_t hidden);
+
+/* y[r] = the network's output for feat[r]. */
+nbody_status nbody_mlp_forward(nbody_ctx *ctx, int32_t hidden, const float *w,
+                               int64_t rows, const float *feat, float *y);
+
+/* grad_loss[0 .. np) = gradient of L = mean_r (y_r - target_r)^2 with
+ * respect to w (same layout), grad_loss[np] = L. Deterministic (fixed
+ * reduction order). */
+nbody_status nbody_mlp_grad(nbody_ctx *ctx, int32_t hidden, const float *w,
+                            int64_t rows, const float *feat, const float *target,
+                            float *grad_loss);
+
+/* One Adam step (Kingma and Ba 2015), step >= 1, in place on w, m, v. */
+nbody_status nbody_mlp_adam(nbody_ctx *ctx, int64_t n_params, float *w,
+                            const float *grad, float *m, float *v, int32_t step,
+                            float lr, float beta1, float beta2, float eps);
+
+/* BLOCKING: `steps` full-batch Adam steps (beta 0.9, 0.999, eps 1e-8) on the
+ * mean squared error, starting from and updating w. loss_out (host, may be
+ * NULL) receives the loss before each step. */
+nbody_status nbody_costmodel_train(nbody_ctx *ctx, int32_t hidden, float *w,
+                                   int64_t rows, const float *feat,
+                                   const float *target, int32_t steps, float lr,
+                                   float *loss_out);
+
+/* Install (copy) the weights used by order 2; w == NULL removes the model. */
+nbody_status nbody_set_cost_model(nbody_ctx *ctx, int32_t hidden, const float *w);
+
+/* Change the queue order (0, 1 or 2, as nbody_params.order). */
+nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order);
 
 #ifdef __cplusplus
 }

@@ -298,3 +298,13 @@ def random_subset(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct indices out of n: the first k entries of a seeded
     Fisher-Yates shuffle (numpy's permutation)."""
     return rng_for(seed, 5).permutation(int(n))[: int(k)].astype(np.int64)
+
+
+def mlp_init(n_params: int, fan_in: np.ndarray, seed: int) -> np.ndarray:
+    """Random initial weights for a small network: entry k uniform in
+    [-1/sqrt(fan_in[k]), 1/sqrt(fan_in[k])) (fan_in gives, per entry, the
+    number of inputs of the unit it feeds), float32."""
+    rng = rng_for(seed, 6)
+    fan = np.asarray(fan_in, np.float64)
+    assert fan.shape == (n_params,)
+    return (rng.uniform(-1.0, 1.0, n_params) / np.sqrt(fan)).astype(np.float32)

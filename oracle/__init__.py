@@ -270,14 +270,22 @@ class TreeResult:
 
 
 def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 ** -9,
-                leaf_max=16, group_max=64, group_merge=0, nthreads=None) -> TreeResult:
+                leaf_max=16, group_max=64, group_merge=0, topo=None,
+                nthreads=None) -> TreeResult:
     """All steps of the tree method for FP32 inputs in caller order.
 
     ``a_old`` (n, 3) in caller order, or None for the bootstrap pass
-    (geometric criterion, no previous acceleration)."""
+    (geometric criterion, no previous acceleration). ``topo`` = (x, y, z)
+    FP32 positions from which keys, sort order, cells and groups are taken
+    (a tree kept across steps: the paper rebuilds the topology only every
+    several steps but recomputes the moments every step, Sec. 1 and 4.1);
+    the moments, group boxes and forces always use (x, y, z)."""
     x, y, z, m = (_c(a, np.float32) for a in (x, y, z, m))
     n = x.shape[0]
-    k, box = keys(x, y, z)
+    if topo is None:
+        k, box = keys(x, y, z)
+    else:
+        k, box = keys(*(_c(a, np.float32) for a in topo))
     perm, ks = sort(k)
     sx, sy, sz, sm = x[perm], y[perm], z[perm], m[perm]
     cells = build_tree(ks, leaf_max)
@@ -317,6 +325,82 @@ def kdk_step(x64, v32, a32, m32, dt, force, *, nkick=None):
     return x, v, a
 
 
+# ------------------------------------------------------------ block steps
+TICK_BITS = 10  # the finest level: dt_max * 2^-10; one "tick" is that step
+
+
+def block_level(a32, dt_max, eta, eps, tick, level_min=0, level_max=TICK_BITS):
+    """Time-step level of each particle (individual block steps).
+
+    dt_k = dt_max 2^-k; the level is the smallest k in [k_lo, level_max] with
+    dt_k <= sqrt(2 eta eps / |a|), i.e. dt_k^4 |a|^2 <= (2 eta eps)^2, all in
+    FP64 with |a|^2 = (ax^2 + ay^2) + az^2 from the FP32 components (each
+    square exact). k_lo = max(level_min, k_align): a particle may only take a
+    step whose boundaries include the current time, so at tick T (mod 2^10)
+    k_align = 10 - (trailing zero bits of T), and 0 at a multiple of 2^10.
+    A particle meeting no level gets level_max."""
+    a = np.asarray(a32, np.float32).astype(np.float64)
+    a2 = (a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1]) + a[:, 2] * a[:, 2]
+    c = 2.0 * float(eta) * float(np.float32(eps))
+    rhs = c * c
+    t = int(tick) % (1 << TICK_BITS)
+    k_align = 0 if t == 0 else TICK_BITS - ((t & -t).bit_length() - 1)
+    lo = max(int(level_min), k_align)
+    lev = np.full(a.shape[0], int(level_max), np.int8)
+    done = np.zeros(a.shape[0], bool)
+    for k in range(lo, int(level_max) + 1):
+        dk = float(dt_max) / float(1 << k)
+        d2 = dk * dk
+        ok = ~done & ((d2 * d2) * a2 <= rhs)
+        lev[ok] = k
+        done |= ok
+    return lev
+
+
+def _steps_ticks(level):
+    return np.left_shift(np.int64(1), (TICK_BITS - level.astype(np.int64)))
+
+
+def block_step(x64, v32, a32, level, dt_max, tick, force, *, eta, eps, level_min=0,
+               level_max=TICK_BITS):
+    """One smallest step of individual block time steps with kick-drift-kick.
+
+    Particle i has step dt_max 2^-level_i, i.e. 2^(10-level_i) ticks, and
+    its step boundaries are the multiples of that. From tick T0:
+      1. the particles with a boundary at T0 take the opening half kick
+         v += a dt_i/2 (FP32);
+      2. T1 = the next boundary of the finest occupied level; every particle
+         drifts x += v (T1 - T0) dt_tick (FP64);
+      3. the particles with a boundary at T1 are active: a = force(x as FP32,
+         a_old = a) for them (the others keep a);
+      4. active particles take the closing half kick with their old step and
+         then choose a new level (block_level at T1).
+    With every particle held on one level this is kick-drift-kick leapfrog
+    with dt = dt_max 2^-level operation for operation. ``force`` maps FP32
+    (n, 3) positions and the FP32 a_old to FP32 accelerations of all
+    particles. Returns (x64, v32, a32, level, T1, active)."""
+    level = np.asarray(level, np.int8).copy()
+    v = np.asarray(v32, np.float32).copy()
+    a = np.asarray(a32, np.float32).copy()
+    T0 = int(tick)
+    step = _steps_ticks(level)
+    hdt = np.array([np.float32(0.5 * (float(dt_max) / float(1 << k)))
+                    for k in range(TICK_BITS + 1)], np.float32)
+    opening = (T0 % step) == 0
+    h = hdt[level][:, None]
+    v[opening] = (v[opening] + (a[opening] * h[opening]).astype(np.float32)).astype(np.float32)
+    s = 1 << (TICK_BITS - int(level.max()))
+    T1 = (T0 // s + 1) * s
+    dt_sub = float(T1 - T0) * (float(dt_max) / float(1 << TICK_BITS))
+    x = np.asarray(x64, np.float64) + v.astype(np.float64) * np.float64(dt_sub)
+    active = (T1 % step) == 0
+    a_new = np.asarray(force(x.astype(np.float32), a), np.float32)
+    a[active] = a_new[active]
+    v[active] = (v[active] + (a[active] * h[active]).astype(np.float32)).astype(np.float32)
+    level[active] = block_level(a[active], dt_max, eta, eps, T1, level_min, level_max)
+    return x, v, a, level, T1, active
+
+
 # ------------------------------------------------------------------ MLP
 def mlp_nparams(hidden=32) -> int:
     return int(lib().orc_mlp_nparams(hidden))
@@ -337,3 +421,72 @@ def mlp_grad(w, feat, target, hidden=32):
     g = np.empty_like(w)
     loss = lib().orc_mlp_grad(hidden, w, f.shape[0], f, t, g)
     return loss, g
+
+
+def mlp_fan_in(hidden=32) -> np.ndarray:
+    """Fan-in of the unit each weight feeds, in the weight layout
+    W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3 (for the seeded initialiser)."""
+    H = hidden
+    return np.concatenate([np.full(4 * H, 4), np.full(H, 4), np.full(H * H, H), np.full(H, H),
+                           np.full(H, H), [H]]).astype(np.float64)
+
+
+def adam_step(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015) in FP64, step number t >= 1:
+    m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+    w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)."""
+    w, g, m, v = (np.asarray(a, np.float64) for a in (w, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def mlp_train(w0, feat, target, *, hidden=32, steps=100, lr=1e-2):
+    """Full-batch Adam on the mean squared error, FP64; returns (w, losses)."""
+    w = np.asarray(w0, np.float64).copy()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    losses = []
+    for t in range(1, steps + 1):
+        loss, g = mlp_grad(w, feat, target, hidden=hidden)
+        losses.append(loss)
+        w, m, v = adam_step(w, g, m, v, t, lr)
+    return w, np.array(losses)
+
+
+# ------------------------------------------------------- cost-model inputs
+DENSITY_FLOOR = 2.0 ** -40  # keeps log2 finite for a one-particle group
+
+
+def cost_features(grp, sx, sy, sz, sm, prev_count_sorted):
+    """Inputs of the learned cost model, per group, in FP64:
+      f0 = log2(count);
+      f1 = log2(h + 2^-40), h = half the diagonal of the members' box;
+      f2 = log2(M) - 3 f1 (mass over the cube of h, a local density);
+      f3 = log2(1 + mean over members of their previous list length).
+    Arrays are sorted FP32 positions and masses; prev_count_sorted holds each
+    particle's list length from its last walk (0 if never walked)."""
+    ng = grp.n
+    f = np.empty((ng, 4))
+    pc = np.asarray(prev_count_sorted, np.float64)
+    for g in range(ng):
+        b, c = int(grp.begin[g]), int(grp.count[g])
+        px = np.asarray(sx[b:b + c], np.float64)
+        py = np.asarray(sy[b:b + c], np.float64)
+        pz = np.asarray(sz[b:b + c], np.float64)
+        ex, ey, ez = px.max() - px.min(), py.max() - py.min(), pz.max() - pz.min()
+        h = 0.5 * np.sqrt(ex * ex + ey * ey + ez * ez)
+        f1 = np.log2(h + DENSITY_FLOOR)
+        f[g, 0] = np.log2(c)
+        f[g, 1] = f1
+        f[g, 2] = np.log2(np.asarray(sm[b:b + c], np.float64).sum()) - 3.0 * f1
+        f[g, 3] = np.log2(1.0 + pc[b:b + c].mean())
+    return f
+
+
+def cost_target(grp, gentries):
+    """Training target: log2 of the group's interactions, count x list length."""
+    return np.log2(np.maximum(1.0, np.asarray(grp.count, np.float64) *
+                              np.asarray(gentries, np.float64)))

@@ -25,8 +25,9 @@ class X:
     """Export selectors (NBODY_X_* of nbody.h): name -> (code, dtype name, per-unit)."""
 
     KEYS, PERM, LEVEL, PBEGIN, PCOUNT, FCHILD, NCHILD, PARENT = 1, 2, 3, 4, 5, 6, 7, 8
-    NODE, MQ, MOM64, GBEGIN, GCOUNT, GBOX, GENTRIES, GHASH, XYZM, BOX = (
-        9, 10, 11, 12, 13, 14, 15, 16, 17, 18)
+    NODE, MQ, MOM64, GBEGIN, GCOUNT, GBOX, GENTRIES, GHASH, XYZM, BOX, QUEUE = (
+        9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19)
+    FEAT, TARGET, PRED = 20, 21, 22
     # (dtype, unit: 'n' | 'cell' | 'group' | 'fixed', elements per unit)
     SPEC = {
         1: ("uint64", "n", 1), 2: ("int32", "n", 1), 3: ("int32", "cell", 1),
@@ -35,6 +36,8 @@ class X:
         10: ("float32", "cell", 2), 11: ("float64", "cell", 4), 12: ("int32", "group", 1),
         13: ("int32", "group", 1), 14: ("float32", "group", 8), 15: ("int32", "group", 1),
         16: ("uint64", "group", 1), 17: ("float32", "n", 4), 18: ("float64", "fixed", 4),
+        19: ("int32", "queued", 1), 20: ("float32", "group", 4), 21: ("float32", "group", 1),
+        22: ("float32", "group", 1),
     }
 
 
@@ -59,7 +62,9 @@ class _State(C.Structure):
                 ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
                 ("m", C.c_void_p), ("ax", C.c_void_p), ("ay", C.c_void_p),
                 ("az", C.c_void_p), ("t", C.c_double), ("dt", C.c_double),
-                ("have_acc", C.c_int32), ("rebuild_interval", C.c_int32)]
+                ("have_acc", C.c_int32), ("rebuild_interval", C.c_int32),
+                ("level", C.c_void_p), ("eta", C.c_double), ("level_min", C.c_int32),
+                ("level_max", C.c_int32), ("tick", C.c_int64)]
 
 
 class _Stats(C.Structure):
@@ -69,7 +74,8 @@ class _Stats(C.Structure):
                 ("t_walk_ms", C.c_double), ("walk_ms_sum", C.c_double),
                 ("walk_calls", C.c_int64), ("build_ms_sum", C.c_double),
                 ("build_calls", C.c_int64), ("entries_sum", C.c_int64),
-                ("interactions_sum", C.c_int64)]
+                ("interactions_sum", C.c_int64), ("queued", C.c_int64), ("active", C.c_int64),
+                ("queued_sum", C.c_int64), ("ngroup_sum", C.c_int64), ("retried", C.c_int64)]
 
 
 # every function declared in include/nbody.h (checked by the tests)
@@ -78,6 +84,8 @@ HEADER_FUNCTIONS = [
     "nbody_destroy", "nbody_workspace_query", "nbody_bind_workspace", "nbody_build_tree",
     "nbody_refit", "nbody_calc_acc", "nbody_step", "nbody_direct", "nbody_export",
     "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide", "nbody_timing",
+    "nbody_mlp_nparams", "nbody_mlp_forward", "nbody_mlp_grad", "nbody_mlp_adam",
+    "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order",
 ]
 
 _lib = None
@@ -110,8 +118,17 @@ def lib():
         L.nbody_get_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.nbody_sync.argtypes = [vp]
         L.nbody_timing.argtypes = [vp, i32]
-        L.nbody_rebuild_decide.argtypes = [C.c_double, C.c_double, C.c_double, i32, i32]
+        L.nbody_rebuild_decide.argtypes = [C.c_double, C.c_double, i32, i32]
         L.nbody_rebuild_decide.restype = i32
+        f32 = C.c_float
+        L.nbody_mlp_nparams.argtypes = [i32]
+        L.nbody_mlp_nparams.restype = i64
+        L.nbody_mlp_forward.argtypes = [vp, i32, vp, i64, vp, vp]
+        L.nbody_mlp_grad.argtypes = [vp, i32, vp, i64, vp, vp, vp]
+        L.nbody_mlp_adam.argtypes = [vp, i64, vp, vp, vp, vp, i32, f32, f32, f32, f32]
+        L.nbody_costmodel_train.argtypes = [vp, i32, vp, i64, vp, vp, i32, f32, vp]
+        L.nbody_set_cost_model.argtypes = [vp, i32, vp]
+        L.nbody_set_order.argtypes = [vp, i32]
         for f in HEADER_FUNCTIONS:
             fn = getattr(L, f)
             if fn.restype is C.c_int or fn.restype is None and f != "nbody_destroy":
@@ -125,10 +142,25 @@ def _check(code: int, where: str):
         raise NbodyError(code, where)
 
 
-def rebuild_decide(t_build_ms, walk_sum_ms, last_walk_ms, steps_since, max_interval=64):
+def mlp_nparams(hidden: int) -> int:
+    v = lib().nbody_mlp_nparams(int(hidden))
+    if v < 0:
+        raise ValueError("unsupported hidden width %d" % hidden)
+    return int(v)
+
+
+def mlp_fan_in(hidden: int):
+    """Inputs of the unit each weight feeds, in the library's weight layout
+    W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3 (for an initialiser)."""
+    import numpy as np
+    H = int(hidden)
+    return np.concatenate([np.full(5 * H, 4), np.full(H * H + H, H), np.full(H + 1, H)]
+                          ).astype(np.float64)
+
+
+def rebuild_decide(t_build_ms, excess_ms, steps_since, max_interval=64):
     """The library's host-side rebuild rule (pure function)."""
-    return bool(lib().nbody_rebuild_decide(t_build_ms, walk_sum_ms, last_walk_ms,
-                                           steps_since, max_interval))
+    return bool(lib().nbody_rebuild_decide(t_build_ms, excess_ms, steps_since, max_interval))
 
 
 @dataclass
@@ -253,11 +285,60 @@ class Context:
     def step(self, state: "State", n_steps: int = 1):
         cs = state._c()
         _check(lib().nbody_step(self._h, C.byref(cs), int(n_steps)), "nbody_step")
+        self.n = state.n
         state.t = cs.t
+        state.tick = cs.tick
         state.have_acc = cs.have_acc
 
     def sync(self):
         _check(lib().nbody_sync(self._h), "nbody_sync")
+
+    # ---- cost model of the walk queue (all tensors float32 CUDA, contiguous)
+    def mlp_forward(self, hidden, w, feat, out=None):
+        import torch
+        rows = feat.shape[0]
+        if out is None:
+            out = torch.empty(rows, dtype=torch.float32, device=self.device)
+        _need(feat, torch.float32, 4 * rows, "feat")
+        _need(w, torch.float32, mlp_nparams(hidden), "w")
+        _check(lib().nbody_mlp_forward(self._h, hidden, _ptr(w), rows, _ptr(feat), _ptr(out)),
+               "nbody_mlp_forward")
+        return out
+
+    def mlp_grad(self, hidden, w, feat, target):
+        """Returns (gradient tensor, loss tensor) of the mean squared error."""
+        import torch
+        rows = feat.shape[0]
+        npar = mlp_nparams(hidden)
+        out = torch.empty(npar + 1, dtype=torch.float32, device=self.device)
+        _need(feat, torch.float32, 4 * rows, "feat")
+        _need(target, torch.float32, rows, "target")
+        _need(w, torch.float32, npar, "w")
+        _check(lib().nbody_mlp_grad(self._h, hidden, _ptr(w), rows, _ptr(feat), _ptr(target),
+                                    _ptr(out)), "nbody_mlp_grad")
+        return out[:npar], out[npar]
+
+    def mlp_adam(self, w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().nbody_mlp_adam(self._h, w.numel(), _ptr(w), _ptr(g), _ptr(m), _ptr(v),
+                                    int(step), float(lr), float(beta1), float(beta2),
+                                    float(eps)), "nbody_mlp_adam")
+
+    def train_cost_model(self, hidden, w, feat, target, steps, lr):
+        """Full-batch Adam on the device, in place on w; returns the losses."""
+        import numpy as np
+        losses = np.zeros(int(steps), np.float32)
+        _check(lib().nbody_costmodel_train(self._h, hidden, _ptr(w), feat.shape[0], _ptr(feat),
+                                           _ptr(target), int(steps), float(lr),
+                                           losses.ctypes.data_as(C.c_void_p)),
+               "nbody_costmodel_train")
+        return losses
+
+    def set_cost_model(self, hidden, w):
+        _check(lib().nbody_set_cost_model(self._h, hidden, _ptr(w)), "nbody_set_cost_model")
+        self._keep_w = w
+
+    def set_order(self, order: int):
+        _check(lib().nbody_set_order(self._h, int(order)), "nbody_set_order")
 
     def timing(self, enable: bool = True):
         """Zero the timing totals; with enable, count interactions of every walk."""
@@ -272,7 +353,8 @@ class Context:
         import torch
         dt, unit, per = X.SPEC[what]
         st = self.stats()
-        cnt = {"n": self.n, "cell": st["ncell"], "group": st["ngroup"], "fixed": 1}[unit] * per
+        cnt = {"n": self.n, "cell": st["ncell"], "group": st["ngroup"], "fixed": 1,
+               "queued": st["queued"]}[unit] * per
         out = torch.empty(max(cnt, 1), dtype=getattr(torch, dt), device=self.device)
         _check(lib().nbody_export(self._h, what, _ptr(out), out.numel()), "nbody_export")
         self.sync()
@@ -297,18 +379,26 @@ class State:
     dt: float = 2.0 ** -7
     have_acc: int = 0
     rebuild_interval: int = 1
+    level: object = None  # int8 tensor: individual block time steps
+    eta: float = 0.025
+    level_min: int = 0
+    level_max: int = 10
+    tick: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     @classmethod
-    def from_numpy(cls, pos, vel, mass, device="cuda", dt=2.0 ** -7, rebuild_interval=1):
+    def from_numpy(cls, pos, vel, mass, device="cuda", dt=2.0 ** -7, rebuild_interval=1,
+                   block_steps=False, **kw):
         import torch
         import numpy as np
         f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
         f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
         n = len(mass)
         st = cls(f64(pos[:, 0]), f64(pos[:, 1]), f64(pos[:, 2]), f32(vel[:, 0]), f32(vel[:, 1]),
-                 f32(vel[:, 2]), f32(mass), dt=dt, rebuild_interval=rebuild_interval)
+                 f32(vel[:, 2]), f32(mass), dt=dt, rebuild_interval=rebuild_interval, **kw)
         st.ax, st.ay, st.az = (torch.zeros(n, dtype=torch.float32, device=device) for _ in range(3))
+        if block_steps:
+            st.level = torch.zeros(n, dtype=torch.int8, device=device)
         return st
 
     @property
@@ -323,6 +413,10 @@ class State:
         for t, nm in ((self.vx, "vx"), (self.vy, "vy"), (self.vz, "vz"), (self.m, "m"),
                       (self.ax, "ax"), (self.ay, "ay"), (self.az, "az")):
             _need(t, torch.float32, n, nm)
+        lev = None
+        if self.level is not None:
+            lev = _need(self.level, torch.int8, n, "level").data_ptr()
         return _State(n, *(t.data_ptr() for t in (self.x, self.y, self.z, self.vx, self.vy,
                                                    self.vz, self.m, self.ax, self.ay, self.az)),
-                      self.t, self.dt, self.have_acc, self.rebuild_interval)
+                      self.t, self.dt, self.have_acc, self.rebuild_interval, lev, self.eta,
+                      self.level_min, self.level_max, self.tick)

@@ -28,17 +28,25 @@ struct nbody_ctx {
   // step statistics and rebuild controller
   int64_t steps = 0, rebuilds = 0;
   int32_t since_rebuild = 0;
-  double walk_sum_ms = 0.0;  // walk time since the last rebuild
+  int64_t epoch = 0;      // tree builds so far (tags the spans of each tree)
+  double excess_ms = 0.0;  // measured extra walk time of the current tree
   double t_build_ms = 0.0, t_walk_ms = 0.0;  // latest measured (events)
-  // timed spans: a ring of (start, end) event pairs around each tree build
-  // and each walk launch, harvested without blocking
+  // timed spans: a ring of (start, end, done) events around each tree build
+  // and each walk launch; a walk span's done event follows the copy of its
+  // statistics to pinned host memory
   static constexpr int kSpans = 64;
-  hipEvent_t ev_a[kSpans] = {}, ev_b[kSpans] = {};
+  hipEvent_t ev_a[kSpans] = {}, ev_b[kSpans] = {}, ev_c[kSpans] = {};
   int span_kind[kSpans] = {};
+  int64_t span_epoch[kSpans] = {};
   int sp_head = 0, sp_count = 0;
   double walk_ms_sum = 0.0, build_ms_sum = 0.0;
   int64_t walk_calls = 0, build_calls = 0;
   bool counting = false;  // accumulate interactions of every walk on the device
+  WalkStat *aux = nullptr;   // pinned, one per span (walk spans)
+  bool last_queued = false;  // the last walk used the queue (block steps)
+  int64_t queued_sum = 0, ngroup_sum = 0;  // groups walked / present, summed over walks
+  int order = 0;       // queue order in use (params.order, or nbody_set_order)
+  int mlp_hidden = 0;  // hidden width of the installed cost model (0: none)
 };
 
 namespace {
@@ -88,7 +96,7 @@ int eff_tile(const nbody_params &p) { return p.list_tile ? p.list_tile : 192; }
 int64_t eff_frontier(const nbody_params &p, int64_t cell_cap) {
   if (p.frontier_cap) return p.frontier_cap;
   int64_t f = 64;
-  while (f < cell_cap && f < 65536) f <<= 1;
+  while (f < cell_cap && f < 16384) f <<= 1;
   return f;
 }
 
@@ -110,13 +118,16 @@ nbody_status status_from_bits(int32_t b) {
 namespace nb {
 
 Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
-  Layout L;
+  Layout L{};  // offsets not taken below stay 0 (caught by carve_complete)
   L.n_max = n;
   L.cell_cap = n + cdiv(21 * n, p.leaf_max + 1) + 2;
   L.sort_blocks = cdiv(n, kSortTile);
   L.build_blocks = cdiv(n, kBuildThreads);
   L.walk_waves = (int64_t)num_cu * eff_waves(p);
   L.frontier_cap = eff_frontier(p, L.cell_cap);
+  L.frontier2_cap = 64;
+  while (L.frontier2_cap < 2 * n) L.frontier2_cap <<= 1;
+  L.retry_waves = 2 * kWalkWavesPerWG;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -152,13 +163,39 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_order = take(4 * N);
   L.off_prevcnt = take(4 * N);
   L.off_frontier = take(4 * (size_t)L.walk_waves * (size_t)L.frontier_cap);
+  L.off_atmp = take(12 * N);
+  L.off_retry = take(4 * N);
+  L.off_frontier2 = take(4 * (size_t)L.retry_waves * (size_t)L.frontier2_cap);
+  L.off_feat = take(16 * N);
+  L.off_target = take(4 * N);
+  L.off_pred = take(4 * N);
+  L.off_plast = take(4 * N);
+  L.off_okeys = take(16 * N);
+  L.off_qtmp = take(4 * N);
+  L.off_mlpw = take(4 * (size_t)kMlpMaxParams);
+  L.off_mlpm = take(4 * (size_t)kMlpMaxParams);
+  L.off_mlpv = take(4 * (size_t)kMlpMaxParams);
+  L.off_mlpg = take(4 * (size_t)(kMlpMaxParams + 1));
+  L.off_mlppart = take(4 * (size_t)kMlpWaves * (size_t)(kMlpMaxParams + 1));
+  L.off_gref = take(4 * N);
   L.total = o;
   return L;
 }
 
+// Every buffer but the scalars lies past offset 0: a pointer that is null or
+// at the workspace base was never carved (a missing layout entry).
+bool carve_complete(const Ptrs &P, const void *base) {
+  static_assert(sizeof(Ptrs) % sizeof(void *) == 0, "Ptrs holds pointers only");
+  void *slots[sizeof(Ptrs) / sizeof(void *)];
+  memcpy(slots, &P, sizeof(Ptrs));
+  for (size_t i = 1; i < sizeof(Ptrs) / sizeof(void *); ++i)
+    if (slots[i] == nullptr || slots[i] == base) return false;
+  return slots[0] == base;
+}
+
 Ptrs carve(void *base, const Layout &L) {
   char *b = static_cast<char *>(base);
-  Ptrs P;
+  Ptrs P{};
   P.sc = reinterpret_cast<DevScalars *>(b + L.off_scalars);
   P.keysA = reinterpret_cast<uint64_t *>(b + L.off_keysA);
   P.keysB = reinterpret_cast<uint64_t *>(b + L.off_keysB);
@@ -187,18 +224,35 @@ Ptrs carve(void *base, const Layout &L) {
   P.order = reinterpret_cast<uint32_t *>(b + L.off_order);
   P.prevcnt = reinterpret_cast<uint32_t *>(b + L.off_prevcnt);
   P.frontier = reinterpret_cast<uint32_t *>(b + L.off_frontier);
+  P.atmp = reinterpret_cast<float *>(b + L.off_atmp);
+  P.retry = reinterpret_cast<uint32_t *>(b + L.off_retry);
+  P.frontier2 = reinterpret_cast<uint32_t *>(b + L.off_frontier2);
+  P.feat = reinterpret_cast<float4 *>(b + L.off_feat);
+  P.target = reinterpret_cast<float *>(b + L.off_target);
+  P.pred = reinterpret_cast<float *>(b + L.off_pred);
+  P.plast = reinterpret_cast<uint32_t *>(b + L.off_plast);
+  P.okeys = reinterpret_cast<uint64_t *>(b + L.off_okeys);
+  P.qtmp = reinterpret_cast<uint32_t *>(b + L.off_qtmp);
+  P.mlpw = reinterpret_cast<float *>(b + L.off_mlpw);
+  P.mlpm = reinterpret_cast<float *>(b + L.off_mlpm);
+  P.mlpv = reinterpret_cast<float *>(b + L.off_mlpv);
+  P.mlpg = reinterpret_cast<float *>(b + L.off_mlpg);
+  P.mlppart = reinterpret_cast<float *>(b + L.off_mlppart);
+  P.gref = reinterpret_cast<uint32_t *>(b + L.off_gref);
   return P;
 }
 
 }  // namespace nb
 
 // Reduction of the walk statistics: sum of entries and entries x size.
+// With order != nullptr only the queued groups order[0 .. nqueue) count.
 __global__ __launch_bounds__(256) void k_stats(DevScalars *sc, const uint32_t *gent,
-                                               const uint32_t *gcount) {
-  const uint32_t ng = sc->ngroup;
+                                               const uint32_t *gcount, const uint32_t *order) {
+  const uint32_t ng = order ? sc->nqueue : sc->ngroup;
   unsigned long long e = 0, it = 0;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
-       g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ng;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t g = order ? order[q] : (uint32_t)q;
     const uint32_t v = gent[g] == 0xffffffffu ? 0u : gent[g];
     e += v;
     it += (unsigned long long)v * gcount[g];
@@ -215,11 +269,13 @@ __global__ __launch_bounds__(256) void k_stats(DevScalars *sc, const uint32_t *g
 
 // Running totals over walks while counting is on (nbody_timing).
 __global__ __launch_bounds__(256) void k_stats_accum(DevScalars *sc, const uint32_t *gent,
-                                                     const uint32_t *gcount) {
-  const uint32_t ng = sc->ngroup;
+                                                     const uint32_t *gcount,
+                                                     const uint32_t *order) {
+  const uint32_t ng = order ? sc->nqueue : sc->ngroup;
   unsigned long long e = 0, it = 0;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
-       g += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < ng;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t g = order ? order[q] : (uint32_t)q;
     const uint32_t v = gent[g] == 0xffffffffu ? 0u : gent[g];
     e += v;
     it += (unsigned long long)v * gcount[g];
@@ -254,6 +310,12 @@ __global__ void k_scalars_init(DevScalars *sc) {
   sc->inter_total = 0;
   sc->entries_acc = 0;
   sc->inter_acc = 0;
+  sc->tick = 0;
+  sc->tick0 = 0;
+  sc->kmax = 0;
+  sc->kmax_next = 0;
+  sc->nqueue = 0;
+  sc->nactive = 0;
 }
 
 // FP32 image of FP64 positions (caller order) into x32[3][n].
@@ -276,7 +338,7 @@ nbody_status pre(nbody_ctx *ctx) {
   return NBODY_OK;
 }
 
-WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap) {
+WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap, bool queued) {
   WalkCfg c;
   c.G = ctx->p.G;
   c.eps = ctx->p.eps;
@@ -287,7 +349,9 @@ WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap) {
   c.hash = ctx->p.checks != 0;
   c.waves_per_cu = eff_waves(ctx->p);
   c.num_cu = ctx->num_cu;
-  c.use_order = 0;
+  c.use_order = queued ? 1 : 0;
+  c.frontier2_cap = ctx->L.frontier2_cap;
+  c.retry_waves = ctx->L.retry_waves;
   return c;
 }
 
@@ -297,6 +361,7 @@ int span_begin(nbody_ctx *ctx, int kind) {
   if (ctx->sp_count == nbody_ctx::kSpans) harvest(ctx, true);
   const int i = (ctx->sp_head + ctx->sp_count) % nbody_ctx::kSpans;
   ctx->span_kind[i] = kind;
+  ctx->span_epoch[i] = ctx->epoch;
   (void)hipEventRecord(ctx->ev_a[i], ctx->st);
   return i;
 }
@@ -306,15 +371,32 @@ void span_end(nbody_ctx *ctx, int i) {
   ctx->sp_count++;
 }
 
-// Fold finished spans into the timers (oldest first); with block, wait for
-// the oldest pending span only.
+// After the end event of walk span i: its statistics to pinned memory, then
+// the span's done event.
+void span_stats(nbody_ctx *ctx, int i, bool queued) {
+  launch_walk_stat(queued, ctx->P, ctx->st);
+  (void)hipMemcpyAsync(&ctx->aux[i], &ctx->P.sc->wstat, sizeof(WalkStat),
+                       hipMemcpyDeviceToHost, ctx->st);
+}
+
+void span_done(nbody_ctx *ctx, int i) { (void)hipEventRecord(ctx->ev_c[i], ctx->st); }
+
+int pending_walks(const nbody_ctx *ctx) {
+  int k = 0;
+  for (int j = 0; j < ctx->sp_count; ++j)
+    k += ctx->span_kind[(ctx->sp_head + j) % nbody_ctx::kSpans] == 1;
+  return k;
+}
+
+// Fold finished spans into the timers and the rebuild controller (oldest
+// first); with block, wait for the oldest pending span.
 void harvest(nbody_ctx *ctx, bool block) {
   bool first = true;
   while (ctx->sp_count > 0) {
     const int i = ctx->sp_head;
     if (block && first) {
-      if (hipEventSynchronize(ctx->ev_b[i]) != hipSuccess) return;
-    } else if (hipEventQuery(ctx->ev_b[i]) != hipSuccess) {
+      if (hipEventSynchronize(ctx->ev_c[i]) != hipSuccess) return;
+    } else if (hipEventQuery(ctx->ev_c[i]) != hipSuccess) {
       return;
     }
     first = false;
@@ -325,9 +407,15 @@ void harvest(nbody_ctx *ctx, bool block) {
         ctx->build_ms_sum += ms;
         ctx->build_calls++;
       } else {
+        const WalkStat &w = ctx->aux[i];
         ctx->t_walk_ms = ms;
         ctx->walk_ms_sum += ms;
         ctx->walk_calls++;
+        ctx->queued_sum += w.queued;
+        ctx->ngroup_sum += w.ngroup;
+        // extra time of this walk over the same groups on a fresh tree
+        if (ctx->span_epoch[i] == ctx->epoch && w.inter > 0 && w.inter_ref < w.inter)
+          ctx->excess_ms += ms * (1.0 - (double)w.inter_ref / (double)w.inter);
       }
     }
     ctx->sp_head = (ctx->sp_head + 1) % nbody_ctx::kSpans;
@@ -338,6 +426,8 @@ void harvest(nbody_ctx *ctx, bool block) {
 nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
                       const float *z, const float *m) {
   const Ptrs &P = ctx->P;
+  ctx->epoch++;
+  ctx->excess_ms = 0.0;
   const int sp = span_begin(ctx, 0);
   launch_bbox(x, y, z, n, P.sc, ctx->st);
   launch_keys(x, y, z, n, P.sc, P.keysA, P.valsA, ctx->st);
@@ -350,6 +440,8 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
                ctx->st);
   launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
   span_end(ctx, sp);
+  span_done(ctx, sp);
+  launch_fill_u32(P.gref, 0u, n, ctx->st);
   ctx->keys = ks;
   ctx->perm = pm;
   ctx->n = n;
@@ -364,17 +456,32 @@ nbody_status do_refit(nbody_ctx *ctx, const float *x, const float *y, const floa
   return hip_status();
 }
 
+// queued: walk only the groups order[0 .. nqueue) (block steps). With a
+// cost-ordered queue the groups are first sorted by predicted cost, and after
+// the walk each member keeps its list length and each group its target.
 nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const float *azo,
-                     float *ax, float *ay, float *az) {
+                     float *ax, float *ay, float *az, bool queued = false) {
   const bool boot = axo == nullptr;
-  launch_group_bounds(axo, ayo, azo, ctx->perm, ctx->n, ctx->p.delta_acc, ctx->P, ctx->st);
-  launch_fill_u32(&ctx->P.sc->queue_head, 0u, 1, ctx->st);
+  const Ptrs &P = ctx->P;
+  launch_group_bounds(axo, ayo, azo, ctx->perm, ctx->n, ctx->p.delta_acc, P, ctx->st);
+  // the learned order needs an installed model; until then the queue is plain
+  const int mode = (ctx->order == 2 && ctx->mlp_hidden == 0) ? 0 : ctx->order;
+  if (mode != 0) {
+    launch_cost_features(ctx->n, ctx->perm, P, ctx->st);
+    launch_cost_order(ctx->n, queued, mode, ctx->mlp_hidden, P, ctx->st);
+  }
+  const bool use_queue = queued || mode != 0;
+  launch_fill_u32(&P.sc->queue_head, 0u, 1, ctx->st);
   const int sp = span_begin(ctx, 1);
-  launch_walk(walk_cfg(ctx, boot), ctx->perm, ctx->n, ax, ay, az, ctx->P, ctx->st);
+  launch_walk(walk_cfg(ctx, boot, use_queue), ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
   span_end(ctx, sp);
+  span_stats(ctx, sp, use_queue);
+  span_done(ctx, sp);
+  ctx->last_queued = use_queue;
+  if (mode != 0) launch_cost_after(ctx->n, true, ctx->perm, P, ctx->st);
   if (ctx->counting)
-    hipLaunchKernelGGL(k_stats_accum, dim3(256), dim3(256), 0, ctx->st, ctx->P.sc,
-                       ctx->P.gent, ctx->P.gcount);
+    hipLaunchKernelGGL(k_stats_accum, dim3(256), dim3(256), 0, ctx->st, P.sc, P.gent,
+                       P.gcount, use_queue ? P.order : nullptr);
   return hip_status();
 }
 
@@ -422,13 +529,27 @@ nbody_status nbody_params_default(nbody_params *p) {
 // minimises tree-construction plus gravity time): with average cost per step
 // since the last rebuild A = (t_build + sum of walk times) / k, rebuild when
 // the latest walk time reaches A. Exported for host-side testing.
-int32_t nbody_rebuild_decide(double t_build_ms, double walk_sum_ms, double last_walk_ms,
-                             int32_t steps_since, int32_t max_interval) {
+int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms, int32_t steps_since,
+                             int32_t max_interval) {
   if (steps_since <= 0) return 0;
   if (steps_since >= max_interval) return 1;
-  const double avg = (t_build_ms + walk_sum_ms) / (double)steps_since;
-  return last_walk_ms >= avg ? 1 : 0;
+  return excess_ms >= t_build_ms ? 1 : 0;
 }
+
+}  // extern "C"
+
+namespace {
+// Before a step's decision: wait until at most one walk is unmeasured (the
+// previous step's), so the rule never runs far behind the device.
+bool rebuild_due(nbody_ctx *ctx, int32_t max_interval) {
+  harvest(ctx, false);
+  while (pending_walks(ctx) > 1) harvest(ctx, true);
+  return nbody_rebuild_decide(ctx->t_build_ms, ctx->excess_ms, ctx->since_rebuild,
+                              max_interval) != 0;
+}
+}  // namespace
+
+extern "C" {
 
 nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **out) {
   if (!out) return NBODY_EINVAL;
@@ -438,6 +559,7 @@ nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **o
   nbody_ctx *c = new (std::nothrow) nbody_ctx();
   if (!c) return NBODY_EINVAL;
   c->p = *p;
+  c->order = p->order;
   c->st = static_cast<hipStream_t>(hip_stream);
   c->num_cu = device_cu_count(&c->device);
   if (c->num_cu <= 0) {
@@ -446,10 +568,17 @@ nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **o
   }
   for (int i = 0; i < nbody_ctx::kSpans; ++i)
     if (hipEventCreate(&c->ev_a[i]) != hipSuccess ||
-        hipEventCreate(&c->ev_b[i]) != hipSuccess) {
+        hipEventCreate(&c->ev_b[i]) != hipSuccess ||
+        hipEventCreate(&c->ev_c[i]) != hipSuccess) {
       nbody_destroy(c);
       return NBODY_EHIP;
     }
+  if (hipHostMalloc((void **)&c->aux, sizeof(WalkStat) * nbody_ctx::kSpans,
+                    hipHostMallocDefault) != hipSuccess) {
+    c->aux = nullptr;
+    nbody_destroy(c);
+    return NBODY_EHIP;
+  }
   *out = c;
   return NBODY_OK;
 }
@@ -459,6 +588,11 @@ void nbody_destroy(nbody_ctx *ctx) {
   for (int i = 0; i < nbody_ctx::kSpans; ++i) {
     if (ctx->ev_a[i]) (void)hipEventDestroy(ctx->ev_a[i]);
     if (ctx->ev_b[i]) (void)hipEventDestroy(ctx->ev_b[i]);
+    if (ctx->ev_c[i]) (void)hipEventDestroy(ctx->ev_c[i]);
+  }
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->st);
+    (void)hipHostFree(ctx->aux);
   }
   delete ctx;
 }
@@ -479,6 +613,7 @@ nbody_status nbody_bind_workspace(nbody_ctx *ctx, void *dev_ptr, size_t bytes,
   if (((uintptr_t)dev_ptr & 255u) != 0) return NBODY_EINVAL;
   const Layout L = make_layout(ctx->p, n_max, ctx->num_cu);
   if (bytes < L.total) return NBODY_ENOMEM;
+  if (!carve_complete(carve(dev_ptr, L), dev_ptr)) return NBODY_ECORRUPT;
   ctx->ws = dev_ptr;
   ctx->ws_bytes = bytes;
   ctx->L = L;
@@ -487,6 +622,7 @@ nbody_status nbody_bind_workspace(nbody_ctx *ctx, void *dev_ptr, size_t bytes,
   ctx->have_tree = false;
   ctx->sticky = NBODY_OK;
   hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
+  launch_fill_u32(ctx->P.plast, 0u, n_max, ctx->st);
   return hip_status();
 }
 
@@ -519,14 +655,78 @@ nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *axo, const float *ayo,
   return do_calc(ctx, axo, ayo, azo, ax, ay, az);
 }
 
+namespace {
+
+// Block steps (level != NULL): see nbody.h and k_block.hip.
+nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
+  nbody_status s;
+  const int64_t n = st->n;
+  float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
+  float *tx = ctx->P.atmp, *ty = tx + n, *tz = tx + 2 * n;
+  const BlockCfg bc{st->dt, st->eta, ctx->p.eps, st->level_min, st->level_max};
+  DevScalars *sc = ctx->P.sc;
+  launch_blk_setup((long long)st->tick, sc, ctx->st);
+  if (!st->have_acc) {
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>(cdiv(n, 1024), 8192)),
+                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, x32);
+    if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+    if ((s = do_calc(ctx, nullptr, nullptr, nullptr, st->ax, st->ay, st->az)) != NBODY_OK)
+      return s;
+    if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
+      return s;
+    launch_blk_init(n, st->ax, st->ay, st->az, st->level, bc, sc, ctx->st);
+    st->have_acc = 1;
+    ctx->since_rebuild = 0;
+  } else {
+    launch_blk_scan(n, st->level, bc, sc, ctx->st);
+  }
+  for (int32_t k = 0; k < n_steps; ++k) {
+    bool rebuild = st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
+                                            : rebuild_due(ctx, 64);
+    if (ctx->n != n) rebuild = true;
+    launch_blk_begin(sc, ctx->st);
+    launch_blk_open_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay,
+                          st->az, st->level, st->dt, sc, x32, ctx->st);
+    if (rebuild) {
+      if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+      ctx->rebuilds++;
+      ctx->since_rebuild = 0;
+    } else {
+      if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
+    }
+    launch_blk_queue(n, st->level, ctx->perm, ctx->P, ctx->st);
+    if ((s = do_calc(ctx, st->ax, st->ay, st->az, tx, ty, tz, true)) != NBODY_OK) return s;
+    launch_blk_close(n, st->ax, st->ay, st->az, tx, ty, tz, st->vx, st->vy, st->vz,
+                     st->level, bc, sc, ctx->st);
+    ctx->since_rebuild++;
+    ctx->steps++;
+    if ((s = hip_status()) != NBODY_OK) return s;
+  }
+  long long tick = 0;
+  if (hipMemcpyAsync(&tick, &sc->tick, sizeof(tick), hipMemcpyDeviceToHost, ctx->st) !=
+          hipSuccess ||
+      hipStreamSynchronize(ctx->st) != hipSuccess)
+    return NBODY_EHIP;
+  st->t += (double)(tick - st->tick) * (st->dt / (double)(1 << kTickBits));
+  st->tick = tick;
+  return NBODY_OK;
+}
+
+}  // namespace
+
 nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   nbody_status s = pre(ctx);
   if (s != NBODY_OK) return s;
   if (!st || n_steps < 0 || st->n < 1 || !st->x || !st->y || !st->z || !st->vx || !st->vy ||
       !st->vz || !st->m || !st->ax || !st->ay || !st->az || !(st->dt > 0.0) ||
-      st->rebuild_interval < 0)
+      !isfinite(st->dt) || st->rebuild_interval < 0)
+    return NBODY_EINVAL;
+  if (st->level &&
+      (!(st->eta > 0.0) || !isfinite(st->eta) || st->level_min < 0 ||
+       st->level_min > st->level_max || st->level_max > kTickBits || st->tick < 0))
     return NBODY_EINVAL;
   if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
+  if (st->level) return step_block(ctx, st, n_steps);
   const int64_t n = st->n;
   float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
   if (!st->have_acc) {
@@ -539,17 +739,11 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       return s;
     st->have_acc = 1;
     ctx->since_rebuild = 0;
-    ctx->walk_sum_ms = 0.0;
   }
   const float hdt = (float)(0.5 * st->dt);
   for (int32_t k = 0; k < n_steps; ++k) {
-    harvest(ctx, false);
-    bool rebuild;
-    if (st->rebuild_interval > 0)
-      rebuild = ctx->since_rebuild >= st->rebuild_interval;
-    else
-      rebuild = nbody_rebuild_decide(ctx->t_build_ms, ctx->walk_sum_ms, ctx->t_walk_ms,
-                                     ctx->since_rebuild, 64) != 0;
+    bool rebuild = st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
+                                            : rebuild_due(ctx, 64);
     if (ctx->n != n) rebuild = true;
     launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
     launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32, ctx->st);
@@ -557,7 +751,6 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
-      ctx->walk_sum_ms = 0.0;
     } else {
       if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
     }
@@ -565,8 +758,6 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       return s;
     launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
     ctx->since_rebuild++;
-    // the controller uses the latest walk time that has been measured
-    ctx->walk_sum_ms += ctx->t_walk_ms;
     ctx->steps++;
     st->t += st->dt;
     if ((s = hip_status()) != NBODY_OK) return s;
@@ -603,6 +794,7 @@ nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable) {
   harvest(ctx, false);
   ctx->walk_ms_sum = ctx->build_ms_sum = 0.0;
   ctx->walk_calls = ctx->build_calls = 0;
+  ctx->queued_sum = ctx->ngroup_sum = 0;
   ctx->counting = enable != 0;
   hipLaunchKernelGGL(k_acc_zero, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
   return hip_status();
@@ -625,7 +817,7 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
   if (!ctx->have_tree) return NBODY_OK;
   hipLaunchKernelGGL(k_stats_zero, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
   hipLaunchKernelGGL(k_stats, dim3(256), dim3(256), 0, ctx->st, ctx->P.sc, ctx->P.gent,
-                     ctx->P.gcount);
+                     ctx->P.gcount, ctx->last_queued ? ctx->P.order : nullptr);
   DevScalars h;
   if ((s = read_scalars(ctx, &h)) != NBODY_OK) return s;
   out->ncell = h.ncell;
@@ -634,6 +826,11 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
   out->interactions = (int64_t)h.inter_total;
   out->entries_sum = (int64_t)h.entries_acc;
   out->interactions_sum = (int64_t)h.inter_acc;
+  out->queued = ctx->last_queued ? (int64_t)h.nqueue : (int64_t)h.ngroup;
+  out->active = (int64_t)h.nactive;
+  out->queued_sum = ctx->queued_sum;
+  out->retried = (int64_t)h.nretry;
+  out->ngroup_sum = ctx->ngroup_sum;
   return NBODY_OK;
 }
 
@@ -668,6 +865,13 @@ nbody_status nbody_export(nbody_ctx *ctx, int32_t what, void *dst, int64_t capac
     case NBODY_X_GHASH: src = P.ghash; count = ng; esz = 8; break;
     case NBODY_X_XYZM: src = P.xyzm; count = 4 * n; break;
     case NBODY_X_BOX: src = P.sc->box; count = 4; esz = 8; break;
+    case NBODY_X_QUEUE:
+      src = P.order;
+      count = ctx->last_queued ? (int64_t)h.nqueue : 0;
+      break;
+    case NBODY_X_FEAT: src = P.feat; count = 4 * ng; break;
+    case NBODY_X_TARGET: src = P.target; count = ng; break;
+    case NBODY_X_PRED: src = P.pred; count = ng; break;
     default: return NBODY_EINVAL;
   }
   if (capacity < count) return NBODY_ENOMEM;
@@ -681,6 +885,96 @@ nbody_status nbody_export(nbody_ctx *ctx, int32_t what, void *dst, int64_t capac
   if (count > 0 && hipMemcpyAsync(dst, src, (size_t)count * esz, hipMemcpyDeviceToDevice,
                                   ctx->st) != hipSuccess)
     return NBODY_EHIP;
+  return NBODY_OK;
+}
+
+
+int64_t nbody_mlp_nparams(int32_t hidden) {
+  return mlp_hidden_ok(hidden) ? mlp_nparams(hidden) : -1;
+}
+
+nbody_status nbody_mlp_forward(nbody_ctx *ctx, int32_t hidden, const float *w, int64_t rows,
+                               const float *feat, float *y) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!mlp_hidden_ok(hidden) || !w || !feat || !y || rows < 0 ||
+      ((uintptr_t)feat & 15u) != 0)
+    return NBODY_EINVAL;
+  if (rows == 0) return NBODY_OK;
+  launch_mlp_forward(hidden, w, rows, nullptr, reinterpret_cast<const float4 *>(feat), y,
+                     ctx->st);
+  return hip_status();
+}
+
+nbody_status nbody_mlp_grad(nbody_ctx *ctx, int32_t hidden, const float *w, int64_t rows,
+                            const float *feat, const float *target, float *grad_loss) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!mlp_hidden_ok(hidden) || !w || !feat || !target || !grad_loss || rows < 1 ||
+      ((uintptr_t)feat & 15u) != 0)
+    return NBODY_EINVAL;
+  launch_mlp_grad(hidden, w, rows, reinterpret_cast<const float4 *>(feat), target,
+                  ctx->P.mlppart, grad_loss, ctx->st);
+  return hip_status();
+}
+
+nbody_status nbody_mlp_adam(nbody_ctx *ctx, int64_t n_params, float *w, const float *grad,
+                            float *m, float *v, int32_t step, float lr, float beta1,
+                            float beta2, float eps) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!w || !grad || !m || !v || n_params < 1 || step < 1 || !(lr > 0.0f) ||
+      !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return NBODY_EINVAL;
+  launch_adam(n_params, w, grad, m, v, step, lr, beta1, beta2, eps, ctx->st);
+  return hip_status();
+}
+
+nbody_status nbody_costmodel_train(nbody_ctx *ctx, int32_t hidden, float *w, int64_t rows,
+                                   const float *feat, const float *target, int32_t steps,
+                                   float lr, float *loss_out) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!mlp_hidden_ok(hidden) || !w || !feat || !target || rows < 1 || steps < 1 ||
+      !(lr > 0.0f) || ((uintptr_t)feat & 15u) != 0)
+    return NBODY_EINVAL;
+  const Ptrs &P = ctx->P;
+  const int64_t np = mlp_nparams(hidden);
+  launch_fill_u32(reinterpret_cast<uint32_t *>(P.mlpm), 0u, np, ctx->st);  // +0.0f
+  launch_fill_u32(reinterpret_cast<uint32_t *>(P.mlpv), 0u, np, ctx->st);
+  for (int32_t t = 1; t <= steps; ++t) {
+    launch_mlp_grad(hidden, w, rows, reinterpret_cast<const float4 *>(feat), target,
+                    P.mlppart, P.mlpg, ctx->st);
+    if (loss_out &&
+        hipMemcpyAsync(&loss_out[t - 1], &P.mlpg[np], sizeof(float), hipMemcpyDeviceToHost,
+                       ctx->st) != hipSuccess)
+      return NBODY_EHIP;
+    launch_adam(np, w, P.mlpg, P.mlpm, P.mlpv, t, lr, 0.9f, 0.999f, 1e-8f, ctx->st);
+  }
+  if ((s = hip_status()) != NBODY_OK) return s;
+  if (hipStreamSynchronize(ctx->st) != hipSuccess) return NBODY_EHIP;
+  return NBODY_OK;
+}
+
+nbody_status nbody_set_cost_model(nbody_ctx *ctx, int32_t hidden, const float *w) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!w) {
+    ctx->mlp_hidden = 0;
+    return NBODY_OK;
+  }
+  if (!mlp_hidden_ok(hidden)) return NBODY_EINVAL;
+  if (hipMemcpyAsync(ctx->P.mlpw, w, sizeof(float) * (size_t)mlp_nparams(hidden),
+                     hipMemcpyDeviceToDevice, ctx->st) != hipSuccess)
+    return NBODY_EHIP;
+  ctx->mlp_hidden = hidden;
+  return NBODY_OK;
+}
+
+nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order) {
+  if (!ctx) return NBODY_EINVAL;
+  if (order < 0 || order > 2) return NBODY_EINVAL;
+  ctx->order = order;
   return NBODY_OK;
 }
 

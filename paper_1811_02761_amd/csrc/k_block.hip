@@ -1,0 +1,329 @@
+// k_block.hip -- individual (block) time steps with kick-drift-kick leapfrog.
+//
+// The paper integrates with block time steps (Sec. 1 and 4.1): particle i
+// advances with dt_i = dt_max 2^-k_i, so its step boundaries are the
+// multiples of 2^(10 - k_i) ticks (a tick is dt_max 2^-10). One call of the
+// step loop moves the system time from tick0 to the next boundary of the
+// finest occupied level:
+//   opening half kick v += a dt_i/2 for the particles with a boundary at
+//   tick0; drift x += v (tick - tick0) dt_tick of every particle (FP64);
+//   forces for the groups holding a particle with a boundary at tick;
+//   closing half kick of those particles with their old step, then a new
+//   level: the smallest k (not below the alignment of the current tick) with
+//   dt_k <= sqrt(2 eta eps / |a|), tested as dt_k^4 |a|^2 <= (2 eta eps)^2 in
+//   FP64 (the criterion of Springel 2005, GADGET-2).
+// With every particle on one level this is plain kick-drift-kick leapfrog
+// operation for operation (the same FP32 kicks and FP64 drift as k_kick and
+// k_drift).
+#include "nbody_internal.h"
+
+namespace nb {
+
+constexpr int kBlkThreads = 256;
+constexpr int kBlkMaxBlocks = 1024;
+
+struct BlkTables {
+  float hdt[kTickBits + 1];    // (float)(dt_k / 2)
+  double lim4[kTickBits + 1];  // dt_k^4 computed as (dt_k * dt_k)^2
+  double rhs;                  // (2 eta eps)^2
+  double dt_tick;              // dt_max 2^-10
+  int level_min, level_max;
+};
+
+BlkTables make_tables(const BlockCfg &c) {
+  BlkTables t;
+  for (int k = 0; k <= kTickBits; ++k) {
+    const double dk = c.dt_max / (double)(1 << k);
+    t.hdt[k] = (float)(0.5 * dk);
+    const double d2 = dk * dk;
+    t.lim4[k] = d2 * d2;
+  }
+  const double cc = 2.0 * c.eta * (double)c.eps;
+  t.rhs = cc * cc;
+  t.dt_tick = c.dt_max / (double)(1 << kTickBits);
+  t.level_min = c.level_min;
+  t.level_max = c.level_max;
+  return t;
+}
+
+__device__ __forceinline__ int align_level(long long tick) {
+  const unsigned long long t = (unsigned long long)tick & ((1ull << kTickBits) - 1);
+  return t == 0 ? 0 : kTickBits - __builtin_ctzll(t);
+}
+
+// levels outside [0, 10] are reported by k_blk_scan; clamp for safe indexing
+__device__ __forceinline__ int clamp_level(int k) { return min(max(k, 0), kTickBits); }
+
+__device__ __forceinline__ bool on_boundary(long long tick, int k) {
+  return (tick & ((1ll << (kTickBits - k)) - 1)) == 0;
+}
+
+__device__ int level_of(float ax, float ay, float az, const BlkTables &t, int lo) {
+  const double x = ax, y = ay, z = az;
+  const double xx = x * x, yy = y * y, zz = z * z;  // exact
+  const double a2 = (xx + yy) + zz;
+  for (int k = lo; k < t.level_max; ++k)
+    if (t.lim4[k] * a2 <= t.rhs) return k;
+  return t.level_max;
+}
+
+// Block-wide max and sum, then one atomic each per block.
+__device__ void block_fold(int kmax, uint32_t cnt, DevScalars *sc, bool with_count) {
+  __shared__ int s_max[kBlkThreads / 64];
+  __shared__ uint32_t s_cnt[kBlkThreads / 64];
+  for (int d = 32; d >= 1; d >>= 1) {
+    kmax = max(kmax, __shfl_xor(kmax, d, 64));
+    cnt += __shfl_xor(cnt, d, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    s_max[w] = kmax;
+    s_cnt[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = 0;
+    uint32_t c = 0;
+    for (int q = 0; q < kBlkThreads / 64; ++q) {
+      m = max(m, s_max[q]);
+      c += s_cnt[q];
+    }
+    atomicMax(&sc->kmax_next, (uint32_t)m);
+    if (with_count) atomicAdd(&sc->nactive, c);
+  }
+}
+
+__global__ void k_blk_setup(long long tick, DevScalars *sc) {
+  if (threadIdx.x != 0) return;
+  sc->tick = tick;
+  sc->tick0 = tick;
+  sc->kmax = 0;
+  sc->kmax_next = 0;
+  sc->nactive = 0;
+  sc->nqueue = 0;
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_init(int64_t n, const float *__restrict__ ax,
+                                                          const float *__restrict__ ay,
+                                                          const float *__restrict__ az,
+                                                          int8_t *__restrict__ level,
+                                                          BlkTables t, DevScalars *sc) {
+  const int lo = max(t.level_min, align_level(sc->tick));
+  int kmax = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = level_of(ax[i], ay[i], az[i], t, lo);
+    level[i] = (int8_t)k;
+    kmax = max(kmax, k);
+  }
+  block_fold(kmax, 0u, sc, false);
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_scan(int64_t n,
+                                                          const int8_t *__restrict__ level,
+                                                          int level_min, int level_max,
+                                                          DevScalars *sc) {
+  int kmax = 0;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = level[i];
+    bad |= k < level_min || k > level_max;
+    kmax = max(kmax, k);
+  }
+  if (bad) atomicOr(&sc->status, kStCorrupt);
+  block_fold(min(kmax, kTickBits), 0u, sc, false);
+}
+
+__global__ void k_blk_begin(DevScalars *sc) {
+  if (threadIdx.x != 0) return;
+  const long long t0 = sc->tick;
+  const uint32_t k = sc->kmax_next;
+  const long long s = 1ll << (kTickBits - (int)k);
+  sc->tick0 = t0;
+  sc->tick = (t0 / s + 1) * s;
+  sc->kmax = k;
+  sc->kmax_next = 0;
+  sc->nactive = 0;
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_open_drift(
+    int64_t n, double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+    float *__restrict__ vx, float *__restrict__ vy, float *__restrict__ vz,
+    const float *__restrict__ ax, const float *__restrict__ ay, const float *__restrict__ az,
+    const int8_t *__restrict__ level, BlkTables t, const DevScalars *__restrict__ sc,
+    float *__restrict__ x32) {
+  const long long t0 = sc->tick0, t1 = sc->tick;
+  const double dt = (double)(t1 - t0) * t.dt_tick;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = clamp_level(level[i]);
+    float ux = vx[i], uy = vy[i], uz = vz[i];
+    if (on_boundary(t0, k)) {
+      const float h = t.hdt[k];
+      const float kx = ax[i] * h, ky = ay[i] * h, kz = az[i] * h;
+      ux = ux + kx;
+      uy = uy + ky;
+      uz = uz + kz;
+      vx[i] = ux;
+      vy[i] = uy;
+      vz[i] = uz;
+    }
+    const double dx = (double)ux * dt, dy = (double)uy * dt, dz = (double)uz * dt;
+    const double nx = x[i] + dx, ny = y[i] + dy, nz = z[i] + dz;
+    x[i] = nx;
+    y[i] = ny;
+    z[i] = nz;
+    x32[i] = (float)nx;
+    x32[n + i] = (float)ny;
+    x32[2 * n + i] = (float)nz;
+  }
+}
+
+__device__ __forceinline__ bool group_active(uint32_t g, uint32_t ng,
+                                             const uint32_t *__restrict__ gbegin,
+                                             const uint32_t *__restrict__ gcount,
+                                             const uint32_t *__restrict__ perm,
+                                             const int8_t *__restrict__ level, long long tick) {
+  if (g >= ng) return false;
+  const uint32_t b = gbegin[g], c = gcount[g];
+  bool act = false;
+  for (uint32_t j = 0; j < c && !act; ++j)
+    act = on_boundary(tick, clamp_level(level[perm[b + j]]));
+  return act;
+}
+
+// Active groups per block of kBlkThreads groups.
+__global__ __launch_bounds__(kBlkThreads) void k_blk_qcount(
+    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
+    const uint32_t *__restrict__ gcount, const uint32_t *__restrict__ perm,
+    const int8_t *__restrict__ level, uint32_t *__restrict__ blk) {
+  __shared__ uint32_t wc[kBlkThreads / 64];
+  const uint32_t g = blockIdx.x * kBlkThreads + threadIdx.x;
+  const bool act = group_active(g, sc->ngroup, gbegin, gcount, perm, level, sc->tick);
+  const uint64_t b = __ballot(act);
+  if (lane_id() == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int q = 0; q < kBlkThreads / 64; ++q) s += wc[q];
+    blk[blockIdx.x] = s;
+  }
+}
+
+// Active groups in group order (blk holds exclusive block offsets).
+__global__ __launch_bounds__(kBlkThreads) void k_blk_qemit(
+    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
+    const uint32_t *__restrict__ gcount, const uint32_t *__restrict__ perm,
+    const int8_t *__restrict__ level, const uint32_t *__restrict__ blk,
+    uint32_t *__restrict__ order) {
+  __shared__ uint32_t wc[kBlkThreads / 64];
+  const uint32_t g = blockIdx.x * kBlkThreads + threadIdx.x;
+  const bool act = group_active(g, sc->ngroup, gbegin, gcount, perm, level, sc->tick);
+  const uint64_t b = __ballot(act);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) wc[w] = (uint32_t)__popcll(b);
+  __syncthreads();
+  uint32_t off = blk[blockIdx.x];
+  for (int q = 0; q < w; ++q) off += wc[q];
+  if (act) order[off + (uint32_t)__popcll(b & lanemask_lt())] = g;
+}
+
+__global__ void k_blk_qtotal(const uint32_t *__restrict__ total, DevScalars *sc) {
+  if (threadIdx.x == 0) sc->nqueue = total[0];
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_close(
+    int64_t n, float *__restrict__ ax, float *__restrict__ ay, float *__restrict__ az,
+    const float *__restrict__ nax, const float *__restrict__ nay,
+    const float *__restrict__ naz, float *__restrict__ vx, float *__restrict__ vy,
+    float *__restrict__ vz, int8_t *__restrict__ level, BlkTables t, DevScalars *sc) {
+  const long long t1 = sc->tick;
+  const int lo = max(t.level_min, align_level(t1));
+  int kmax = 0;
+  uint32_t cnt = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int k = clamp_level(level[i]);
+    if (on_boundary(t1, k)) {
+      const float a0 = nax[i], a1 = nay[i], a2 = naz[i];
+      ax[i] = a0;
+      ay[i] = a1;
+      az[i] = a2;
+      const float h = t.hdt[k];
+      const float kx = a0 * h, ky = a1 * h, kz = a2 * h;
+      vx[i] = vx[i] + kx;
+      vy[i] = vy[i] + ky;
+      vz[i] = vz[i] + kz;
+      k = level_of(a0, a1, a2, t, lo);
+      level[i] = (int8_t)k;
+      ++cnt;
+    }
+    kmax = max(kmax, k);
+  }
+  block_fold(kmax, cnt, sc, true);
+}
+
+namespace {
+unsigned blk_grid(int64_t n) {
+  int64_t g = cdiv(n, kBlkThreads);
+  if (g > kBlkMaxBlocks) g = kBlkMaxBlocks;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+}  // namespace
+
+void launch_blk_setup(long long tick, DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_blk_setup, dim3(1), dim3(64), 0, st, tick, sc);
+}
+
+void launch_blk_init(int64_t n, const float *ax, const float *ay, const float *az,
+                     int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_blk_init, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, ax, ay, az,
+                     level, make_tables(c), sc);
+}
+
+void launch_blk_scan(int64_t n, const int8_t *level, const BlockCfg &c, DevScalars *sc,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_blk_scan, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, level,
+                     c.level_min, c.level_max, sc);
+}
+
+void launch_blk_begin(DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_blk_begin, dim3(1), dim3(64), 0, st, sc);
+}
+
+void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx, float *vy,
+                           float *vz, const float *ax, const float *ay, const float *az,
+                           const int8_t *level, double dt_max, const DevScalars *sc,
+                           float *x32, hipStream_t st) {
+  BlockCfg c{dt_max, 1.0, 1.0f, 0, kTickBits};
+  int64_t g = cdiv(n, 4 * kBlkThreads);  // a few particles per thread
+  if (g > 16384) g = 16384;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_blk_open_drift, dim3((unsigned)g), dim3(kBlkThreads), 0, st, n, x, y,
+                     z, vx, vy, vz, ax, ay, az, level, make_tables(c), sc, x32);
+}
+
+void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, const Ptrs &P,
+                      hipStream_t st) {
+  // ngroup <= n: one thread per possible group; the build's block-count
+  // buffer (free outside the build) holds the per-block counts and the total
+  const uint32_t nblk = (uint32_t)cdiv(n, kBlkThreads);
+  uint32_t *blk = P.blkcnt, *total = P.blkcnt + nblk;
+  hipLaunchKernelGGL(k_blk_qcount, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gbegin,
+                     P.gcount, perm, level, blk);
+  launch_scan_rows(blk, nblk, 1, total, st);
+  hipLaunchKernelGGL(k_blk_qemit, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gbegin,
+                     P.gcount, perm, level, blk, P.order);
+  hipLaunchKernelGGL(k_blk_qtotal, dim3(1), dim3(64), 0, st, total, P.sc);
+}
+
+void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
+                      const float *nay, const float *naz, float *vx, float *vy, float *vz,
+                      int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_blk_close, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, ax, ay, az,
+                     nax, nay, naz, vx, vy, vz, level, make_tables(c), sc);
+}
+
+}  // namespace nb

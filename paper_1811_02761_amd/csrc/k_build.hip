@@ -396,4 +396,9 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   hipLaunchKernelGGL(k_group_size, dim3(ge), dim3(256), 0, st, P.sc, P.gbegin, P.gcount);
 }
 
+void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_rows, dim3(nrows), dim3(256), 0, st, rows, len, totals);
+}
+
 }  // namespace nb

@@ -155,6 +155,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   }
 }
 
+void launch_digit_sort(int64_t n, int shift, const uint64_t *kin, const uint32_t *vin,
+                       uint64_t *kout, uint32_t *vout, uint32_t *hist, hipStream_t st) {
+  const int64_t nblk = cdiv(n, kSortTile);
+  uint32_t *totals = hist + (int64_t)kSortRadix * nblk;
+  hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortThreads), 0, st, kin, n, shift, hist,
+                     nblk);
+  hipLaunchKernelGGL(k_sort_scan, dim3(kSortRadix), dim3(kSortThreads), 0, st, hist, nblk,
+                     totals);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortThreads), 0, st, kin, vin, n, shift,
+                     hist, nblk, totals, kout, vout);
+}
+
 void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
                  uint32_t *valsB, uint32_t *hist, int64_t blocks, hipStream_t st,
                  uint64_t **keys_out, uint32_t **vals_out) {

@@ -73,7 +73,10 @@ struct WalkArgs {
   const uint32_t *gcount;
   const float4 *gbox;
   const uint32_t *perm;
-  const uint32_t *order;
+  const uint32_t *order;   // queue -> group (nullptr: identity)
+  const uint32_t *qcount;  // queue length (device)
+  uint32_t *retry;         // overflowing groups go here (nullptr: report instead)
+  uint32_t *nretry;
   uint32_t *frontier;
   uint32_t *gent;
   unsigned long long *ghash;
@@ -129,21 +132,45 @@ struct Acc3<true> {
   }
 };
 
+// Entries of zero mass pad a flushed tile to a multiple of S * kFlushUnroll,
+// so every lane runs the same trip count and the loads of one trip are
+// issued together. A padding entry adds exactly +0 to each sum (r^2 >= eps^2
+// keeps it finite), and each lane still adds its entries in list order.
+constexpr uint32_t kFlushUnroll = 4;
+constexpr uint32_t kListPad = 8 * kFlushUnroll;  // largest S times the unroll
+
+__device__ __forceinline__ void eq1_term(const float4 e, float4 pi, float eps2, float &dx,
+                                         float &dy, float &dz, float &f) {
+  dx = e.x - pi.x;
+  dy = e.y - pi.y;
+  dz = e.z - pi.z;
+  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float mr = e.w * rinv;
+  const float rinv2 = rinv * rinv;
+  f = mr * rinv2;
+}
+
 template <bool kComp>
-__device__ __forceinline__ void flush_tile(const float4 *__restrict__ list, uint32_t cnt,
-                                           uint32_t stream, uint32_t S, float4 pi,
-                                           float eps2, Acc3<kComp> &acc) {
-#pragma unroll 4
-  for (uint32_t j = stream; j < cnt; j += S) {
-    const float4 e = list[j];
-    const float dx = e.x - pi.x;
-    const float dy = e.y - pi.y;
-    const float dz = e.z - pi.z;
-    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-    const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float mr = e.w * rinv;
-    const float rinv2 = rinv * rinv;
-    acc.add(dx, dy, dz, mr * rinv2);
+__device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t cnt,
+                                           uint32_t lane, uint32_t stream, uint32_t S,
+                                           float4 pi, float eps2, Acc3<kComp> &acc) {
+  const uint32_t step = S * kFlushUnroll;
+  const uint32_t padded = (cnt + step - 1) / step * step;
+  // every lane stores (two lanes per slot, same value): no lane-predicated
+  // region; slots [cnt, cnt + kListPad) are free
+  list[cnt + (lane & (kListPad - 1))] = make_float4(0.f, 0.f, 0.f, 0.f);
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t j0 = stream; j0 < padded; j0 += step) {
+    float4 e[kFlushUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kFlushUnroll; ++u) e[u] = list[j0 + u * S];
+#pragma unroll
+    for (uint32_t u = 0; u < kFlushUnroll; ++u) {
+      float dx, dy, dz, f;
+      eq1_term(e[u], pi, eps2, dx, dy, dz, f);
+      acc.add(dx, dy, dz, f);
+    }
   }
 }
 
@@ -153,15 +180,16 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
   const uint32_t wv = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   // LDS: per wave a list tile, then per wave the chunk's owner table
-  float4 *list = lds_list + wv * a.tile;
-  float4 *s_ent = lds_list + kWalkWavesPerWG * a.tile + wv * 64;
+  const uint32_t TS = a.tile + kListPad;  // tile + padding slots
+  float4 *list = lds_list + wv * TS;
+  float4 *s_ent = lds_list + kWalkWavesPerWG * TS + wv * 64;
   uint32_t *s_incl =
-      reinterpret_cast<uint32_t *>(lds_list + kWalkWavesPerWG * (a.tile + 64)) + wv * 128;
+      reinterpret_cast<uint32_t *>(lds_list + kWalkWavesPerWG * (TS + 64)) + wv * 128;
   uint32_t *s_src = s_incl + 64;
   uint32_t *ring =
       a.frontier + (size_t)(blockIdx.x * kWalkWavesPerWG + wv) * (size_t)(a.fmask + 1);
   const uint32_t F = a.fmask + 1;
-  const uint32_t ng = a.sc->ngroup;
+  const uint32_t ng = *a.qcount;
   const uint32_t ncell = a.sc->ncell;
   const uint32_t npart = a.n;
   // No lane-predicated region may sit in this loop: the compiler threads such
@@ -276,7 +304,7 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
         done += take;
         if (cnt == a.tile) {
           __builtin_amdgcn_wave_barrier();
-          flush_tile<kComp>(list, cnt, stream, S, pi, a.eps2, acc);
+          flush_tile<kComp>(list, cnt, lane, stream, S, pi, a.eps2, acc);
           __builtin_amdgcn_wave_barrier();
           cnt = 0;
         }
@@ -286,12 +314,19 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (overflow || corrupt) {
+    // overflow and corrupt are wave-uniform: these branches are not
+    // lane-predicated; every lane joins the atomics and stores
+    const bool handoff = overflow && !corrupt && a.retry != nullptr;
+    if (handoff) {
+      const uint32_t slot = __builtin_amdgcn_readfirstlane(
+          atomicAdd(a.nretry, lane == 0 ? 1u : 0u));
+      a.retry[slot] = g;
+    } else if (overflow || corrupt) {
       atomicOr(&a.sc->status, overflow ? kStOverflow : kStCorrupt);
-      cnt = 0;
     }
+    if (overflow || corrupt) cnt = 0;
     __builtin_amdgcn_wave_barrier();
-    flush_tile<kComp>(list, cnt, stream, S, pi, a.eps2, acc);
+    flush_tile<kComp>(list, cnt, lane, stream, S, pi, a.eps2, acc);
     __builtin_amdgcn_wave_barrier();
     float sx, sy, sz;
     acc.total(sx, sy, sz);
@@ -321,6 +356,50 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
   }
 }
 
+// One workgroup: interactions of the walked groups now and on their first
+// walk of this tree (recorded here), summed in a fixed order.
+__global__ __launch_bounds__(1024) void k_walk_stat(DevScalars *__restrict__ sc,
+                                                    const uint32_t *__restrict__ order,
+                                                    const uint32_t *__restrict__ gcount,
+                                                    const uint32_t *__restrict__ gent,
+                                                    uint32_t *__restrict__ gref) {
+  __shared__ unsigned long long s_cur[16], s_ref[16];
+  const uint32_t nq = order ? sc->nqueue : sc->ngroup;
+  unsigned long long cur = 0, ref = 0;
+  for (uint32_t q = threadIdx.x; q < nq; q += blockDim.x) {
+    const uint32_t g = order ? order[q] : q;
+    const uint32_t e = gent[g], c = gcount[g];
+    if (e == 0xffffffffu) continue;
+    uint32_t r = gref[g];
+    if (r == 0) {
+      r = e;
+      gref[g] = e;
+    }
+    cur += (unsigned long long)e * c;
+    ref += (unsigned long long)r * c;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    cur += __shfl_xor(cur, d, 64);
+    ref += __shfl_xor(ref, d, 64);
+  }
+  if (lane_id() == 0) {
+    s_cur[threadIdx.x >> 6] = cur;
+    s_ref[threadIdx.x >> 6] = ref;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += s_cur[w];
+      b += s_ref[w];
+    }
+    sc->wstat.ngroup = sc->ngroup;
+    sc->wstat.queued = nq;
+    sc->wstat.inter = a;
+    sc->wstat.inter_ref = b;
+  }
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -332,6 +411,11 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
   if (g > 1024) g = 1024;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, v, n);
+}
+
+void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st) {
+  hipLaunchKernelGGL(k_walk_stat, dim3(1), dim3(1024), 0, st, P.sc, queued ? P.order : nullptr,
+                     P.gcount, P.gent, P.gref);
 }
 
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
@@ -346,7 +430,6 @@ void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
 
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, float *ay,
                  float *az, const Ptrs &P, hipStream_t st) {
-  (void)n;
   WalkArgs a;
   a.nodeA = P.nodeA;
   a.nodeB = P.nodeB;
@@ -356,6 +439,9 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   a.gbox = P.gbox;
   a.perm = perm;
   a.order = c.use_order ? P.order : nullptr;
+  a.qcount = c.use_order ? &P.sc->nqueue : &P.sc->ngroup;
+  a.retry = P.retry;
+  a.nretry = &P.sc->nretry;
   a.frontier = P.frontier;
   a.gent = P.gent;
   a.ghash = P.ghash;
@@ -370,20 +456,38 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   a.fmask = (uint32_t)c.frontier_cap - 1u;
   a.bootstrap = c.bootstrap;
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
-  // per wave: list tile (16 B/entry) + owner table (64 x (16 + 4 + 4) B)
-  const size_t lds = (size_t)kWalkWavesPerWG * (c.list_tile * sizeof(float4) + 64 * 24);
-  const dim3 grid(blocks), block(64 * kWalkWavesPerWG);
-  if (c.compensated) {
-    if (c.hash)
-      hipLaunchKernelGGL((k_walk<true, true>), grid, block, lds, st, a);
-    else
-      hipLaunchKernelGGL((k_walk<true, false>), grid, block, lds, st, a);
-  } else {
-    if (c.hash)
-      hipLaunchKernelGGL((k_walk<false, true>), grid, block, lds, st, a);
-    else
-      hipLaunchKernelGGL((k_walk<false, false>), grid, block, lds, st, a);
-  }
+  // per wave: list tile + padding (16 B/entry) + owner table (64 x (16 + 4 + 4) B)
+  const size_t lds =
+      (size_t)kWalkWavesPerWG * ((c.list_tile + kListPad) * sizeof(float4) + 64 * 24);
+  auto launch = [&](const WalkArgs &w, dim3 grid) {
+    const dim3 block(64 * kWalkWavesPerWG);
+    if (c.compensated) {
+      if (c.hash)
+        hipLaunchKernelGGL((k_walk<true, true>), grid, block, lds, st, w);
+      else
+        hipLaunchKernelGGL((k_walk<true, false>), grid, block, lds, st, w);
+    } else {
+      if (c.hash)
+        hipLaunchKernelGGL((k_walk<false, true>), grid, block, lds, st, w);
+      else
+        hipLaunchKernelGGL((k_walk<false, false>), grid, block, lds, st, w);
+    }
+  };
+  launch_fill_u32(&P.sc->nretry, 0u, 1, st);
+  launch(a, dim3(blocks));
+  // retry pass: the overflowing groups, walked by a few wavefronts whose
+  // frontier holds the two widest levels of any tree; a second overflow is
+  // reported (it cannot happen: a breadth-first frontier never holds more
+  // than two levels of cells, and a level has at most n cells)
+  WalkArgs r = a;
+  r.order = P.retry;
+  r.qcount = &P.sc->nretry;
+  r.retry = nullptr;
+  r.frontier = P.frontier2;
+  r.fmask = (uint32_t)c.frontier2_cap - 1u;
+  launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
+  launch(r, dim3(c.retry_waves / kWalkWavesPerWG));
+  (void)n;
 }
 
 }  // namespace nb

@@ -25,6 +25,14 @@ constexpr int32_t kStOverflow = 2;
 constexpr int32_t kStCapacity = 4;
 constexpr int32_t kStCorrupt = 8;  // internal consistency check failed
 
+// Statistics of the last walk for the rebuild controller (copied to the host).
+struct WalkStat {
+  uint32_t ngroup, queued;
+  unsigned long long inter;      // interactions of the walked groups
+  unsigned long long inter_ref;  // the same groups' interactions on their first
+                                 // walk since the tree was built
+};
+
 // Device scalars kept in the workspace.
 struct DevScalars {
   uint32_t bbox[6];        // ordered-int min x,y,z then max x,y,z
@@ -38,7 +46,16 @@ struct DevScalars {
   unsigned long long inter_total;
   unsigned long long entries_acc;  // running totals while counting
   unsigned long long inter_acc;
-  uint32_t pad[8];
+  // individual block time steps (ticks of dt_max 2^-kTickBits)
+  long long tick;          // current time
+  long long tick0;         // start of the current step
+  uint32_t kmax;           // finest occupied level during the current step
+  uint32_t kmax_next;      // finest level after the closing kicks
+  uint32_t nqueue;         // groups in the walk queue (order[])
+  uint32_t nactive;        // particles active at the end of the current step
+  uint32_t nretry;         // groups handed from the walk to its retry pass
+  uint32_t pad[3];
+  WalkStat wstat;
 };
 
 // Offsets of the workspace, all 256-byte aligned.
@@ -53,7 +70,11 @@ struct Layout {
       off_xyzm, off_x32, off_pinfo, off_leafof, off_blkcnt, off_clevel,
       off_cpbegin, off_cpcount, off_cfchild, off_cnchild, off_cparent,
       off_mom64, off_nodeA, off_nodeB, off_gbegin, off_gcount, off_gbox,
-      off_gent, off_ghash, off_order, off_frontier, off_prevcnt;
+      off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
+      off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
+      off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref;
+  int64_t frontier2_cap = 0;  // retry pass: power of two >= 2 n
+  int retry_waves = 0;
   size_t total = 0;
 };
 
@@ -80,6 +101,20 @@ struct Ptrs {
   uint32_t *order;      // walk queue order
   uint32_t *frontier;   // per wave ring
   uint32_t *prevcnt;    // per group: entries of the previous walk (ordering)
+  float *atmp;          // [3][n] walk output of a block step (caller order)
+  uint32_t *retry;      // groups whose frontier outgrew the main pass
+  uint32_t *frontier2;  // retry pass frontier rings
+  // cost model of the walk queue
+  float4 *feat;         // per group: 4 features
+  float *target;        // per group: log2 interactions of its last walk
+  float *pred;          // per group: model prediction
+  uint32_t *plast;      // per particle (caller order): list length of its last walk
+  uint64_t *okeys;      // [2][n] queue sort keys
+  uint32_t *qtmp;       // queue sort values before the digit pass
+  float *mlpw;          // weights in use (largest model)
+  float *mlpm, *mlpv, *mlpg;  // Adam moments, gradient + loss (training)
+  float *mlppart;       // per-wavefront gradient shares
+  uint32_t *gref;       // per group: list length of its first walk on this tree (0: none)
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
@@ -111,8 +146,10 @@ struct WalkCfg {
   int frontier_cap;
   int waves_per_cu;
   int num_cu;
-  int use_order;
-  bool hash;  // record the per-group entry hash
+  int use_order;  // walk the groups order[0 .. nqueue) instead of all groups
+  bool hash;      // record the per-group entry hash
+  int64_t frontier2_cap;
+  int retry_waves;
 };
 // enqueue the walk kernel (the queue head must already be zero)
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
@@ -126,6 +163,66 @@ void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
                   const float *vy, const float *vz, double dt, float *x32,
                   hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+// exclusive scan of rows[r][0 .. len) for r < nrows, row totals to totals[r]
+void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
+                      hipStream_t st);
+
+// sc->wstat of the walk just finished (queued: order[0 .. nqueue), else all)
+void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st);
+
+// single 8-bit digit pass of the stable radix sort (digit = key >> shift)
+void launch_digit_sort(int64_t n, int shift, const uint64_t *kin, const uint32_t *vin,
+                       uint64_t *kout, uint32_t *vout, uint32_t *hist, hipStream_t st);
+
+// cost model of the walk queue
+constexpr int kMlpMaxHidden = 64;
+constexpr int kMlpMaxParams = 7 * kMlpMaxHidden + kMlpMaxHidden * kMlpMaxHidden + 1;
+constexpr int kMlpWaves = 256;  // wavefronts of the gradient kernel
+bool mlp_hidden_ok(int H);
+int64_t mlp_nparams(int H);
+void launch_mlp_forward(int H, const float *w, int64_t rows, const uint32_t *rows_dev,
+                        const float4 *feat, float *y, hipStream_t st);
+// grad_loss[0 .. np) = gradient of the mean squared error, grad_loss[np] = loss
+void launch_mlp_grad(int H, const float *w, int64_t rows, const float4 *feat,
+                     const float *target, float *partial, float *grad_loss, hipStream_t st);
+void launch_adam(int64_t np, float *w, const float *g, float *m, float *v, int step, float lr,
+                 float b1, float b2, float eps, hipStream_t st);
+void launch_cost_features(int64_t n, const uint32_t *perm, const Ptrs &P, hipStream_t st);
+void launch_cost_after(int64_t n, bool queued, const uint32_t *perm, const Ptrs &P,
+                       hipStream_t st);
+// order[0 .. nqueue) by predicted cost (mode 1: count and previous list
+// length, mode 2: the model); queued: sort the current queue, else all groups
+void launch_cost_order(int64_t n, bool queued, int mode, int H, const Ptrs &P,
+                       hipStream_t st);
+
+// individual block time steps
+constexpr int kTickBits = 10;  // finest level: dt_max 2^-10
+struct BlockCfg {
+  double dt_max;
+  double eta;
+  float eps;
+  int level_min, level_max;
+};
+void launch_blk_setup(long long tick, DevScalars *sc, hipStream_t st);
+// level of every particle from a (at the current tick); kmax_next = max level
+void launch_blk_init(int64_t n, const float *ax, const float *ay, const float *az,
+                     int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st);
+// kmax_next = max level; levels outside [level_min, level_max] set kStCorrupt
+void launch_blk_scan(int64_t n, const int8_t *level, const BlockCfg &c, DevScalars *sc,
+                     hipStream_t st);
+// next tick; opening kicks at tick0; drift of every particle to tick
+void launch_blk_begin(DevScalars *sc, hipStream_t st);
+void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx, float *vy,
+                           float *vz, const float *ax, const float *ay, const float *az,
+                           const int8_t *level, double dt_max, const DevScalars *sc,
+                           float *x32, hipStream_t st);
+// walk queue = the groups holding a particle active at tick (group order)
+void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, const Ptrs &P,
+                      hipStream_t st);
+// active particles: a = anew, closing kick, new level; kmax_next, nactive
+void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
+                      const float *nay, const float *naz, float *vx, float *vy, float *vz,
+                      int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st);
 void launch_order_by_count(int64_t n, const Ptrs &P, hipStream_t st);
 
 // ---- device helpers ----

@@ -73,26 +73,22 @@ def test_null_context_is_rejected(nb):
 
 def test_rebuild_rule_synthetic_sequences(nb):
     d = nb.rebuild_decide
-    # no steps since rebuild: never
-    assert not d(5.0, 0.0, 1.0, 0)
-    # cap on the interval
-    assert d(5.0, 10.0, 0.1, 64, 64)
-    # build 10 ms, walks 1.0, 1.1, 1.2 ...: average after k steps is
-    # (10 + sum)/k; rebuild when the latest walk reaches it
-    walks = [1.0 + 0.1 * k for k in range(100)]
-    s, decided = 0.0, None
-    for k in range(1, 100):
-        s += walks[k - 1]
-        if d(10.0, s, walks[k - 1], k):
-            decided = k
-            break
-    # closed form: smallest k with 1 + 0.1 (k-1) >= (10 + k + 0.05 k (k-1)) / k
-    # <=> 0.05 k^2 >= 10  <=> k >= 14.14
-    assert decided == 15
+    # no steps since rebuild: never; the cap on the interval
+    assert not d(5.0, 100.0, 0)
+    assert d(5.0, 0.0, 64, 64)
+    # walks of a fresh tree take 1 ms and every step on the same tree adds
+    # 0.1 ms: walk k (k = 0, 1, ...) has excess 0.1 k, so the cumulative excess
+    # after K steps is 0.05 K (K - 1); with a 10 ms build the rule fires at the
+    # smallest K with 0.05 K (K - 1) >= 10, K = 15 (the mean cost per step,
+    # 10 / K + 1 + 0.05 (K - 1), is smallest near K = sqrt(200) = 14.1)
+    def interval(t_build, slope):
+        ex = 0.0
+        for k in range(1, 200):
+            ex += slope * (k - 1)
+            if d(t_build, ex, k, 1000):
+                return k
+    assert interval(10.0, 0.1) == 15
+    mean = lambda K: 10.0 / K + 1 + 0.05 * (K - 1)  # noqa: E731
+    assert abs(mean(15) - min(mean(K) for K in range(1, 100))) < 0.01
     # a cheap build rebuilds early, an expensive one late
-    s = 0.0
-    for k in range(1, 100):
-        s += walks[k - 1]
-        if d(0.5, s, walks[k - 1], k):
-            break
-    assert k < 6
+    assert interval(0.5, 0.1) < 6 < 15 < interval(100.0, 0.1)

@@ -1,0 +1,177 @@
+"""GPU parity of the learned cost model through the C ABI: MLP inference,
+gradient and Adam against the FP64 oracle, training on the device, the
+per-group features and targets against the oracle's definitions, and forces
+bit-identical under the plain, size-based and learned queue orders."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import nbody_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def nb(torch):
+    import paper_1811_02761_amd as nb
+
+    nb.lib()
+    return nb
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.mark.parametrize("H", [8, 32, 64])
+def test_mlp_forward_grad_adam_match_oracle(nb, torch, orc, H):
+    ctx = nb.Context(nb.Params(), n_max=1024)
+    npar = nb.mlp_nparams(H)
+    assert npar == orc.mlp_nparams(H)
+    w = I.mlp_init(npar, orc.mlp_fan_in(H), 11)
+    rng = np.random.default_rng(H)
+    rows = 5000
+    f = rng.standard_normal((rows, 4)).astype(np.float32)
+    t = rng.standard_normal(rows).astype(np.float32)
+    W, F, T = _dev(torch, w), _dev(torch, f), _dev(torch, t)
+    y = ctx.mlp_forward(H, W, F).cpu().numpy()
+    yo = orc.mlp_forward(w.astype(np.float64), f.astype(np.float64), hidden=H)
+    assert np.abs(y - yo).max() <= 1e-5 * np.abs(yo).max(), np.abs(y - yo).max()
+    g, loss = ctx.mlp_grad(H, W, F, T)
+    lo, go = orc.mlp_grad(w.astype(np.float64), f.astype(np.float64), t.astype(np.float64),
+                          hidden=H)
+    g = g.cpu().numpy()
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max(), np.abs(g - go).max()
+    assert abs(float(loss) - lo) <= 1e-5 * lo
+    # one Adam step from the same gradient
+    m = torch.zeros(npar, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    G = _dev(torch, g)
+    ctx.mlp_adam(W, G, m, v, 1, 1e-2)
+    wo, _, _ = orc.adam_step(w.astype(np.float64), g.astype(np.float64), np.zeros(npar),
+                             np.zeros(npar), 1, 1e-2)
+    assert np.abs(W.cpu().numpy() - wo).max() <= 1e-6
+
+
+def test_training_on_device(nb, torch, orc):
+    H = 16
+    ctx = nb.Context(nb.Params(), n_max=1024)
+    npar = nb.mlp_nparams(H)
+    w0 = I.mlp_init(npar, orc.mlp_fan_in(H), 5)
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((16, 4)).astype(np.float32)
+    t = rng.standard_normal(16).astype(np.float32)
+    W = _dev(torch, w0)
+    losses = ctx.train_cost_model(H, W, _dev(torch, f), _dev(torch, t), 1500, 1e-2)
+    _say("16-row fit: loss %.3g -> %.3g" % (losses[0], losses[-1]))
+    assert losses[-1] < 1e-3 * losses[0]
+    # the first steps follow the FP64 oracle's trajectory
+    _, lo = orc.mlp_train(w0.astype(np.float64), f.astype(np.float64), t.astype(np.float64),
+                          hidden=H, steps=5, lr=1e-2)
+    np.testing.assert_allclose(losses[:5], lo, rtol=1e-4)
+
+
+def _walk(nb, torch, ctx, x, y, z, m, a_old):
+    X, Y, Z, M = (_dev(torch, a) for a in (x, y, z, m))
+    ctx.build_tree(X, Y, Z, M)
+    acc = ctx.calc_acc(tuple(_dev(torch, a_old[:, k]) for k in range(3)))
+    ctx.sync()
+    return np.stack([a.cpu().numpy() for a in acc], 1)
+
+
+def test_orders_bit_identical_features_and_targets(nb, torch, orc):
+    n = 30000
+    g = I.galaxy(n, 31)
+    x, y, z, _, _, _, m = g.f32()
+    params = nb.Params(checks=1)
+    ref0 = orc.tree_forces(x, y, z, m, a_old=None, group_merge=params.group_merge)
+    a_old = ref0.acc.astype(np.float32)
+    r = orc.tree_forces(x, y, z, m, a_old=a_old, group_merge=params.group_merge)
+    ctx = nb.Context(params, n_max=n)
+    plain = _walk(nb, torch, ctx, x, y, z, m, a_old)
+    ctx.set_order(1)
+    o1 = _walk(nb, torch, ctx, x, y, z, m, a_old)   # members learn their list length
+    o1b = _walk(nb, torch, ctx, x, y, z, m, a_old)  # features use it
+    feat = ctx.export(nb.X.FEAT).reshape(-1, 4)
+    target = ctx.export(nb.X.TARGET)
+    q = ctx.export(nb.X.QUEUE).cpu().numpy()
+    np.testing.assert_array_equal(np.sort(q), np.arange(r.grp.n))
+    sx, sy, sz, sm = x[r.perm], y[r.perm], z[r.perm], m[r.perm]
+    prev = np.zeros(n)
+    for gi in range(r.grp.n):
+        b, c = r.grp.begin[gi], r.grp.count[gi]
+        prev[b:b + c] = r.gentries[gi]
+    fo = orc.cost_features(r.grp, sx, sy, sz, sm, prev)
+    assert np.abs(feat.cpu().numpy() - fo).max() <= 1e-5
+    assert np.abs(target.cpu().numpy() - orc.cost_target(r.grp, r.gentries)).max() <= 1e-5
+    # train a model on these statistics and walk in its order
+    H = 32
+    W = _dev(torch, I.mlp_init(nb.mlp_nparams(H), orc.mlp_fan_in(H), 7))
+    losses = ctx.train_cost_model(H, W, feat.contiguous(), target.contiguous(), 300, 1e-2)
+    ctx.set_cost_model(H, W)
+    ctx.set_order(2)
+    o2 = _walk(nb, torch, ctx, x, y, z, m, a_old)
+    pred = ctx.export(nb.X.PRED).cpu().numpy()
+    for a in (o1, o1b, o2):
+        np.testing.assert_array_equal(a, plain)
+    # the model's misses against the measured counts, next to the size-based
+    # estimate (log2 count + log2(1 + previous list length))
+    t = target.cpu().numpy()
+    f = feat.cpu().numpy()
+    mae_model = np.abs(pred - t).mean()
+    mae_size = np.abs(f[:, 0] + f[:, 3] - t).mean()
+    _say("loss %.3g -> %.3g; mean |log2 miss|: model %.3f, size-based %.3f"
+         % (losses[0], losses[-1], mae_model, mae_size))
+    assert mae_model < mae_size
+
+
+def test_learned_order_timing_report(nb, torch, orc):
+    # what the learned order gains over the plain (Morton) queue: walk times
+    # of the same tree under both orders (reported), results bit-identical
+    n = 1 << 20
+    g = I.galaxy(n, 32)
+    x, y, z, _, _, _, m = g.f32()
+    ctx = nb.Context(nb.Params(), n_max=n)
+    X, Y, Z, M = (_dev(torch, a) for a in (x, y, z, m))
+    ctx.build_tree(X, Y, Z, M)
+    a0 = ctx.calc_acc(None)
+    a1 = ctx.calc_acc(a0)
+    ctx.set_order(1)
+    ctx.calc_acc(a1)
+    ctx.calc_acc(a1)
+    ctx.sync()
+    feat = ctx.export(nb.X.FEAT).reshape(-1, 4).contiguous()
+    target = ctx.export(nb.X.TARGET).contiguous()
+    H = 32
+    W = _dev(torch, I.mlp_init(nb.mlp_nparams(H), orc.mlp_fan_in(H), 9))
+    ctx.train_cost_model(H, W, feat, target, 300, 1e-2)
+    ctx.set_cost_model(H, W)
+    times, outs = {}, {}
+    for order in (0, 2, 0, 2):
+        ctx.set_order(order)
+        ctx.timing(True)
+        out = ctx.calc_acc(a1)
+        ctx.sync()
+        s = ctx.stats()
+        times.setdefault(order, []).append(s["walk_ms_sum"])
+        outs[order] = [t.cpu().numpy() for t in out]
+    for u, v in zip(outs[0], outs[2]):
+        np.testing.assert_array_equal(u, v)
+    _say("walk ms plain %s learned %s (ratio %.3f)"
+         % (times[0], times[2], min(times[0]) / min(times[2])))

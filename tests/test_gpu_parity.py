@@ -261,17 +261,27 @@ def test_nonfinite_input_is_reported(nb, torch):
         ctx.build_tree(Y, Y, Y, M)
 
 
-def test_frontier_overflow_is_reported(nb, torch):
+def test_frontier_overflow_is_walked_again(nb, torch, orc):
+    # delta_acc = 0 opens every cell: with a 64-cell frontier every group
+    # overflows and is walked again by the retry pass; results bit-identical
     g = I.galaxy(20000, 14)
     x, y, z, _, _, _, m = g.f32()
-    ctx = nb.Context(nb.Params(frontier_cap=64, delta_acc=0.0), n_max=20000)
-    X, Y, Z, M = (_dev(torch, a) for a in (x, y, z, m))
-    ctx.build_tree(X, Y, Z, M)
-    ones = torch.ones(20000, dtype=torch.float32, device="cuda")
-    ctx.calc_acc((ones, ones, ones))
-    with pytest.raises(nb.NbodyError) as ei:
-        ctx.sync()
-    assert ei.value.code == nb.NBODY_EOVERFLOW
+    a_old = np.ones((20000, 3), np.float32)
+    outs = []
+    for fc in (64, 0):
+        ctx, acc = _run(nb, torch, x, y, z, m, nb.Params(frontier_cap=fc, delta_acc=0.0),
+                        a_old=a_old)
+        st = ctx.stats()
+        _say("frontier %d: retried %d of %d groups" % (fc, st["retried"], st["ngroup"]))
+        if fc == 64:
+            assert st["retried"] == st["ngroup"]
+        else:
+            assert st["retried"] == 0
+        outs.append((acc, _np(ctx.export(nb.X.GENTRIES)), _np(ctx.export(nb.X.GHASH))))
+    for u, v in zip(*outs):
+        np.testing.assert_array_equal(u, v)
+    ref = _ref(orc, x, y, z, m, nb.Params(delta_acc=0.0), a_old)
+    np.testing.assert_array_equal(outs[0][1].astype(np.int64), ref.gentries)
 
 
 def test_calc_before_build_and_workspace_limits(nb, torch):
