@@ -70,7 +70,7 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
                               np.ascontiguousarray(mom.com[:, 1]),
                               np.ascontiguousarray(mom.com[:, 2]), mom.b2, mom.q, g.n,
                               g.begin, g.count, np.ascontiguousarray(lo.reshape(-1)),
-                              np.ascontiguousarray(hi.reshape(-1)), dA, int(sa is None),
+                              np.ascontiguousarray(hi.reshape(-1)), dA, None, int(sa is None),
                               1.0, eps, ax, ay, az, ent, gh, nth)
         return (time.perf_counter() - t, int((ent * g.count).sum()),
                 np.stack([ax, ay, az], 1).astype(np.float32))

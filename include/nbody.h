@@ -67,12 +67,12 @@ enum {
  *                features and targets of the cost model (NBODY_X_FEAT,
  *                NBODY_X_TARGET). The order never changes the results
  *                (bit-identical). nbody_set_order changes it later.
- *  frontier_cap: cells per wavefront in the walk's breadth-first frontier
- *                buffer (power of two >= 64; 0 = the cell capacity rounded
- *                up to a power of two, at most 16384). A group whose
- *                frontier outgrows it is walked again by a few wavefronts
- *                whose frontier holds any tree (2n cells), so the results
- *                never depend on it.
+ *  frontier_cap: cells per wavefront in the walk's candidate stack (power
+ *                of two >= 64; 0 = the cell capacity rounded up to a power
+ *                of two, at most 16384, which no tree can fill: the stack
+ *                holds at most 512 cells per level). A group whose stack
+ *                outgrows a smaller cap is walked again by a few wavefronts
+ *                with a 16384-cell stack, so the results never depend on it.
  *  list_tile   : interaction-list entries held in LDS per wavefront before a
  *                flush (multiple of 8, 64..2048; 0 = 192).
  *  waves_per_cu: resident wavefronts per compute unit of the persistent walk
@@ -188,7 +188,9 @@ enum {
   NBODY_X_QUEUE = 19,    /* uint32[queued] groups walked by the last walk, in order */
   NBODY_X_FEAT = 20,     /* float32[ngroup][4] cost-model features (orders 1, 2) */
   NBODY_X_TARGET = 21,   /* float32[ngroup] log2 interactions of the last walk */
-  NBODY_X_PRED = 22      /* float32[ngroup] the model's prediction (order 2) */
+  NBODY_X_PRED = 22,     /* float32[ngroup] the model's prediction (order 2) */
+  NBODY_X_SYSBOX = 23,   /* float64[n_sys][4] batch: each system's root cube lo, L */
+  NBODY_X_GROOT = 24     /* uint32[ngroup] batch: each group's walk root cell */
 };
 
 int32_t nbody_abi_version(void);
@@ -251,6 +253,17 @@ nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *ax_old,
  * BLOCKS at its end to read the time reached (st->tick, st->t). */
 nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps);
 
+/* The global-step form of nbody_step (st->level must be NULL) with a fixed
+ * rebuild interval (st->rebuild_interval >= 1), each step replayed from a
+ * HIP graph: the first call captures a rebuild step and a refit step on a
+ * private stream (default priority) and later calls replay them while the
+ * state arrays, n, dt, the queue order and the systems stay the same
+ * (otherwise they are captured again). Ordered after earlier work on the
+ * context's stream, and later work there waits for it. No timing spans and
+ * no rebuild controller inside the graph; results bit-identical to
+ * nbody_step with the same interval. */
+nbody_status nbody_step_graph(nbody_ctx *ctx, nbody_state *st, int32_t n_steps);
+
 /* Eq. 1 by direct O(N^2) summation in FP32 on the GPU (the tree walk's
  * arithmetic calibration and the delta_acc = 0 reference). */
 nbody_status nbody_direct(nbody_ctx *ctx, int64_t n, const float *x,
@@ -294,7 +307,9 @@ int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms,
  * the member count, log2(h + 2^-40) with h half the diagonal of the members'
  * box, log2 of the group mass minus 3x the previous value, and log2(1 + the
  * members' mean list length from their last walk). Weights: FP32, row-major
- * output-major, W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3. All arrays are
+ * output-major, mu[4] is[4] W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3; the
+ * inputs are standardised first, z = (f - mu) * is, with mu, is constants of
+ * the model (their gradient entries are 0). All arrays are
  * device memory; feat is [rows][4] FP32, 16-byte aligned. Calls enqueue on
  * the context's stream (they need a bound workspace for scratch). */
 
@@ -317,9 +332,10 @@ nbody_status nbody_mlp_adam(nbody_ctx *ctx, int64_t n_params, float *w,
                             const float *grad, float *m, float *v, int32_t step,
                             float lr, float beta1, float beta2, float eps);
 
-/* BLOCKING: `steps` full-batch Adam steps (beta 0.9, 0.999, eps 1e-8) on the
- * mean squared error, starting from and updating w. loss_out (host, may be
- * NULL) receives the loss before each step. */
+/* BLOCKING: set the standardisation of w from the rows (mean, 1 / standard
+ * deviation), then `steps` full-batch Adam steps (beta 0.9, 0.999, eps 1e-8)
+ * on the mean squared error, starting from and updating w. loss_out (host,
+ * may be NULL) receives the loss before each step. */
 nbody_status nbody_costmodel_train(nbody_ctx *ctx, int32_t hidden, float *w,
                                    int64_t rows, const float *feat,
                                    const float *target, int32_t steps, float lr,
@@ -330,6 +346,18 @@ nbody_status nbody_set_cost_model(nbody_ctx *ctx, int32_t hidden, const float *w
 
 /* Change the queue order (0, 1 or 2, as nbody_params.order). */
 nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order);
+
+/* ---- Batches of independent systems in one tree (one sort, one build,
+ * one persistent walk for all of them). offsets (host, n_sys + 1 entries,
+ * offsets[0] = 0, strictly increasing: no empty system) give each system's
+ * caller-order range; later builds (nbody_build_tree with n = offsets[n_sys],
+ * nbody_step) use them. Each system gets its own root cube; its index fills
+ * the top r octal digits of the key (r = smallest with 8^r >= n_sys, 0 for
+ * one system) above a Morton key of 21 - r levels; cells above level r are
+ * always split, groups lie at level r or deeper, and each group's walk
+ * starts at its system's root, so no interaction crosses systems. n_sys = 1
+ * returns to a single system. BLOCKING (copies the offsets). */
+nbody_status nbody_set_systems(nbody_ctx *ctx, int32_t n_sys, const int64_t *offsets);
 
 #ifdef __cplusplus
 }

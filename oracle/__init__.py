@@ -56,14 +56,17 @@ def lib():
         L.orc_root_cube.argtypes = [C.c_int64, f32p, f32p, f32p, f64p]
         L.orc_root_cube.restype = C.c_int
         L.orc_keys.argtypes = [C.c_int64, f32p, f32p, f32p, f64p, u64p]
+        L.orc_keys_bits.argtypes = [C.c_int64, f32p, f32p, f32p, f64p, C.c_int32, u64p]
         L.orc_sort.argtypes = [C.c_int64, u64p, i64p, u64p]
-        L.orc_build.argtypes = [C.c_int64, u64p, C.c_int32, C.c_int64] + [C.c_void_p] * 6
+        L.orc_build.argtypes = [C.c_int64, u64p, C.c_int32, C.c_int32, C.c_int64] + \
+            [C.c_void_p] * 6
         L.orc_build.restype = C.c_int64
         L.orc_moments.argtypes = [C.c_int64, i64p, i64p, i64p, i32p, f32p, f32p,
                                   f32p, f32p, C.c_float, f32p, f32p, f32p, f32p,
                                   f32p, f32p] + [C.c_void_p] * 4
         L.orc_groups.argtypes = [C.c_int64, i32p, i64p, i64p, i64p, i32p, C.c_int32,
-                                 C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+                                 C.c_int32, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]
         L.orc_groups.restype = C.c_int64
         L.orc_group_bounds.argtypes = [C.c_int64, i64p, i64p, f32p, f32p, f32p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
@@ -73,7 +76,7 @@ def lib():
         L.orc_mac.restype = C.c_int
         L.orc_walk.argtypes = ([C.c_int64, f32p, f32p, f32p, f32p, C.c_int64, i64p,
                                 i64p, i64p, i32p, f32p, f32p, f32p, f32p, f32p, f32p,
-                                C.c_int64, i64p, i64p, f32p, f32p, f32p, C.c_int,
+                                C.c_int64, i64p, i64p, f32p, f32p, f32p, C.c_void_p, C.c_int,
                                 C.c_double, C.c_double, f64p, f64p, f64p, i64p,
                                 u64p, C.c_int])
         L.orc_mix64.argtypes = [C.c_uint64]
@@ -136,13 +139,44 @@ def root_cube(x, y, z):
     return box
 
 
-def keys(x, y, z, box=None):
+def keys(x, y, z, box=None, bits=21):
     x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
     if box is None:
         box = root_cube(x, y, z)
     k = np.empty(x.shape[0], np.uint64)
-    lib().orc_keys(x.shape[0], x, y, z, _c(box, np.float64), k)
+    if bits == 21:
+        lib().orc_keys(x.shape[0], x, y, z, _c(box, np.float64), k)
+    else:
+        lib().orc_keys_bits(x.shape[0], x, y, z, _c(box, np.float64), bits, k)
     return k, box
+
+
+def system_digits(n_sys: int) -> int:
+    """Octal digits that hold a system index (0 for a single system)."""
+    r = 0
+    while 8 ** r < n_sys:
+        r += 1
+    return r
+
+
+def batch_keys(x, y, z, offsets):
+    """Keys of several independent systems in one array (caller order,
+    system s at [offsets[s], offsets[s+1])): the system index fills the top
+    r = system_digits(S) octal digits, below it the system's own Morton key
+    of 21 - r levels in its own root cube. Returns (keys, boxes (S, 4), r)."""
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    off = np.asarray(offsets, np.int64)
+    S = off.shape[0] - 1
+    r = system_digits(S)
+    bits = 21 - r
+    k = np.empty(x.shape[0], np.uint64)
+    boxes = np.empty((S, 4))
+    for s in range(S):
+        a, b = off[s], off[s + 1]
+        ks, box = keys(x[a:b], y[a:b], z[a:b], bits=bits)
+        k[a:b] = ks | (np.uint64(s) << np.uint64(3 * bits))
+        boxes[s] = box
+    return k, boxes, r
 
 
 def sort(k):
@@ -167,13 +201,15 @@ class Cells:
         return int(self.level.shape[0])
 
 
-def build_tree(keys_sorted, leaf_max=16) -> Cells:
+def build_tree(keys_sorted, leaf_max=16, min_level=0) -> Cells:
+    """Cells are split while they hold more than leaf_max particles or sit
+    above min_level (the system digits of a batch), and lie above level 21."""
     ks = _c(keys_sorted, np.uint64)
     n = ks.shape[0]
-    nc = lib().orc_build(n, ks, leaf_max, 0, *([None] * 6))
+    nc = lib().orc_build(n, ks, leaf_max, min_level, 0, *([None] * 6))
     arr = Cells(np.empty(nc, np.int32), np.empty(nc, np.int64), np.empty(nc, np.int64),
                 np.empty(nc, np.int64), np.empty(nc, np.int32), np.empty(nc, np.int64))
-    lib().orc_build(n, ks, leaf_max, nc, _ptr(arr.level), _ptr(arr.pbegin),
+    lib().orc_build(n, ks, leaf_max, min_level, nc, _ptr(arr.level), _ptr(arr.pbegin),
                     _ptr(arr.pcount), _ptr(arr.first_child), _ptr(arr.n_child),
                     _ptr(arr.parent))
     return arr
@@ -211,10 +247,10 @@ class Groups:
         return int(self.begin.shape[0])
 
 
-def groups(cells: Cells, group_max=64, merge=0) -> Groups:
+def groups(cells: Cells, group_max=64, merge=0, min_level=0) -> Groups:
     nc = cells.n
     args = (nc, cells.level, cells.pbegin, cells.pcount, cells.first_child, cells.n_child,
-            group_max, int(merge))
+            group_max, int(merge), int(min_level))
     ng = lib().orc_groups(*args, 0, None, None, None)
     g = Groups(np.empty(ng, np.int64), np.empty(ng, np.int64), np.empty(ng, np.int64))
     lib().orc_groups(*args, ng, _ptr(g.begin), _ptr(g.count), _ptr(g.cell))
@@ -270,7 +306,7 @@ class TreeResult:
 
 
 def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 ** -9,
-                leaf_max=16, group_max=64, group_merge=0, topo=None,
+                leaf_max=16, group_max=64, group_merge=0, topo=None, systems=None,
                 nthreads=None) -> TreeResult:
     """All steps of the tree method for FP32 inputs in caller order.
 
@@ -279,18 +315,30 @@ def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 *
     FP32 positions from which keys, sort order, cells and groups are taken
     (a tree kept across steps: the paper rebuilds the topology only every
     several steps but recomputes the moments every step, Sec. 1 and 4.1);
-    the moments, group boxes and forces always use (x, y, z)."""
+    the moments, group boxes and forces always use (x, y, z).
+    ``systems`` = offsets (S + 1) of independent systems stored one after
+    another: one tree over batch keys (see batch_keys), groups below the
+    system digits, and each group's walk starting at its system's root."""
     x, y, z, m = (_c(a, np.float32) for a in (x, y, z, m))
     n = x.shape[0]
-    if topo is None:
-        k, box = keys(x, y, z)
+    src = (x, y, z) if topo is None else tuple(_c(a, np.float32) for a in topo)
+    r = 0
+    if systems is None:
+        k, box = keys(*src)
     else:
-        k, box = keys(*(_c(a, np.float32) for a in topo))
+        k, box, r = batch_keys(*src, systems)
     perm, ks = sort(k)
     sx, sy, sz, sm = x[perm], y[perm], z[perm], m[perm]
-    cells = build_tree(ks, leaf_max)
+    cells = build_tree(ks, leaf_max, r)
     mom = moments(cells, sx, sy, sz, sm, G)
-    grp = groups(cells, group_max, group_merge)
+    grp = groups(cells, group_max, group_merge, r)
+    groot = None
+    if r > 0:
+        # the system roots are the level-r cells, one per system in index order
+        roots = np.flatnonzero(cells.level == r)
+        off = np.asarray(systems, np.int64)
+        assert roots.shape[0] == off.shape[0] - 1
+        groot = roots[np.searchsorted(off, grp.begin, side="right") - 1].astype(np.int64)
     sa = None if a_old is None else np.asarray(a_old, np.float32)[perm]
     glo, ghi, gamin, gdA = group_bounds(grp, sx, sy, sz, sa, delta_acc)
     ax, ay, az = (np.empty(n) for _ in range(3))
@@ -300,8 +348,8 @@ def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 *
                    cells.first_child, cells.n_child, mom.m32, _c(mom.com[:, 0], np.float32),
                    _c(mom.com[:, 1], np.float32), _c(mom.com[:, 2], np.float32), mom.b2,
                    mom.q, grp.n, grp.begin, grp.count, _c(glo.reshape(-1), np.float32),
-                   _c(ghi.reshape(-1), np.float32), gdA, int(a_old is None), G, eps,
-                   ax, ay, az, gent, gh, nthreads or nthreads_default())
+                   _c(ghi.reshape(-1), np.float32), gdA, _ptr(groot), int(a_old is None), G,
+                   eps, ax, ay, az, gent, gh, nthreads or nthreads_default())
     acc_s = np.stack([ax, ay, az], axis=1)
     acc = np.empty_like(acc_s)
     acc[perm] = acc_s
@@ -425,10 +473,21 @@ def mlp_grad(w, feat, target, hidden=32):
 
 def mlp_fan_in(hidden=32) -> np.ndarray:
     """Fan-in of the unit each weight feeds, in the weight layout
-    W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3 (for the seeded initialiser)."""
+    mu[4] is[4] W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3 (for the seeded
+    initialiser; the standardisation entries count 1)."""
     H = hidden
-    return np.concatenate([np.full(4 * H, 4), np.full(H, 4), np.full(H * H, H), np.full(H, H),
-                           np.full(H, H), [H]]).astype(np.float64)
+    return np.concatenate([np.ones(8), np.full(4 * H, 4), np.full(H, 4), np.full(H * H, H),
+                           np.full(H, H), np.full(H, H), [H]]).astype(np.float64)
+
+
+def mlp_standardize(w, feat):
+    """Set the model's input standardisation from training data: mu = the
+    mean of each feature, is = 1 / max(standard deviation, 1e-6), FP64."""
+    w = np.asarray(w, np.float64).copy()
+    f = np.asarray(feat, np.float64)
+    w[0:4] = f.mean(axis=0)
+    w[4:8] = 1.0 / np.maximum(f.std(axis=0), 1e-6)
+    return w
 
 
 def adam_step(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
@@ -444,8 +503,9 @@ def adam_step(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def mlp_train(w0, feat, target, *, hidden=32, steps=100, lr=1e-2):
-    """Full-batch Adam on the mean squared error, FP64; returns (w, losses)."""
-    w = np.asarray(w0, np.float64).copy()
+    """Full-batch Adam on the mean squared error, FP64, after setting the
+    input standardisation from feat; returns (w, losses)."""
+    w = mlp_standardize(w0, feat)
     m = np.zeros_like(w)
     v = np.zeros_like(w)
     losses = []

@@ -53,20 +53,25 @@ int orc_root_cube(int64_t n, const float *x, const float *y, const float *z,
 void orc_keys(int64_t n, const float *x, const float *y, const float *z,
               const double box[4], uint64_t *keys);
 
+/* The same with `bits` bits per axis (3 * bits key bits). */
+void orc_keys_bits(int64_t n, const float *x, const float *y, const float *z,
+                   const double box[4], int32_t bits, uint64_t *keys);
+
 /* Stable ascending sort by key: perm[s] = original index of the particle
  * at sorted position s; keys_sorted[s] = keys[perm[s]]. */
 void orc_sort(int64_t n, const uint64_t *keys, int64_t *perm,
               uint64_t *keys_sorted);
 
 /* Level-order octree of sorted keys. A cell at level l covers the particles
- * whose key >> 3(21-l) equals its prefix; it is split iff it holds more than
- * leaf_max particles and l < 21; only non-empty octants become children,
+ * whose key >> 3(21-l) equals its prefix; it is split iff (it holds more
+ * than leaf_max particles or l < min_level) and l < 21; only non-empty
+ * octants become children,
  * stored consecutively in octant order. Cells are numbered by level, then by
  * prefix. Returns the number of cells; if it exceeds cap, nothing beyond cap
  * is written (call with cap = 0 to query). first_child = -1 and n_child = 0
  * for leaves; parent = -1 for the root. */
 int64_t orc_build(int64_t n, const uint64_t *keys_sorted, int32_t leaf_max,
-                  int64_t cap, int32_t *level, int64_t *pbegin,
+                  int32_t min_level, int64_t cap, int32_t *level, int64_t *pbegin,
                   int64_t *pcount, int64_t *first_child, int32_t *n_child,
                   int64_t *parent);
 
@@ -83,9 +88,9 @@ void orc_moments(int64_t ncell, const int64_t *pbegin, const int64_t *pcount,
                  float *comy, float *comz, float *b2, float *q, double *Dm,
                  double *Dsx, double *Dsy, double *Dsz);
 
-/* i-groups: cells holding at most group_max particles (or at level 21)
- * whose parent holds more than group_max particles; the root if n <=
- * group_max. Listed in sorted-particle order; a group cell holding more than
+/* i-groups: cells at min_level or deeper holding at most group_max
+ * particles (or leaves) whose parent is not such a cell; the root if n <=
+ * group_max and min_level == 0. Listed in sorted-particle order; a group cell holding more than
  * group_max particles is cut into consecutive pieces of group_max. With
  * merge != 0, consecutive sibling group cells are joined greedily (in octant
  * order) while the joined count stays within group_max. Returns the count
@@ -94,7 +99,8 @@ void orc_moments(int64_t ncell, const int64_t *pbegin, const int64_t *pcount,
 int64_t orc_groups(int64_t ncell, const int32_t *level, const int64_t *pbegin,
                    const int64_t *pcount, const int64_t *first_child,
                    const int32_t *n_child, int32_t group_max, int32_t merge,
-                   int64_t cap, int64_t *gbegin, int64_t *gcount, int64_t *gcell);
+                   int32_t min_level, int64_t cap, int64_t *gbegin, int64_t *gcount,
+                   int64_t *gcell);
 
 /* Per group: exact FP32 bounding box of the members, amin = min over members
  * of sqrtf(fmaf(az,az,fmaf(ay,ay,ax*ax))) of the previous acceleration, and
@@ -116,7 +122,8 @@ int orc_mac(const float lo[3], const float hi[3], float dA, int bootstrap,
  * pseudo-particles com, m32) and the particles of opened leaves, then sum
  * Eq. 1 over them in FP64 for every member. Outputs (sorted order) FP64
  * accelerations; per group the number of entries and an order-independent
- * hash of the entry identities (cell c -> c, leaf particle s -> 2^40 + s). */
+ * hash of the entry identities (cell c -> c, leaf particle s -> 2^40 + s).
+ * groot (may be NULL: the root, cell 0) gives each group's starting cell. */
 void orc_walk(int64_t n, const float *sx, const float *sy, const float *sz,
               const float *sm, int64_t ncell, const int64_t *pbegin,
               const int64_t *pcount, const int64_t *first_child,
@@ -124,16 +131,18 @@ void orc_walk(int64_t n, const float *sx, const float *sy, const float *sz,
               const float *comy, const float *comz, const float *b2,
               const float *q, int64_t ngroup, const int64_t *gbegin,
               const int64_t *gcount, const float *glo3, const float *ghi3,
-              const float *gdA, int bootstrap, double G, double eps,
-              double *ax, double *ay, double *az, int64_t *gentries,
+              const float *gdA, const int64_t *groot, int bootstrap, double G,
+              double eps, double *ax, double *ay, double *az, int64_t *gentries,
               uint64_t *ghash, int nthreads);
 
 /* Entry-identity mixer used by the per-group hash (splitmix64 finaliser). */
 uint64_t orc_mix64(uint64_t v);
 
 /* MLP cost model 4 -> H -> H -> 1 with tanh hidden units, FP64.
- * Weight layout (row-major, output-major): W1[H][4] b1[H] W2[H][H] b2[H]
- * W3[H] b3. Forward: y = W3 h2 + b3. Loss over a batch: mean (y - t)^2.
+ * Weight layout (row-major, output-major): mu[4] is[4] W1[H][4] b1[H]
+ * W2[H][H] b2[H] W3[H] b3. The inputs are first standardised, z = (f - mu)
+ * * is (fixed constants of the model, set from the training data). Forward:
+ * y = W3 h2 + b3. Loss over a batch: mean (y - t)^2.
  * orc_mlp_grad returns the loss and the gradient (same layout). */
 int64_t orc_mlp_nparams(int32_t hidden);
 void orc_mlp_forward(int32_t hidden, const double *w, int64_t rows,

@@ -27,7 +27,7 @@ class X:
     KEYS, PERM, LEVEL, PBEGIN, PCOUNT, FCHILD, NCHILD, PARENT = 1, 2, 3, 4, 5, 6, 7, 8
     NODE, MQ, MOM64, GBEGIN, GCOUNT, GBOX, GENTRIES, GHASH, XYZM, BOX, QUEUE = (
         9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19)
-    FEAT, TARGET, PRED = 20, 21, 22
+    FEAT, TARGET, PRED, SYSBOX, GROOT = 20, 21, 22, 23, 24
     # (dtype, unit: 'n' | 'cell' | 'group' | 'fixed', elements per unit)
     SPEC = {
         1: ("uint64", "n", 1), 2: ("int32", "n", 1), 3: ("int32", "cell", 1),
@@ -37,7 +37,7 @@ class X:
         13: ("int32", "group", 1), 14: ("float32", "group", 8), 15: ("int32", "group", 1),
         16: ("uint64", "group", 1), 17: ("float32", "n", 4), 18: ("float64", "fixed", 4),
         19: ("int32", "queued", 1), 20: ("float32", "group", 4), 21: ("float32", "group", 1),
-        22: ("float32", "group", 1),
+        22: ("float32", "group", 1), 23: ("float64", "sys", 4), 24: ("int32", "group", 1),
     }
 
 
@@ -85,7 +85,8 @@ HEADER_FUNCTIONS = [
     "nbody_refit", "nbody_calc_acc", "nbody_step", "nbody_direct", "nbody_export",
     "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide", "nbody_timing",
     "nbody_mlp_nparams", "nbody_mlp_forward", "nbody_mlp_grad", "nbody_mlp_adam",
-    "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order",
+    "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order", "nbody_set_systems",
+    "nbody_step_graph",
 ]
 
 _lib = None
@@ -129,6 +130,8 @@ def lib():
         L.nbody_costmodel_train.argtypes = [vp, i32, vp, i64, vp, vp, i32, f32, vp]
         L.nbody_set_cost_model.argtypes = [vp, i32, vp]
         L.nbody_set_order.argtypes = [vp, i32]
+        L.nbody_set_systems.argtypes = [vp, i32, vp]
+        L.nbody_step_graph.argtypes = [vp, C.POINTER(_State), i32]
         for f in HEADER_FUNCTIONS:
             fn = getattr(L, f)
             if fn.restype is C.c_int or fn.restype is None and f != "nbody_destroy":
@@ -151,11 +154,12 @@ def mlp_nparams(hidden: int) -> int:
 
 def mlp_fan_in(hidden: int):
     """Inputs of the unit each weight feeds, in the library's weight layout
-    W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3 (for an initialiser)."""
+    mu[4] is[4] W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3 (for an initialiser;
+    the standardisation entries count 1)."""
     import numpy as np
     H = int(hidden)
-    return np.concatenate([np.full(5 * H, 4), np.full(H * H + H, H), np.full(H + 1, H)]
-                          ).astype(np.float64)
+    return np.concatenate([np.ones(8), np.full(5 * H, 4), np.full(H * H + H, H),
+                           np.full(H + 1, H)]).astype(np.float64)
 
 
 def rebuild_decide(t_build_ms, excess_ms, steps_since, max_interval=64):
@@ -228,6 +232,7 @@ class Context:
                                           int(n_max)), "nbody_bind_workspace")
         self.n_max = int(n_max)
         self.n = 0
+        self.nsys = 1
 
     def __del__(self):
         try:
@@ -290,6 +295,14 @@ class Context:
         state.tick = cs.tick
         state.have_acc = cs.have_acc
 
+    def step_graph(self, state: "State", n_steps: int = 1):
+        """Global steps replayed from a captured HIP graph (fixed rebuild interval)."""
+        cs = state._c()
+        _check(lib().nbody_step_graph(self._h, C.byref(cs), int(n_steps)), "nbody_step_graph")
+        self.n = state.n
+        state.t = cs.t
+        state.have_acc = cs.have_acc
+
     def sync(self):
         _check(lib().nbody_sync(self._h), "nbody_sync")
 
@@ -340,6 +353,14 @@ class Context:
     def set_order(self, order: int):
         _check(lib().nbody_set_order(self._h, int(order)), "nbody_set_order")
 
+    def set_systems(self, offsets):
+        """Several independent systems in one tree: caller-order offsets (S + 1)."""
+        import numpy as np
+        off = np.ascontiguousarray(offsets, np.int64)
+        _check(lib().nbody_set_systems(self._h, off.shape[0] - 1,
+                                       off.ctypes.data_as(C.c_void_p)), "nbody_set_systems")
+        self.nsys = off.shape[0] - 1
+
     def timing(self, enable: bool = True):
         """Zero the timing totals; with enable, count interactions of every walk."""
         _check(lib().nbody_timing(self._h, int(bool(enable))), "nbody_timing")
@@ -354,7 +375,7 @@ class Context:
         dt, unit, per = X.SPEC[what]
         st = self.stats()
         cnt = {"n": self.n, "cell": st["ncell"], "group": st["ngroup"], "fixed": 1,
-               "queued": st["queued"]}[unit] * per
+               "queued": st["queued"], "sys": self.nsys}[unit] * per
         out = torch.empty(max(cnt, 1), dtype=getattr(torch, dt), device=self.device)
         _check(lib().nbody_export(self._h, what, _ptr(out), out.numel()), "nbody_export")
         self.sync()

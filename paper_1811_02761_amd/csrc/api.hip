@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "nbody_internal.h"
 
@@ -46,6 +47,20 @@ struct nbody_ctx {
   bool last_queued = false;  // the last walk used the queue (block steps)
   int64_t queued_sum = 0, ngroup_sum = 0;  // groups walked / present, summed over walks
   int order = 0;       // queue order in use (params.order, or nbody_set_order)
+  int nsys = 1, sys_r = 0;      // batch of independent systems (nbody_set_systems)
+  // graph-captured steps (nbody_step_graph): one graph per step kind
+  bool capturing = false;
+  hipStream_t cap_st = nullptr;  // capture and replay stream (default priority)
+  hipEvent_t cap_ev[2] = {};
+  hipGraphExec_t gexec[2] = {};  // [0] refit step, [1] rebuild step
+  struct GraphKey {
+    const void *p[10];
+    int64_t n;
+    double dt;
+    int order, nsys;
+    int64_t epoch_sys;
+  } gkey[2] = {};
+  int64_t sys_n = 0;            // particles of the batch
   int mlp_hidden = 0;  // hidden width of the installed cost model (0: none)
 };
 
@@ -125,8 +140,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.build_blocks = cdiv(n, kBuildThreads);
   L.walk_waves = (int64_t)num_cu * eff_waves(p);
   L.frontier_cap = eff_frontier(p, L.cell_cap);
-  L.frontier2_cap = 64;
-  while (L.frontier2_cap < 2 * n) L.frontier2_cap <<= 1;
+  // the walk's stack holds at most 512 cells per tree level (22 levels)
+  L.frontier2_cap = 16384;
   L.retry_waves = 2 * kWalkWavesPerWG;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -178,6 +193,9 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_mlpg = take(4 * (size_t)(kMlpMaxParams + 1));
   L.off_mlppart = take(4 * (size_t)kMlpWaves * (size_t)(kMlpMaxParams + 1));
   L.off_gref = take(4 * N);
+  L.off_sysoff = take(4 * (size_t)(kMaxSystems + 1));
+  L.off_sysbox = take(32 * (size_t)kMaxSystems);
+  L.off_groot = take(4 * N);
   L.total = o;
   return L;
 }
@@ -239,6 +257,9 @@ Ptrs carve(void *base, const Layout &L) {
   P.mlpg = reinterpret_cast<float *>(b + L.off_mlpg);
   P.mlppart = reinterpret_cast<float *>(b + L.off_mlppart);
   P.gref = reinterpret_cast<uint32_t *>(b + L.off_gref);
+  P.sysoff = reinterpret_cast<uint32_t *>(b + L.off_sysoff);
+  P.sysbox = reinterpret_cast<double4 *>(b + L.off_sysbox);
+  P.groot = reinterpret_cast<uint32_t *>(b + L.off_groot);
   return P;
 }
 
@@ -352,12 +373,16 @@ WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap, bool queued) {
   c.use_order = queued ? 1 : 0;
   c.frontier2_cap = ctx->L.frontier2_cap;
   c.retry_waves = ctx->L.retry_waves;
+  c.batch = ctx->sys_r > 0;
   return c;
 }
 
 void harvest(nbody_ctx *ctx, bool block);
 
+// While a step is being captured into a graph there are no spans (no events,
+// no copies to the host): span_begin returns -1 and the rest do nothing.
 int span_begin(nbody_ctx *ctx, int kind) {
+  if (ctx->capturing) return -1;
   if (ctx->sp_count == nbody_ctx::kSpans) harvest(ctx, true);
   const int i = (ctx->sp_head + ctx->sp_count) % nbody_ctx::kSpans;
   ctx->span_kind[i] = kind;
@@ -367,6 +392,7 @@ int span_begin(nbody_ctx *ctx, int kind) {
 }
 
 void span_end(nbody_ctx *ctx, int i) {
+  if (i < 0) return;
   (void)hipEventRecord(ctx->ev_b[i], ctx->st);
   ctx->sp_count++;
 }
@@ -374,12 +400,15 @@ void span_end(nbody_ctx *ctx, int i) {
 // After the end event of walk span i: its statistics to pinned memory, then
 // the span's done event.
 void span_stats(nbody_ctx *ctx, int i, bool queued) {
+  if (i < 0) return;
   launch_walk_stat(queued, ctx->P, ctx->st);
   (void)hipMemcpyAsync(&ctx->aux[i], &ctx->P.sc->wstat, sizeof(WalkStat),
                        hipMemcpyDeviceToHost, ctx->st);
 }
 
-void span_done(nbody_ctx *ctx, int i) { (void)hipEventRecord(ctx->ev_c[i], ctx->st); }
+void span_done(nbody_ctx *ctx, int i) {
+  if (i >= 0) (void)hipEventRecord(ctx->ev_c[i], ctx->st);
+}
 
 int pending_walks(const nbody_ctx *ctx) {
   int k = 0;
@@ -426,18 +455,23 @@ void harvest(nbody_ctx *ctx, bool block) {
 nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
                       const float *z, const float *m) {
   const Ptrs &P = ctx->P;
+  if (ctx->sys_r > 0 && n != ctx->sys_n) return NBODY_EINVAL;  // not the configured batch
   ctx->epoch++;
   ctx->excess_ms = 0.0;
   const int sp = span_begin(ctx, 0);
-  launch_bbox(x, y, z, n, P.sc, ctx->st);
-  launch_keys(x, y, z, n, P.sc, P.keysA, P.valsA, ctx->st);
+  if (ctx->sys_r > 0) {
+    launch_sys_keys(x, y, z, n, ctx->nsys, ctx->sys_r, P, ctx->st);
+  } else {
+    launch_bbox(x, y, z, n, P.sc, ctx->st);
+    launch_keys(x, y, z, n, P.sc, P.keysA, P.valsA, ctx->st);
+  }
   uint64_t *ks;
   uint32_t *pm;
   launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
               &ks, &pm);
   launch_gather(x, y, z, m, pm, n, P.xyzm, ctx->st);
-  launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, P, ctx->L,
-               ctx->st);
+  launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, ctx->nsys,
+               ctx->sys_r, P, ctx->L, ctx->st);
   launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
   span_end(ctx, sp);
   span_done(ctx, sp);
@@ -593,6 +627,14 @@ void nbody_destroy(nbody_ctx *ctx) {
   if (ctx->aux) {
     (void)hipStreamSynchronize(ctx->st);
     (void)hipHostFree(ctx->aux);
+  }
+  if (ctx->cap_st) {
+    (void)hipStreamSynchronize(ctx->cap_st);
+    for (int k = 0; k < 2; ++k) {
+      if (ctx->gexec[k]) (void)hipGraphExecDestroy(ctx->gexec[k]);
+      if (ctx->cap_ev[k]) (void)hipEventDestroy(ctx->cap_ev[k]);
+    }
+    (void)hipStreamDestroy(ctx->cap_st);
   }
   delete ctx;
 }
@@ -872,6 +914,11 @@ nbody_status nbody_export(nbody_ctx *ctx, int32_t what, void *dst, int64_t capac
     case NBODY_X_FEAT: src = P.feat; count = 4 * ng; break;
     case NBODY_X_TARGET: src = P.target; count = ng; break;
     case NBODY_X_PRED: src = P.pred; count = ng; break;
+    case NBODY_X_SYSBOX: src = P.sysbox; count = 4 * (int64_t)ctx->nsys; esz = 8; break;
+    case NBODY_X_GROOT:
+      src = P.groot;
+      count = ctx->sys_r > 0 ? ng : 0;
+      break;
     default: return NBODY_EINVAL;
   }
   if (capacity < count) return NBODY_ENOMEM;
@@ -940,6 +987,7 @@ nbody_status nbody_costmodel_train(nbody_ctx *ctx, int32_t hidden, float *w, int
     return NBODY_EINVAL;
   const Ptrs &P = ctx->P;
   const int64_t np = mlp_nparams(hidden);
+  launch_mlp_standardize(reinterpret_cast<const float4 *>(feat), rows, w, ctx->st);
   launch_fill_u32(reinterpret_cast<uint32_t *>(P.mlpm), 0u, np, ctx->st);  // +0.0f
   launch_fill_u32(reinterpret_cast<uint32_t *>(P.mlpv), 0u, np, ctx->st);
   for (int32_t t = 1; t <= steps; ++t) {
@@ -976,6 +1024,136 @@ nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order) {
   if (order < 0 || order > 2) return NBODY_EINVAL;
   ctx->order = order;
   return NBODY_OK;
+}
+
+
+nbody_status nbody_set_systems(nbody_ctx *ctx, int32_t n_sys, const int64_t *offsets) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (n_sys < 1 || n_sys > kMaxSystems || !offsets || offsets[0] != 0) return NBODY_EINVAL;
+  for (int32_t i = 0; i < n_sys; ++i)
+    if (offsets[i + 1] <= offsets[i]) return NBODY_EINVAL;  // every system non-empty
+  if (offsets[n_sys] > ctx->L.n_max) return NBODY_ENOMEM;
+  std::vector<uint32_t> off((size_t)n_sys + 1);
+  for (int32_t i = 0; i <= n_sys; ++i) off[i] = (uint32_t)offsets[i];
+  if (hipMemcpyAsync(ctx->P.sysoff, off.data(), sizeof(uint32_t) * off.size(),
+                     hipMemcpyHostToDevice, ctx->st) != hipSuccess ||
+      hipStreamSynchronize(ctx->st) != hipSuccess)
+    return NBODY_EHIP;
+  int r = 0;
+  while (n_sys > 1 && (1 << (3 * r)) < n_sys) ++r;
+  ctx->nsys = n_sys;
+  ctx->sys_r = r;
+  ctx->sys_n = offsets[n_sys];
+  ctx->have_tree = false;
+  return NBODY_OK;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+// One global kick-drift-kick step (rebuild or refit), as nbody_step runs it.
+nbody_status step_body(nbody_ctx *ctx, nbody_state *st, bool rebuild) {
+  nbody_status s;
+  const int64_t n = st->n;
+  float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
+  const float hdt = (float)(0.5 * st->dt);
+  launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
+  launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32, ctx->st);
+  if (rebuild) {
+    if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+  } else {
+    if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
+  }
+  if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
+    return s;
+  launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
+  return hip_status();
+}
+
+nbody_ctx::GraphKey graph_key(const nbody_ctx *ctx, const nbody_state *st) {
+  nbody_ctx::GraphKey k{};
+  const void *p[10] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, st->m, st->ax, st->ay, st->az};
+  memcpy(k.p, p, sizeof(p));
+  k.n = st->n;
+  k.dt = st->dt;
+  k.order = (ctx->order == 2 && ctx->mlp_hidden == 0) ? 0 : ctx->order;
+  k.nsys = ctx->nsys;
+  return k;
+}
+
+// Capture one step of `kind` (1: rebuild) on the private stream.
+nbody_status capture_step(nbody_ctx *ctx, nbody_state *st, int kind) {
+  hipStream_t orig = ctx->st;
+  ctx->st = ctx->cap_st;
+  ctx->capturing = true;
+  nbody_status s = NBODY_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    s = NBODY_EHIP;
+  } else {
+    s = step_body(ctx, st, kind == 1);
+    if (hipStreamEndCapture(ctx->cap_st, &g) != hipSuccess && s == NBODY_OK) s = NBODY_EHIP;
+  }
+  ctx->capturing = false;
+  ctx->st = orig;
+  if (s != NBODY_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (ctx->gexec[kind]) (void)hipGraphExecDestroy(ctx->gexec[kind]);
+  ctx->gexec[kind] = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ctx->gexec[kind], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ctx->gexec[kind] = nullptr;
+    return NBODY_EHIP;
+  }
+  ctx->gkey[kind] = graph_key(ctx, st);
+  return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nbody_status nbody_step_graph(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!st || st->level || st->rebuild_interval < 1) return NBODY_EINVAL;
+  if (!ctx->cap_st) {
+    if (hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->cap_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->cap_ev[1], hipEventDisableTiming) != hipSuccess)
+      return NBODY_EHIP;
+  }
+  // argument checks and the first force evaluation, eagerly
+  if ((s = nbody_step(ctx, st, 0)) != NBODY_OK) return s;
+  if (n_steps == 0) return NBODY_OK;
+  const nbody_ctx::GraphKey key = graph_key(ctx, st);
+  if (hipEventRecord(ctx->cap_ev[0], ctx->st) != hipSuccess ||
+      hipStreamWaitEvent(ctx->cap_st, ctx->cap_ev[0], 0) != hipSuccess)
+    return NBODY_EHIP;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const int kind = (ctx->n != st->n || ctx->since_rebuild >= st->rebuild_interval) ? 1 : 0;
+    if (!ctx->gexec[kind] || memcmp(&ctx->gkey[kind], &key, sizeof(key)) != 0)
+      if ((s = capture_step(ctx, st, kind)) != NBODY_OK) return s;
+    if (hipGraphLaunch(ctx->gexec[kind], ctx->cap_st) != hipSuccess) return NBODY_EHIP;
+    if (kind == 1) {
+      ctx->rebuilds++;
+      ctx->since_rebuild = 0;
+      ctx->n = st->n;
+    }
+    ctx->since_rebuild++;
+    ctx->steps++;
+    st->t += st->dt;
+  }
+  if (hipEventRecord(ctx->cap_ev[1], ctx->cap_st) != hipSuccess ||
+      hipStreamWaitEvent(ctx->st, ctx->cap_ev[1], 0) != hipSuccess)
+    return NBODY_EHIP;
+  return hip_status();
 }
 
 }  // extern "C"

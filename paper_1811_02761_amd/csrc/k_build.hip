@@ -92,7 +92,7 @@ __device__ __forceinline__ int ilog2_floor(int v) { return 31 - __clz(v); }
 // Pass A: per sorted particle s_i and D_i; per block and level the number of
 // cells starting in the block.
 __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
-                                                uint32_t n, int leaf_max,
+                                                uint32_t n, int leaf_max, int min_level,
                                                 uint32_t *__restrict__ pinfo,
                                                 uint32_t *__restrict__ blkcnt,
                                                 uint32_t nblk) {
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
   if (valid) {
     s = (i == 0) ? 0 : cpl_keys(sk[li - 1], sk[li]) + 1;
     const int M = max(tL[li - leaf_max], tL[li - (1 << kLw) + 1]);
-    D = min(M + 1, kMaxLevel);
+    D = max(min(M + 1, kMaxLevel), min_level);  // cells above min_level always split
     pinfo[i] = (uint32_t)s | ((uint32_t)D << 5);  // group mark (bit 15) clear
   }
   const int w = threadIdx.x >> 6;
@@ -277,32 +277,42 @@ __device__ __forceinline__ void mark_chunks(uint32_t *__restrict__ pinfo, uint32
   for (uint32_t s = 0; s < cnt; s += gmax) pinfo[b + s] |= kGroupMark;
 }
 
-// Group starts: the root if it holds at most group_max particles (or is a
-// leaf); otherwise every cell holding more than group_max particles marks
-// the starts among its children (joining consecutive small siblings when
-// `merge`). Every particle is marked at most once.
+// A cell may hold a group iff it is at min_level (the system digits of a
+// batch) or deeper and holds at most group_max particles or is a leaf.
+__device__ __forceinline__ bool group_ok(int32_t level, uint32_t cnt, int nchild,
+                                         uint32_t gmax, int min_level) {
+  return level >= min_level && (cnt <= gmax || nchild == 0);
+}
+
+// Group starts: the root if it may hold a group; otherwise every cell that
+// may not marks the group starts among its children (joining consecutive
+// small siblings when `merge`; an over-full leaf is cut into pieces of
+// group_max). Every particle is marked at most once.
 __global__ __launch_bounds__(256) void k_group_mark(DevScalars *__restrict__ sc,
+                                                    const int32_t *__restrict__ clevel,
                                                     const uint32_t *__restrict__ cpbegin,
                                                     const uint32_t *__restrict__ cpcount,
                                                     const int32_t *__restrict__ cfchild,
                                                     const int32_t *__restrict__ cnchild,
-                                                    uint32_t gmax, int merge,
+                                                    uint32_t gmax, int merge, int min_level,
                                                     uint32_t *__restrict__ pinfo) {
   const uint32_t nc = sc->ncell;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc;
        c += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t cnt = cpcount[c];
     const int k = cnchild[c];
-    if (c == 0 && (cnt <= gmax || k == 0)) {
+    const bool ok = group_ok(clevel[c], cnt, k, gmax, min_level);
+    if (c == 0 && ok) {
       mark_chunks(pinfo, cpbegin[0], cnt, gmax);
       continue;
     }
-    if (cnt <= gmax || k == 0) continue;
+    if (ok || k == 0) continue;
     const int32_t f = cfchild[c];
     uint32_t run = 0;  // particles in the open joined group (0: none open)
     for (int q = 0; q < k; ++q) {
       const uint32_t cb = cpbegin[f + q], cc = cpcount[f + q];
-      if (cc <= gmax) {
+      const bool cok = group_ok(clevel[f + q], cc, cnchild[f + q], gmax, min_level);
+      if (cok && cc <= gmax) {
         if (merge && run > 0 && run + cc <= gmax) {
           run += cc;
         } else {
@@ -311,7 +321,7 @@ __global__ __launch_bounds__(256) void k_group_mark(DevScalars *__restrict__ sc,
         }
       } else {
         run = 0;
-        if (cnchild[f + q] == 0) mark_chunks(pinfo, cb, cc, gmax);  // level-21 leaf
+        if (cok) mark_chunks(pinfo, cb, cc, gmax);  // an over-full (level-21) leaf
       }
     }
   }
@@ -367,12 +377,37 @@ __global__ __launch_bounds__(256) void k_group_size(const DevScalars *__restrict
     gcount[g] = gbegin[g + 1] - gbegin[g];
 }
 
+// Batch: each group's walk starts at its system's root, the level-r cell of
+// the system (one per system, numbered by system index). Sorted positions of
+// system s are [off[s], off[s+1]) as in caller order.
+__global__ __launch_bounds__(256) void k_group_root(const DevScalars *__restrict__ sc,
+                                                    const uint32_t *__restrict__ gbegin,
+                                                    const uint32_t *__restrict__ off, int nsys,
+                                                    int r, uint32_t *__restrict__ groot) {
+  const uint32_t ng = sc->ngroup;
+  const uint32_t base = sc->lvl_off[r];
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = gbegin[g];
+    int lo = 0, hi = nsys;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= b)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    groot[g] = base + (uint32_t)lo;
+  }
+}
+
 void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
-                  int group_merge, const Ptrs &P, const Layout &L, hipStream_t st) {
+                  int group_merge, int nsys, int r, const Ptrs &P, const Layout &L,
+                  hipStream_t st) {
   const uint32_t nblk = (uint32_t)cdiv(n, kB);
   // block rows [kLevels][nblk], then kLevels totals
   uint32_t *totals = P.blkcnt + (int64_t)kLevels * nblk;
-  hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, leaf_max,
+  hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, leaf_max, r,
                      P.pinfo, P.blkcnt, nblk);
   hipLaunchKernelGGL(k_scan_rows, dim3(kLevels), dim3(256), 0, st, P.blkcnt, nblk, totals);
   hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
@@ -385,8 +420,9 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                      P.cparent, P.nodeB);
   // groups (the block rows are free again: reuse them for the group scan)
   uint32_t *gblk = P.blkcnt, *gtot = P.blkcnt + nblk;
-  hipLaunchKernelGGL(k_group_mark, dim3(ge), dim3(256), 0, st, P.sc, P.cpbegin, P.cpcount,
-                     P.cfchild, P.cnchild, (uint32_t)group_max, group_merge, P.pinfo);
+  hipLaunchKernelGGL(k_group_mark, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cpbegin,
+                     P.cpcount, P.cfchild, P.cnchild, (uint32_t)group_max, group_merge, r,
+                     P.pinfo);
   hipLaunchKernelGGL(k_group_count, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk);
   hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, st, gblk, nblk, gtot);
   hipLaunchKernelGGL(k_group_emit, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk,
@@ -394,6 +430,9 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   hipLaunchKernelGGL(k_group_total, dim3(1), dim3(64), 0, st, gtot, (uint32_t)n, P.sc,
                      P.gbegin);
   hipLaunchKernelGGL(k_group_size, dim3(ge), dim3(256), 0, st, P.sc, P.gbegin, P.gcount);
+  if (r > 0)
+    hipLaunchKernelGGL(k_group_root, dim3(ge), dim3(256), 0, st, P.sc, P.gbegin, P.sysoff, nsys,
+                       r, P.groot);
 }
 
 void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,

@@ -80,9 +80,11 @@ __global__ __launch_bounds__(256) void k_cost_after(
 }
 
 // ---------------------------------------------------------------- MLP
-// Weight layout (row-major, output-major): W1[H][4] b1[H] W2[H][H] b2[H]
-// W3[H] b3.
-__host__ __device__ constexpr int mlp_np(int H) { return 7 * H + H * H + 1; }
+// Weight layout (row-major, output-major): mu[4] is[4] W1[H][4] b1[H]
+// W2[H][H] b2[H] W3[H] b3. The inputs are standardised first, z = (f - mu)
+// * is; mu and is are constants of the model (set from the training data),
+// not trained.
+__host__ __device__ constexpr int mlp_np(int H) { return 8 + 7 * H + H * H + 1; }
 
 // Forward, one thread per row; the weights are staged in LDS. rows_dev
 // (optional) bounds the rows on the device.
@@ -94,12 +96,14 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ w
   __shared__ float sw[mlp_np(H)];
   for (int i = threadIdx.x; i < mlp_np(H); i += blockDim.x) sw[i] = w[i];
   __syncthreads();
-  const float *W1 = sw, *b1 = W1 + 4 * H, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H,
-              *b3 = W3 + H;
+  const float *mu = sw, *is = sw + 4, *W1 = sw + 8, *b1 = W1 + 4 * H, *W2 = b1 + H,
+              *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + H;
   const int64_t nr = rows_dev ? (int64_t)*rows_dev : rows;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr;
        r += (int64_t)gridDim.x * blockDim.x) {
-    const float4 f = feat[r];
+    const float4 fr = feat[r];
+    const float4 f = make_float4((fr.x - mu[0]) * is[0], (fr.y - mu[1]) * is[1],
+                                 (fr.z - mu[2]) * is[2], (fr.w - mu[3]) * is[3]);
     float h1[H];
 #pragma unroll
     for (int u = 0; u < H; ++u) {
@@ -133,8 +137,10 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ w, i
                                                   const float *__restrict__ target,
                                                   float *__restrict__ partial) {
   __shared__ float sW2[H * H];
-  const float *W1 = w, *b1 = W1 + 4 * H, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H,
-              *b3 = W3 + H;
+  const float *mu = w, *is = w + 4, *W1 = w + 8, *b1 = W1 + 4 * H, *W2 = b1 + H,
+              *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + H;
+  const float mu0 = mu[0], mu1 = mu[1], mu2 = mu[2], mu3 = mu[3];
+  const float is0 = is[0], is1 = is[1], is2 = is[2], is3 = is[3];
   for (int i = threadIdx.x; i < H * H; i += blockDim.x) sW2[i] = W2[i];
   __syncthreads();
   const int u = lane_id();
@@ -151,7 +157,9 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ w, i
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   for (int64_t r = gw; r < rows; r += nw) {
-    const float4 f = feat[r];
+    const float4 fr = feat[r];
+    const float4 f = make_float4((fr.x - mu0) * is0, (fr.y - mu1) * is1, (fr.z - mu2) * is2,
+                                 (fr.w - mu3) * is3);
     float s1 = bb1;
     s1 = __builtin_fmaf(w10, f.x, s1);
     s1 = __builtin_fmaf(w11, f.y, s1);
@@ -184,12 +192,14 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ w, i
   }
   constexpr int np = mlp_np(H);
   float *out = partial + gw * (np + 1);
+  if (u < 8) out[u] = 0.0f;  // the standardisation is not trained
+  float *o = out + 8;
   if (on) {
-    for (int j = 0; j < 4; ++j) out[4 * u + j] = gW1[j];
-    out[4 * H + u] = gb1;
-    for (int k = 0; k < H; ++k) out[5 * H + u * H + k] = gW2[k];
-    out[5 * H + H * H + u] = gb2;
-    out[6 * H + H * H + u] = gW3;
+    for (int j = 0; j < 4; ++j) o[4 * u + j] = gW1[j];
+    o[4 * H + u] = gb1;
+    for (int k = 0; k < H; ++k) o[5 * H + u * H + k] = gW2[k];
+    o[5 * H + H * H + u] = gb2;
+    o[6 * H + H * H + u] = gW3;
   }
   if (u == 0) {
     out[np - 1] = gb3;
@@ -203,6 +213,46 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ pa
     float s = 0.f;
     for (int q = 0; q < nw; ++q) s += partial[(int64_t)q * np1 + i];
     out[i] = s;
+  }
+}
+
+// The model's input standardisation from training rows (one workgroup, FP64
+// sums): mu = mean, is = 1 / max(standard deviation, 1e-6).
+__global__ __launch_bounds__(256) void k_mlp_standardize(const float4 *__restrict__ feat,
+                                                         int64_t rows, float *__restrict__ w) {
+  __shared__ double s1[4][4], s2[4][4];
+  double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+    const float4 f = feat[r];
+    const double v[4] = {f.x, f.y, f.z, f.w};
+    for (int k = 0; k < 4; ++k) {
+      a[k] += v[k];
+      b[k] += v[k] * v[k];
+    }
+  }
+  for (int k = 0; k < 4; ++k)
+    for (int d = 32; d >= 1; d >>= 1) {
+      a[k] += __shfl_xor(a[k], d, 64);
+      b[k] += __shfl_xor(b[k], d, 64);
+    }
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 0)
+    for (int k = 0; k < 4; ++k) {
+      s1[wv][k] = a[k];
+      s2[wv][k] = b[k];
+    }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    double sa = 0, sb = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      sa += s1[q][k];
+      sb += s2[q][k];
+    }
+    const double mean = sa / (double)rows;
+    const double var = fmax(sb / (double)rows - mean * mean, 0.0);
+    w[k] = (float)mean;
+    w[4 + k] = (float)(1.0 / fmax(sqrt(var), 1e-6));
   }
 }
 
@@ -309,6 +359,10 @@ void launch_adam(int64_t np, float *w, const float *g, float *m, float *v, int s
   const float c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)step)));
   hipLaunchKernelGGL(k_adam, dim3(grid_for(np, 256, 64)), dim3(256), 0, st, np, w, g, m, v, lr,
                      b1, b2, eps, c1, c2);
+}
+
+void launch_mlp_standardize(const float4 *feat, int64_t rows, float *w, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_standardize, dim3(1), dim3(256), 0, st, feat, rows, w);
 }
 
 void launch_cost_features(int64_t n, const uint32_t *perm, const Ptrs &P, hipStream_t st) {

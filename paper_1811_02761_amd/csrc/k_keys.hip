@@ -117,6 +117,106 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
   }
 }
 
+// ---- several independent systems in one tree (system s holds caller
+// indices [off[s], off[s+1])): each system gets its own root cube, and its
+// index fills the top r octal digits of the key above a (21 - r)-level
+// Morton key in that cube.
+
+// One workgroup per system: exact bounds, then lo and L of its root cube.
+__global__ __launch_bounds__(256) void k_sys_bbox(const float *__restrict__ x,
+                                                  const float *__restrict__ y,
+                                                  const float *__restrict__ z,
+                                                  const uint32_t *__restrict__ off,
+                                                  double4 *__restrict__ sysbox,
+                                                  DevScalars *sc) {
+  const uint32_t s = blockIdx.x;
+  const uint32_t a = off[s], b = off[s + 1];
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (uint32_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+    const float v[3] = {x[i], y[i], z[i]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      bad |= !isfinite(v[k]);
+      lo[k] = fminf(lo[k], v[k]);
+      hi[k] = fmaxf(hi[k], v[k]);
+    }
+  }
+  __shared__ float red[6][4];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float p = wave_min(lo[k]);
+    const float q = wave_max(hi[k]);
+    if (lane_id() == 0) {
+      red[k][w] = p;
+      red[3 + k][w] = q;
+    }
+  }
+  if (__any(bad) && lane_id() == 0) atomicOr(&sc->status, kStNonFinite);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double l[3], ext = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      float p = red[k][0], q = red[3 + k][0];
+      for (int j = 1; j < (int)(blockDim.x >> 6); ++j) {
+        p = fminf(p, red[k][j]);
+        q = fmaxf(q, red[3 + k][j]);
+      }
+      l[k] = (double)p;
+      const double e = (double)q - (double)p;
+      ext = e > ext ? e : ext;
+    }
+    int eL = 0;
+    if (ext > 0.0) {
+      int e;
+      const double f = frexp(ext, &e);
+      eL = (f == 0.5) ? e - 1 : e;
+    }
+    sysbox[s] = make_double4(l[0], l[1], l[2], ldexp(1.0, eL));
+  }
+}
+
+__device__ __forceinline__ uint32_t quantise_bits(float v, double lo, double scale,
+                                                  double top) {
+  const double t = ((double)v - lo) * scale;
+  if (t >= top) return (uint32_t)top;
+  if (t <= 0.0) return 0u;
+  return (uint32_t)t;
+}
+
+__global__ __launch_bounds__(256) void k_sys_keys(const float *__restrict__ x,
+                                                  const float *__restrict__ y,
+                                                  const float *__restrict__ z, int64_t n,
+                                                  const uint32_t *__restrict__ off, int nsys,
+                                                  int r, const double4 *__restrict__ sysbox,
+                                                  uint64_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals) {
+  const int bits = kMaxLevel - r;
+  const double top = ldexp(1.0, bits) - 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // system of i: the last s with off[s] <= i
+    int lo = 0, hi = nsys;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= (uint32_t)i)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const double4 bx = sysbox[lo];
+    const double scale = ldexp(1.0, bits) / bx.w;
+    const uint32_t qx = quantise_bits(x[i], bx.x, scale, top);
+    const uint32_t qy = quantise_bits(y[i], bx.y, scale, top);
+    const uint32_t qz = quantise_bits(z[i], bx.z, scale, top);
+    keys[i] = ((uint64_t)lo << (3 * bits)) | (spread3(qx) << 2) | (spread3(qy) << 1) |
+              spread3(qz);
+    vals[i] = (uint32_t)i;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ x,
                                                 const float *__restrict__ y,
                                                 const float *__restrict__ z,
@@ -142,6 +242,14 @@ void launch_bbox(const float *x, const float *y, const float *z, int64_t n,
   hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, sc);
   hipLaunchKernelGGL(k_bbox, dim3(grid_for(n, 8, 2048)), dim3(256), 0, st, x, y, z,
                      n, sc);
+}
+
+void launch_sys_keys(const float *x, const float *y, const float *z, int64_t n, int nsys,
+                     int r, const Ptrs &P, hipStream_t st) {
+  hipLaunchKernelGGL(k_sys_bbox, dim3(nsys), dim3(256), 0, st, x, y, z, P.sysoff, P.sysbox,
+                     P.sc);
+  hipLaunchKernelGGL(k_sys_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z, n,
+                     P.sysoff, nsys, r, P.sysbox, P.keysA, P.valsA);
 }
 
 void launch_keys(const float *x, const float *y, const float *z, int64_t n,

@@ -2,18 +2,22 @@
 //
 // One wavefront serves one i-group at a time, taking groups from a global
 // work queue until the queue is empty (persistent kernel). For its group it
-// traverses the tree breadth first from the root: 64 candidate cells at a
-// time are tested against the acceleration MAC of Eq. 2 (one lane per cell);
-// accepted cells enter the interaction list as pseudo-particles (centre of
-// mass, mass), opened leaves contribute their particles, opened internal
-// cells append their children to the wave's frontier ring in global memory
-// (the paper's per-SM cell buffer, Sec. 3). Offsets come from wave prefix
-// sums. The list lives in LDS; whenever it holds `list_tile` entries it is
-// flushed: every lane adds Eq. 1 over the tile for its particle, in FP32.
+// traverses the tree from the root, depth first in chunks: the top 64 (or
+// fewer) candidate cells of the wave's stack in global memory (the paper's
+// per-SM cell buffer, Sec. 3) are popped and tested against the acceleration
+// MAC of Eq. 2, one lane per cell; accepted cells enter the interaction list
+// as pseudo-particles (centre of mass, mass), opened leaves contribute their
+// particles, opened internal cells push their children (lane order). Each
+// chunk pushes at most 512 cells, so the stack never holds more than 512 per
+// tree level (under 11K cells), unlike a breadth-first frontier, which can
+// hold a whole level. Offsets come from wave prefix sums. The list lives in
+// LDS; whenever it holds `list_tile` entries it is flushed: every lane adds
+// Eq. 1 over the tile for its particle, in FP32.
 //
-// Canonical order: list entries appear in breadth-first candidate order and
-// a flush only cuts that sequence, so each lane's summation order is fixed by
-// the group alone. It does not depend on the tile size, the queue order or
+// Canonical order: list entries appear in the order of this traversal (a
+// function of the tree and the group alone) and a flush only cuts that
+// sequence, so each lane's summation order is fixed by the group alone. It
+// does not depend on the tile size, the stack capacity, the queue order or
 // which wave runs the group: results are bit-identical across them.
 //
 // Lane layout: groups of at most 8, 16 or 32 members use S = 8, 4 or 2
@@ -75,6 +79,7 @@ struct WalkArgs {
   const uint32_t *perm;
   const uint32_t *order;   // queue -> group (nullptr: identity)
   const uint32_t *qcount;  // queue length (device)
+  const uint32_t *groot;   // per group root cell (nullptr: the root, cell 0)
   uint32_t *retry;         // overflowing groups go here (nullptr: report instead)
   uint32_t *nretry;
   uint32_t *frontier;
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
   uint32_t *s_incl =
       reinterpret_cast<uint32_t *>(lds_list + kWalkWavesPerWG * (TS + 64)) + wv * 128;
   uint32_t *s_src = s_incl + 64;
-  uint32_t *ring =
+  uint32_t *stk =
       a.frontier + (size_t)(blockIdx.x * kWalkWavesPerWG + wv) * (size_t)(a.fmask + 1);
   const uint32_t F = a.fmask + 1;
   const uint32_t ng = *a.qcount;
@@ -213,21 +218,22 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
     const float4 pi = a.xyzm[gb + (mem_ok ? member : 0u)];
     Acc3<kComp> acc;
     uint64_t hsum = 0;
-    ring[0] = 0u;  // the root (every lane stores the same value)
-    uint32_t head = 0, tail = 1, cnt = 0;
+    stk[0] = a.groot ? a.groot[g] : 0u;  // the walk's root (same value in every lane)
+    uint32_t top = 1, visited = 0, cnt = 0;
     uint32_t entries = 0;
     bool overflow = false, corrupt = false;
-    while (head < tail) {
-      const uint32_t nc = min(64u, tail - head);
-      if (head + nc > ncell) {  // a tree visits each cell at most once
+    while (top > 0) {
+      const uint32_t nc = min(64u, top);
+      visited += nc;
+      if (visited > ncell) {  // a tree visits each cell at most once
         corrupt = true;
         break;
       }
-      const uint32_t cc = lane < nc ? ring[(head + lane) & a.fmask] : 0u;
+      top -= nc;
+      const uint32_t cc = lane < nc ? stk[top + lane] : 0u;
       const bool bad_c = lane < nc && cc >= ncell;
       const bool has = lane < nc && !bad_c;
       const uint32_t c = has ? cc : 0u;
-      head += nc;
       float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
       if (has) {
         A = a.nodeA[c];
@@ -264,15 +270,17 @@ __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
       const bool leaf = (w1 & kLeafBit) != 0u;
       const uint32_t ne = !has ? 0u : accept ? 1u : leaf ? (w1 & ~kLeafBit) : 0u;
       const uint32_t nch = (has && !accept && !leaf) ? w1 : 0u;
-      // children -> frontier ring
+      // children -> stack (over the popped chunk, in lane order)
       const uint32_t chi = wave_incl_scan_dpp(nch);
       const uint32_t chtot = wave_last(chi);
-      if (tail - head + chtot > F) {
+      if (top + chtot > F) {
         overflow = true;
         break;
       }
-      for (uint32_t k = 0; k < nch; ++k) ring[(tail + chi - nch + k) & a.fmask] = w0 + k;
-      tail += chtot;
+      // every lane has read its candidate before any lane overwrites it
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t k = 0; k < nch; ++k) stk[top + chi - nch + k] = w0 + k;
+      top += chtot;
       // entries -> LDS list (flushing full tiles). Lane k owns entries
       // [incl_k - ne_k, incl_k); the copy is cooperative: lane r of the wave
       // fetches entry done + r, finding its owner by binary search.
@@ -440,6 +448,7 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   a.perm = perm;
   a.order = c.use_order ? P.order : nullptr;
   a.qcount = c.use_order ? &P.sc->nqueue : &P.sc->ngroup;
+  a.groot = c.batch ? P.groot : nullptr;
   a.retry = P.retry;
   a.nretry = &P.sc->nretry;
   a.frontier = P.frontier;
@@ -475,10 +484,10 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   };
   launch_fill_u32(&P.sc->nretry, 0u, 1, st);
   launch(a, dim3(blocks));
-  // retry pass: the overflowing groups, walked by a few wavefronts whose
-  // frontier holds the two widest levels of any tree; a second overflow is
-  // reported (it cannot happen: a breadth-first frontier never holds more
-  // than two levels of cells, and a level has at most n cells)
+  // retry pass: the groups that outgrew a small stack (frontier_cap below
+  // the bound), walked by a few wavefronts whose stack holds 512 cells per
+  // level of the deepest tree; a second overflow is reported (it cannot
+  // happen)
   WalkArgs r = a;
   r.order = P.retry;
   r.qcount = &P.sc->nretry;

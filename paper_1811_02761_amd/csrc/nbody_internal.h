@@ -72,8 +72,8 @@ struct Layout {
       off_mom64, off_nodeA, off_nodeB, off_gbegin, off_gcount, off_gbox,
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
-      off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref;
-  int64_t frontier2_cap = 0;  // retry pass: power of two >= 2 n
+      off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot;
+  int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   size_t total = 0;
 };
@@ -115,6 +115,9 @@ struct Ptrs {
   float *mlpm, *mlpv, *mlpg;  // Adam moments, gradient + loss (training)
   float *mlppart;       // per-wavefront gradient shares
   uint32_t *gref;       // per group: list length of its first walk on this tree (0: none)
+  uint32_t *sysoff;     // batch: system offsets [kMaxSystems + 1]
+  double4 *sysbox;      // batch: per system root cube lo x, y, z, side L
+  uint32_t *groot;      // batch: per group the walk's root cell
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
@@ -131,8 +134,15 @@ void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
                  uint64_t **keys_out, uint32_t **vals_out);
 void launch_gather(const float *x, const float *y, const float *z, const float *m,
                    const uint32_t *perm, int64_t n, float4 *xyzm, hipStream_t st);
+// r > 0: a batch of nsys systems (cells above level r always split, groups
+// at level r or deeper, per-group walk roots in P.groot)
 void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
-                  int group_merge, const Ptrs &P, const Layout &L, hipStream_t st);
+                  int group_merge, int nsys, int r, const Ptrs &P, const Layout &L,
+                  hipStream_t st);
+// batch keys into P.keysA / P.valsA from P.sysoff; per-system cubes to P.sysbox
+void launch_sys_keys(const float *x, const float *y, const float *z, int64_t n, int nsys,
+                     int r, const Ptrs &P, hipStream_t st);
+constexpr int kMaxSystems = 4096;
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L,
                     hipStream_t st);
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
@@ -150,6 +160,7 @@ struct WalkCfg {
   bool hash;      // record the per-group entry hash
   int64_t frontier2_cap;
   int retry_waves;
+  bool batch;     // per-group roots (several systems in one tree)
 };
 // enqueue the walk kernel (the queue head must already be zero)
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
@@ -176,7 +187,7 @@ void launch_digit_sort(int64_t n, int shift, const uint64_t *kin, const uint32_t
 
 // cost model of the walk queue
 constexpr int kMlpMaxHidden = 64;
-constexpr int kMlpMaxParams = 7 * kMlpMaxHidden + kMlpMaxHidden * kMlpMaxHidden + 1;
+constexpr int kMlpMaxParams = 8 + 7 * kMlpMaxHidden + kMlpMaxHidden * kMlpMaxHidden + 1;
 constexpr int kMlpWaves = 256;  // wavefronts of the gradient kernel
 bool mlp_hidden_ok(int H);
 int64_t mlp_nparams(int H);
@@ -187,6 +198,8 @@ void launch_mlp_grad(int H, const float *w, int64_t rows, const float4 *feat,
                      const float *target, float *partial, float *grad_loss, hipStream_t st);
 void launch_adam(int64_t np, float *w, const float *g, float *m, float *v, int step, float lr,
                  float b1, float b2, float eps, hipStream_t st);
+// w[0 .. 8): the model's input standardisation from the training rows
+void launch_mlp_standardize(const float4 *feat, int64_t rows, float *w, hipStream_t st);
 void launch_cost_features(int64_t n, const uint32_t *perm, const Ptrs &P, hipStream_t st);
 void launch_cost_after(int64_t n, bool queued, const uint32_t *perm, const Ptrs &P,
                        hipStream_t st);

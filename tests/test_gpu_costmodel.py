@@ -118,8 +118,10 @@ def test_orders_bit_identical_features_and_targets(nb, torch, orc):
         b, c = r.grp.begin[gi], r.grp.count[gi]
         prev[b:b + c] = r.gentries[gi]
     fo = orc.cost_features(r.grp, sx, sy, sz, sm, prev)
-    assert np.abs(feat.cpu().numpy() - fo).max() <= 1e-5
-    assert np.abs(target.cpu().numpy() - orc.cost_target(r.grp, r.gentries)).max() <= 1e-5
+    tol = lambda ref: 1e-5 * np.maximum(1.0, np.abs(ref))  # noqa: E731  FP32 log2 of FP64
+    assert np.all(np.abs(feat.cpu().numpy() - fo) <= tol(fo))
+    to = orc.cost_target(r.grp, r.gentries)
+    assert np.all(np.abs(target.cpu().numpy() - to) <= tol(to))
     # train a model on these statistics and walk in its order
     H = 32
     W = _dev(torch, I.mlp_init(nb.mlp_nparams(H), orc.mlp_fan_in(H), 7))
@@ -131,14 +133,16 @@ def test_orders_bit_identical_features_and_targets(nb, torch, orc):
     for a in (o1, o1b, o2):
         np.testing.assert_array_equal(a, plain)
     # the model's misses against the measured counts, next to the size-based
-    # estimate (log2 count + log2(1 + previous list length))
+    # estimate (log2 count + log2(1 + previous list length)) and a count-only
+    # estimate (log2 count + the best constant)
     t = target.cpu().numpy()
     f = feat.cpu().numpy()
     mae_model = np.abs(pred - t).mean()
     mae_size = np.abs(f[:, 0] + f[:, 3] - t).mean()
-    _say("loss %.3g -> %.3g; mean |log2 miss|: model %.3f, size-based %.3f"
-         % (losses[0], losses[-1], mae_model, mae_size))
-    assert mae_model < mae_size
+    mae_count = np.abs(f[:, 0] + np.median(t - f[:, 0]) - t).mean()
+    _say("loss %.3g -> %.3g; mean |log2 miss|: model %.3f, size-based %.3f, count-only %.3f"
+         % (losses[0], losses[-1], mae_model, mae_size, mae_count))
+    assert mae_model <= 0.25 and mae_model < 0.5 * mae_count
 
 
 def test_learned_order_timing_report(nb, torch, orc):

@@ -43,7 +43,7 @@ def test_fan_in_layout(orc):
     for H in (8, 32):
         fan = orc.mlp_fan_in(H)
         assert fan.shape == (orc.mlp_nparams(H),)
-        assert fan[0] == 4 and fan[-1] == H
+        assert fan[0] == 1 and fan[8] == 4 and fan[-1] == H
 
 
 class _G:

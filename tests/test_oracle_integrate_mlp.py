@@ -57,7 +57,7 @@ def test_mlp_gradient_finite_differences(orc):
     H = 8
     rng = np.random.default_rng(0)
     npar = orc.mlp_nparams(H)
-    assert npar == 4 * H + H + H * H + H + H + 1
+    assert npar == 8 + 4 * H + H + H * H + H + H + 1
     w = rng.normal(0, 0.5, npar)
     f = rng.normal(0, 1, (16, 4))
     t = rng.normal(0, 1, 16)
@@ -71,7 +71,10 @@ def test_mlp_gradient_finite_differences(orc):
         wp[k] += h
         wm[k] -= h
         num[k] = (orc.mlp_grad(wp, f, t, hidden=H)[0] - orc.mlp_grad(wm, f, t, hidden=H)[0]) / (2 * h)
-    np.testing.assert_allclose(g, num, rtol=1e-6, atol=1e-9)
+    # the standardisation entries are constants (gradient 0); the rest match
+    # central differences
+    np.testing.assert_array_equal(g[:8], 0.0)
+    np.testing.assert_allclose(g[8:], num[8:], rtol=1e-6, atol=1e-9)
 
 
 def test_mlp_forward_special_case(orc):
@@ -80,11 +83,30 @@ def test_mlp_forward_special_case(orc):
     H = 4
     npar = orc.mlp_nparams(H)
     w = np.zeros(npar)
+    w[4:8] = 1.0  # identity standardisation
     w[-1] = 2.5
     f = np.random.default_rng(1).normal(size=(5, 4))
     np.testing.assert_array_equal(orc.mlp_forward(w, f, hidden=H), np.full(5, 2.5))
-    w[4 * H:5 * H] = math.atanh(0.5)  # b1
-    w[5 * H:5 * H + H * H] = 1.0  # W2 = ones -> layer 2 pre-activation = H * 0.5
-    w[5 * H + H * H + H:5 * H + H * H + 2 * H] = 1.0  # W3 = ones
+    o = 8
+    w[o + 4 * H:o + 5 * H] = math.atanh(0.5)  # b1
+    w[o + 5 * H:o + 5 * H + H * H] = 1.0  # W2 = ones -> layer 2 pre-activation = H * 0.5
+    w[o + 5 * H + H * H + H:o + 5 * H + H * H + 2 * H] = 1.0  # W3 = ones
     y = orc.mlp_forward(w, f, hidden=H)
     np.testing.assert_allclose(y, 2.5 + H * math.tanh(H * 0.5), rtol=1e-14)
+
+
+def test_mlp_standardisation(orc):
+    # the standardised network equals the plain one on pre-standardised inputs
+    H = 8
+    rng = np.random.default_rng(3)
+    f = rng.normal(5.0, 3.0, (40, 4))
+    w = rng.normal(0, 0.5, orc.mlp_nparams(H))
+    w = orc.mlp_standardize(w, f)
+    np.testing.assert_allclose(w[:4], f.mean(0), rtol=1e-14)
+    np.testing.assert_allclose(w[4:8], 1 / f.std(0), rtol=1e-14)
+    z = (f - f.mean(0)) / f.std(0)
+    w_id = w.copy()
+    w_id[:4] = 0.0
+    w_id[4:8] = 1.0
+    np.testing.assert_allclose(orc.mlp_forward(w, f, hidden=H), orc.mlp_forward(w_id, z, hidden=H),
+                               rtol=1e-12, atol=1e-12)
