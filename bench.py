@@ -1,12 +1,14 @@
-"""Benchmark: leapfrog steps of the octree gravity hot path on one MI355X.
+"""Benchmark: block time steps of the octree gravity hot path on one MI355X.
 
 Workload (default): three-component galaxy, N = 2^23 equal-mass particles
 (80 % NFW halo truncated at 30 scale radii, 5 % Hernquist bulge, 15 %
 exponential disc with scale height 0.1 scale length), softening 2^-6, Eq. 2
-accuracy parameter 2^-9, kick-drift-kick steps of dt = 2^-7 with every
-particle active each step and the tree rebuild interval chosen by the
-library's build/walk timing rule. A step = kick, drift (FP64), tree rebuild
-or refit (keys, sort, build, moments), group boxes, group-wise walk, kick.
+accuracy parameter 2^-9, individual block time steps (dt_max = 2^-3, eta =
+0.025, so the finest occupied level steps by 2^-7) and the tree rebuild
+interval chosen by the library's measured-excess rule. A step = one smallest
+block step: opening kicks, drift of every particle (FP64), tree rebuild or
+refit (keys, sort, build, moments), group boxes, walk of the groups holding
+particles whose step ends, closing kicks and new levels.
 
 Prints one JSON line with s/step, interactions/s, the walk's fraction of the
 MI355X FP32 vector peak (22 Flop per interaction, rsqrt counted as 4), the
@@ -15,8 +17,10 @@ walk's roofline record and the CPU oracle baseline on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,6 +36,26 @@ FP32_NONPACKED_TFLOPS = 78.6
 
 def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_walk_galaxy_2e23_traffic.md")
+WALK_SOURCE = os.path.join(ROOT, "paper_1811_02761_amd", "csrc", "k_walk.hip")
+
+
+def walk_traffic():
+    """HBM bytes per k_walk launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's reading), or None
+    when the summary is missing or was taken on another walk source."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        src = hashlib.sha1(open(WALK_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m1 = re.search(r"walk_source_sha1:\s*([0-9a-f]{40})", text)
+    m2 = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m1 and m2) or m1.group(1) != src:
+        return None
+    return float(m2.group(1))
 
 
 def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_frac=1.0,
@@ -296,7 +320,8 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": walk_traffic(),
+            "traffic_unit": "bytes per launch",
         },
         "cpu_baseline": cpu,
     }

@@ -506,9 +506,11 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   }
   const bool use_queue = queued || mode != 0;
   launch_fill_u32(&P.sc->queue_head, 0u, 1, ctx->st);
+  const WalkCfg wc = walk_cfg(ctx, boot, use_queue);
   const int sp = span_begin(ctx, 1);
-  launch_walk(walk_cfg(ctx, boot, use_queue), ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
+  launch_walk(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
   span_end(ctx, sp);
+  launch_walk_retry(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
   span_stats(ctx, sp, use_queue);
   span_done(ctx, sp);
   ctx->last_queued = use_queue;

@@ -180,8 +180,7 @@ __device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t c
 }
 
 template <bool kComp, bool kHash>
-__global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
-  HIP_DYNAMIC_SHARED(float4, lds_list)
+__device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   const uint32_t wv = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   // LDS: per wave a list tile, then per wave the chunk's owner table
@@ -408,6 +407,20 @@ __global__ __launch_bounds__(1024) void k_walk_stat(DevScalars *__restrict__ sc,
   }
 }
 
+// The walk, and its retry pass as a kernel of its own (so that profiles and
+// the walk timing see the main pass alone).
+template <bool kComp, bool kHash>
+__global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
+  HIP_DYNAMIC_SHARED(float4, lds_list)
+  walk_body<kComp, kHash>(a, lds_list);
+}
+
+template <bool kComp, bool kHash>
+__global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk_retry(WalkArgs a) {
+  HIP_DYNAMIC_SHARED(float4, lds_list)
+  walk_body<kComp, kHash>(a, lds_list);
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -436,8 +449,9 @@ void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
                      P.xyzm, perm, axo, ayo, azo, delta_acc, P.gbox);
 }
 
-void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, float *ay,
-                 float *az, const Ptrs &P, hipStream_t st) {
+namespace {
+WalkArgs walk_args(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, float *ay,
+                   float *az, const Ptrs &P) {
   WalkArgs a;
   a.nodeA = P.nodeA;
   a.nodeB = P.nodeB;
@@ -464,39 +478,53 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   a.tile = (uint32_t)c.list_tile;
   a.fmask = (uint32_t)c.frontier_cap - 1u;
   a.bootstrap = c.bootstrap;
+  return a;
+}
+
+// per wave: list tile + padding (16 B/entry) + owner table (64 x (16 + 4 + 4) B)
+size_t walk_lds(const WalkCfg &c) {
+  return (size_t)kWalkWavesPerWG * ((c.list_tile + kListPad) * sizeof(float4) + 64 * 24);
+}
+
+}  // namespace
+
+#define NB_WALK_LAUNCH(KERNEL, c, grid, lds, st, w)                           \
+  do {                                                                         \
+    const dim3 block_(64 * kWalkWavesPerWG);                                   \
+    if ((c).compensated) {                                                     \
+      if ((c).hash)                                                            \
+        hipLaunchKernelGGL((KERNEL<true, true>), grid, block_, lds, st, w);    \
+      else                                                                     \
+        hipLaunchKernelGGL((KERNEL<true, false>), grid, block_, lds, st, w);   \
+    } else {                                                                   \
+      if ((c).hash)                                                            \
+        hipLaunchKernelGGL((KERNEL<false, true>), grid, block_, lds, st, w);   \
+      else                                                                     \
+        hipLaunchKernelGGL((KERNEL<false, false>), grid, block_, lds, st, w);  \
+    }                                                                          \
+  } while (0)
+
+void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, float *ay,
+                 float *az, const Ptrs &P, hipStream_t st) {
+  const WalkArgs a = walk_args(c, perm, n, ax, ay, az, P);
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
-  // per wave: list tile + padding (16 B/entry) + owner table (64 x (16 + 4 + 4) B)
-  const size_t lds =
-      (size_t)kWalkWavesPerWG * ((c.list_tile + kListPad) * sizeof(float4) + 64 * 24);
-  auto launch = [&](const WalkArgs &w, dim3 grid) {
-    const dim3 block(64 * kWalkWavesPerWG);
-    if (c.compensated) {
-      if (c.hash)
-        hipLaunchKernelGGL((k_walk<true, true>), grid, block, lds, st, w);
-      else
-        hipLaunchKernelGGL((k_walk<true, false>), grid, block, lds, st, w);
-    } else {
-      if (c.hash)
-        hipLaunchKernelGGL((k_walk<false, true>), grid, block, lds, st, w);
-      else
-        hipLaunchKernelGGL((k_walk<false, false>), grid, block, lds, st, w);
-    }
-  };
   launch_fill_u32(&P.sc->nretry, 0u, 1, st);
-  launch(a, dim3(blocks));
-  // retry pass: the groups that outgrew a small stack (frontier_cap below
-  // the bound), walked by a few wavefronts whose stack holds 512 cells per
-  // level of the deepest tree; a second overflow is reported (it cannot
-  // happen)
-  WalkArgs r = a;
+  NB_WALK_LAUNCH(k_walk, c, dim3(blocks), walk_lds(c), st, a);
+}
+
+// Retry pass: the groups that outgrew a small stack (frontier_cap below the
+// bound), walked by a few wavefronts whose stack holds 512 cells per level of
+// the deepest tree; a second overflow is reported (it cannot happen).
+void launch_walk_retry(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
+                       float *ay, float *az, const Ptrs &P, hipStream_t st) {
+  WalkArgs r = walk_args(c, perm, n, ax, ay, az, P);
   r.order = P.retry;
   r.qcount = &P.sc->nretry;
   r.retry = nullptr;
   r.frontier = P.frontier2;
   r.fmask = (uint32_t)c.frontier2_cap - 1u;
   launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
-  launch(r, dim3(c.retry_waves / kWalkWavesPerWG));
-  (void)n;
+  NB_WALK_LAUNCH(k_walk_retry, c, dim3(c.retry_waves / kWalkWavesPerWG), walk_lds(c), st, r);
 }
 
 }  // namespace nb

@@ -162,9 +162,12 @@ struct WalkCfg {
   int retry_waves;
   bool batch;     // per-group roots (several systems in one tree)
 };
-// enqueue the walk kernel (the queue head must already be zero)
+// enqueue the walk kernel (the queue head must already be zero), then its
+// retry pass for groups whose stack overflowed
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
                  float *ay, float *az, const Ptrs &P, hipStream_t st);
+void launch_walk_retry(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
+                       float *ay, float *az, const Ptrs &P, hipStream_t st);
 void launch_direct(int64_t n, const float *x, const float *y, const float *z,
                    const float *m, float G, float eps, float *ax, float *ay,
                    float *az, hipStream_t st);

@@ -1,0 +1,173 @@
+"""GPU parity of batched independent systems (one tree, one walk) and of
+graph-captured steps, through the C ABI.
+
+Batch: keys, permutation, cells, groups, walk roots, lists and entry hashes
+bit-exact against the oracle's batch; forces under the tree-parity rule (the
+conditioning A_i taken within each system); and bit-identical to running each
+system on its own. Graph: every replay of the captured step equals the eager
+step bit for bit, with eager work and synchronisations between replays."""
+import sys
+
+import numpy as np
+import pytest
+
+import nbody_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def nb(torch):
+    import paper_1811_02761_amd as nb
+
+    nb.lib()
+    return nb
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _batch(n_sys, seed, lo, hi):
+    ps = I.cluster_batch(n_sys, seed, log2_min=lo, log2_max=hi)
+    off = np.concatenate([[0], np.cumsum([p.n for p in ps])]).astype(np.int64)
+    cat = lambda k: np.ascontiguousarray(np.concatenate([p.f32()[k] for p in ps]))  # noqa: E731
+    return ps, off, cat(0), cat(1), cat(2), cat(6)
+
+
+def _calc(nb, torch, ctx, x, y, z, m, a_old):
+    X, Y, Z, M = (_dev(torch, a) for a in (x, y, z, m))
+    ctx.build_tree(X, Y, Z, M)
+    ao = None if a_old is None else tuple(_dev(torch, a_old[:, k]) for k in range(3))
+    acc = ctx.calc_acc(ao)
+    ctx.sync()
+    return np.stack([_np(a) for a in acc], 1)
+
+
+@pytest.mark.parametrize("n_sys,seed,lo,hi", [(9, 5, 7.0, 10.5), (64, 4, 8.0, 12.0)])
+def test_batch_matches_oracle_and_separate_runs(nb, torch, orc, n_sys, seed, lo, hi):
+    ps, off, x, y, z, m = _batch(n_sys, seed, lo, hi)
+    n = x.shape[0]
+    _say("batch", n_sys, "systems", n, "particles")
+    params = nb.Params(checks=1)
+    ctx = nb.Context(params, n_max=n)
+    ctx.set_systems(off)
+    a0 = _calc(nb, torch, ctx, x, y, z, m, None)
+    r0 = orc.tree_forces(x, y, z, m, a_old=None, systems=off, group_merge=params.group_merge)
+    a_old = r0.acc.astype(np.float32)
+    a1 = _calc(nb, torch, ctx, x, y, z, m, a_old)
+    r = orc.tree_forces(x, y, z, m, a_old=a_old, systems=off, group_merge=params.group_merge)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.KEYS)), r.keys_sorted)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.PERM)).astype(np.int64), r.perm)
+    box = _np(ctx.export(nb.X.SYSBOX)).reshape(-1, 4)
+    for s in range(n_sys):
+        a, b = off[s], off[s + 1]
+        np.testing.assert_array_equal(box[s], orc.root_cube(x[a:b], y[a:b], z[a:b]))
+    c = r.cells
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.LEVEL)), c.level)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.PCOUNT)), c.pcount)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.FCHILD)), c.first_child)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.GBEGIN)).astype(np.int64), r.grp.begin)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.GCOUNT)).astype(np.int64), r.grp.count)
+    roots = np.flatnonzero(c.level == orc.system_digits(n_sys))
+    sys_of = np.searchsorted(off, r.grp.begin, side="right") - 1
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.GROOT)).astype(np.int64), roots[sys_of])
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.GENTRIES)).astype(np.int64), r.gentries)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.GHASH)), r.ghash)
+    A = np.concatenate([orc.direct(np.stack([x[a:b], y[a:b], z[a:b]], 1), m[a:b], want_aabs=True)[1]
+                        for a, b in zip(off[:-1], off[1:])])
+    et = np.linalg.norm(a1 - r.acc, axis=1) / A
+    e = np.linalg.norm(a1 - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+    _say("  max e~ %.3g p99.9 e %.3g" % (et.max(), np.percentile(e, 99.9)))
+    assert et.max() <= 1e-5 and np.percentile(e, 99.9) <= 1e-5
+    # each system alone gives the same bits (when no single-system cell needs
+    # more than 21 - r levels)
+    r_dig = orc.system_digits(n_sys)
+    for s in range(n_sys):
+        a, b = off[s], off[s + 1]
+        rs = orc.tree_forces(x[a:b], y[a:b], z[a:b], m[a:b], a_old=None)
+        if (rs.cells.level[rs.cells.n_child > 0] >= 21 - r_dig).any():
+            continue
+        cs = nb.Context(params, n_max=b - a)
+        s0 = _calc(nb, torch, cs, x[a:b], y[a:b], z[a:b], m[a:b], None)
+        s1 = _calc(nb, torch, cs, x[a:b], y[a:b], z[a:b], m[a:b], a_old[a:b])
+        np.testing.assert_array_equal(s0, a0[a:b])
+        np.testing.assert_array_equal(s1, a1[a:b])
+
+
+def _state_arrays(st):
+    return [_np(t) for t in (st.x, st.y, st.z, st.vx, st.vy, st.vz, st.ax, st.ay, st.az)]
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_graph_replay_equals_eager(nb, torch, batch):
+    if batch:
+        ps, off, _, _, _, _ = _batch(16, 8, 8.0, 11.0)
+        pos = np.concatenate([p.pos for p in ps])
+        vel = np.concatenate([p.vel for p in ps])
+        mass = np.concatenate([p.mass for p in ps])
+    else:
+        g = I.plummer(20000, 12)
+        pos, vel, mass = g.pos, g.vel, g.mass
+    n = mass.shape[0]
+    dt = 2.0 ** -7
+    eager_ctx = nb.Context(nb.Params(), n_max=n)
+    graph_ctx = nb.Context(nb.Params(), n_max=n)
+    if batch:
+        eager_ctx.set_systems(off)
+        graph_ctx.set_systems(off)
+    se = nb.State.from_numpy(pos, vel, mass, dt=dt, rebuild_interval=2)
+    sg = nb.State.from_numpy(pos, vel, mass, dt=dt, rebuild_interval=2)
+    for rep in range(4):
+        eager_ctx.step(se, 1)
+        graph_ctx.step_graph(sg, 1)
+        eager_ctx.sync()
+        graph_ctx.sync()
+        # eager work on the device between replays
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+        for u, v in zip(_state_arrays(se), _state_arrays(sg)):
+            np.testing.assert_array_equal(u, v)
+    # several replays in one call
+    eager_ctx.step(se, 3)
+    graph_ctx.step_graph(sg, 3)
+    graph_ctx.sync()
+    for u, v in zip(_state_arrays(se), _state_arrays(sg)):
+        np.testing.assert_array_equal(u, v)
+    assert se.t == sg.t
+
+
+def test_autotuner_picks_a_measured_configuration(nb, torch):
+    from paper_1811_02761_amd import autotune
+
+    ps, off, x, y, z, m = _batch(16, 9, 9.0, 13.0)
+    best, table = autotune.autotune(x, y, z, m, nb.Params(), systems=off, reps=2,
+                                    tiles=(128, 192), waves=(24, 32), group_max=(32, 64))
+    _say("autotuner:", best, "of", len(table))
+    assert len(table) == 8 and all(r["walk_ms"] > 0 for r in table)
+    fastest = min(table, key=lambda r: r["walk_ms"])
+    assert (best.list_tile, best.waves_per_cu, best.group_max) == \
+        (fastest["list_tile"], fastest["waves_per_cu"], fastest["group_max"])
+    # tile and wave count never change the results
+    outs = {}
+    for r in table:
+        if r["group_max"] == best.group_max:
+            outs[(r["list_tile"], r["waves_per_cu"])] = r["acc_digest"]
+    assert len(set(outs.values())) == 1
