@@ -196,6 +196,7 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_sysoff = take(4 * (size_t)(kMaxSystems + 1));
   L.off_sysbox = take(32 * (size_t)kMaxSystems);
   L.off_groot = take(4 * N);
+  L.off_inv = take(4 * N);
   L.total = o;
   return L;
 }
@@ -260,6 +261,7 @@ Ptrs carve(void *base, const Layout &L) {
   P.sysoff = reinterpret_cast<uint32_t *>(b + L.off_sysoff);
   P.sysbox = reinterpret_cast<double4 *>(b + L.off_sysbox);
   P.groot = reinterpret_cast<uint32_t *>(b + L.off_groot);
+  P.inv = reinterpret_cast<uint32_t *>(b + L.off_inv);
   return P;
 }
 
@@ -470,6 +472,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
   launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
               &ks, &pm);
   launch_gather(x, y, z, m, pm, n, P.xyzm, ctx->st);
+  launch_invert(pm, n, P.inv, ctx->st);
   launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, ctx->nsys,
                ctx->sys_r, P, ctx->L, ctx->st);
   launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
@@ -488,6 +491,19 @@ nbody_status do_refit(nbody_ctx *ctx, const float *x, const float *y, const floa
   launch_gather(x, y, z, m, ctx->perm, ctx->n, ctx->P.xyzm, ctx->st);
   launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, ctx->st);
   return hip_status();
+}
+
+// Refit after a drift that wrote the key-ordered positions itself.
+nbody_status do_refit_sorted(nbody_ctx *ctx) {
+  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, ctx->st);
+  return hip_status();
+}
+
+// Drift output: the key-ordered array of the current tree when the step
+// refits it (same particle set), else the caller-order FP32 image.
+SortedOut drift_out(const nbody_ctx *ctx, const nbody_state *st, bool rebuild) {
+  if (rebuild || !ctx->have_tree || ctx->n != st->n) return SortedOut{nullptr, nullptr, nullptr};
+  return SortedOut{ctx->P.xyzm, ctx->P.inv, st->m};
 }
 
 // queued: walk only the groups order[0 .. nqueue) (block steps). With a
@@ -730,13 +746,14 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     if (ctx->n != n) rebuild = true;
     launch_blk_begin(sc, ctx->st);
     launch_blk_open_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay,
-                          st->az, st->level, st->dt, sc, x32, ctx->st);
+                          st->az, st->level, st->dt, sc, x32, drift_out(ctx, st, rebuild),
+                          ctx->st);
     if (rebuild) {
       if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
     } else {
-      if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
+      if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
     }
     launch_blk_queue(n, st->level, ctx->perm, ctx->P, ctx->st);
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, tx, ty, tz, true)) != NBODY_OK) return s;
@@ -790,13 +807,14 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
                                             : rebuild_due(ctx, 64);
     if (ctx->n != n) rebuild = true;
     launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
-    launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32, ctx->st);
+    launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32,
+                 drift_out(ctx, st, rebuild), ctx->st);
     if (rebuild) {
       if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
     } else {
-      if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
+      if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
     }
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
@@ -1063,11 +1081,12 @@ nbody_status step_body(nbody_ctx *ctx, nbody_state *st, bool rebuild) {
   float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
   const float hdt = (float)(0.5 * st->dt);
   launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
-  launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32, ctx->st);
+  launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32,
+               drift_out(ctx, st, rebuild), ctx->st);
   if (rebuild) {
     if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
   } else {
-    if ((s = do_refit(ctx, x32, y32, z32, st->m)) != NBODY_OK) return s;
+    if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
   }
   if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
     return s;

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_open_drift(
     float *__restrict__ vx, float *__restrict__ vy, float *__restrict__ vz,
     const float *__restrict__ ax, const float *__restrict__ ay, const float *__restrict__ az,
     const int8_t *__restrict__ level, BlkTables t, const DevScalars *__restrict__ sc,
-    float *__restrict__ x32) {
+    float *__restrict__ x32, SortedOut so) {
   const long long t0 = sc->tick0, t1 = sc->tick;
   const double dt = (double)(t1 - t0) * t.dt_tick;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -174,9 +174,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_open_drift(
     x[i] = nx;
     y[i] = ny;
     z[i] = nz;
-    x32[i] = (float)nx;
-    x32[n + i] = (float)ny;
-    x32[2 * n + i] = (float)nz;
+    store_position(i, n, (float)nx, (float)ny, (float)nz, x32, so);
   }
 }
 
@@ -296,13 +294,13 @@ void launch_blk_begin(DevScalars *sc, hipStream_t st) {
 void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx, float *vy,
                            float *vz, const float *ax, const float *ay, const float *az,
                            const int8_t *level, double dt_max, const DevScalars *sc,
-                           float *x32, hipStream_t st) {
+                           float *x32, SortedOut so, hipStream_t st) {
   BlockCfg c{dt_max, 1.0, 1.0f, 0, kTickBits};
   int64_t g = cdiv(n, 4 * kBlkThreads);  // a few particles per thread
   if (g > 16384) g = 16384;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_blk_open_drift, dim3((unsigned)g), dim3(kBlkThreads), 0, st, n, x, y,
-                     z, vx, vy, vz, ax, ay, az, level, make_tables(c), sc, x32);
+                     z, vx, vy, vz, ax, ay, az, level, make_tables(c), sc, x32, so);
 }
 
 void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, const Ptrs &P,

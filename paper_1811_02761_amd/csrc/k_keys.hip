@@ -217,6 +217,13 @@ __global__ __launch_bounds__(256) void k_sys_keys(const float *__restrict__ x,
   }
 }
 
+__global__ __launch_bounds__(256) void k_invert(const uint32_t *__restrict__ perm, int64_t n,
+                                                uint32_t *__restrict__ inv) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    inv[perm[s]] = (uint32_t)s;
+}
+
 __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ x,
                                                 const float *__restrict__ y,
                                                 const float *__restrict__ z,
@@ -250,6 +257,10 @@ void launch_sys_keys(const float *x, const float *y, const float *z, int64_t n, 
                      P.sc);
   hipLaunchKernelGGL(k_sys_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z, n,
                      P.sysoff, nsys, r, P.sysbox, P.keysA, P.valsA);
+}
+
+void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t st) {
+  hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, perm, n, inv);
 }
 
 void launch_keys(const float *x, const float *y, const float *z, int64_t n,

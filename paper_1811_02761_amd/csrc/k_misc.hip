@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_drift(int64_t n, double *__restrict__ x
                                                const float *__restrict__ vx,
                                                const float *__restrict__ vy,
                                                const float *__restrict__ vz, double dt,
-                                               float *__restrict__ x32) {
+                                               float *__restrict__ x32, SortedOut so) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double dx = (double)vx[i] * dt, dy = (double)vy[i] * dt, dz = (double)vz[i] * dt;
@@ -75,9 +75,7 @@ __global__ __launch_bounds__(256) void k_drift(int64_t n, double *__restrict__ x
     x[i] = nx;
     y[i] = ny;
     z[i] = nz;
-    x32[i] = (float)nx;
-    x32[n + i] = (float)ny;
-    x32[2 * n + i] = (float)nz;
+    store_position(i, n, (float)nx, (float)ny, (float)nz, x32, so);
   }
 }
 
@@ -102,10 +100,10 @@ void launch_kick(int64_t n, float *vx, float *vy, float *vz, const float *ax,
 }
 
 void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
-                  const float *vy, const float *vz, double dt, float *x32,
+                  const float *vy, const float *vz, double dt, float *x32, SortedOut so,
                   hipStream_t st) {
   hipLaunchKernelGGL(k_drift, dim3(grid_1d(n)), dim3(256), 0, st, n, x, y, z, vx, vy, vz,
-                     dt, x32);
+                     dt, x32, so);
 }
 
 }  // namespace nb

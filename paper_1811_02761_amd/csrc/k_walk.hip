@@ -156,6 +156,28 @@ __device__ __forceinline__ void eq1_term(const float4 e, float4 pi, float eps2, 
   f = mr * rinv2;
 }
 
+// The stream count S is a template constant: the trip count and the LDS
+// offsets of one trip (u * S entries past the trip's base) are then uniform
+// and immediate.
+template <bool kComp, uint32_t S>
+__device__ __forceinline__ void flush_tile_s(const float4 *__restrict__ list, uint32_t padded,
+                                             uint32_t stream, float4 pi, float eps2,
+                                             Acc3<kComp> &acc) {
+  constexpr uint32_t step = S * kFlushUnroll;
+  const float4 *p = list + stream;
+  for (uint32_t j0 = 0; j0 < padded; j0 += step) {
+    float4 e[kFlushUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kFlushUnroll; ++u) e[u] = p[j0 + u * S];
+#pragma unroll
+    for (uint32_t u = 0; u < kFlushUnroll; ++u) {
+      float dx, dy, dz, f;
+      eq1_term(e[u], pi, eps2, dx, dy, dz, f);
+      acc.add(dx, dy, dz, f);
+    }
+  }
+}
+
 template <bool kComp>
 __device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t cnt,
                                            uint32_t lane, uint32_t stream, uint32_t S,
@@ -166,17 +188,15 @@ __device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t c
   // region; slots [cnt, cnt + kListPad) are free
   list[cnt + (lane & (kListPad - 1))] = make_float4(0.f, 0.f, 0.f, 0.f);
   __builtin_amdgcn_wave_barrier();
-  for (uint32_t j0 = stream; j0 < padded; j0 += step) {
-    float4 e[kFlushUnroll];
-#pragma unroll
-    for (uint32_t u = 0; u < kFlushUnroll; ++u) e[u] = list[j0 + u * S];
-#pragma unroll
-    for (uint32_t u = 0; u < kFlushUnroll; ++u) {
-      float dx, dy, dz, f;
-      eq1_term(e[u], pi, eps2, dx, dy, dz, f);
-      acc.add(dx, dy, dz, f);
-    }
-  }
+  // S is wave-uniform: these branches are not lane-predicated
+  if (S == 1)
+    flush_tile_s<kComp, 1>(list, padded, stream, pi, eps2, acc);
+  else if (S == 2)
+    flush_tile_s<kComp, 2>(list, padded, stream, pi, eps2, acc);
+  else if (S == 4)
+    flush_tile_s<kComp, 4>(list, padded, stream, pi, eps2, acc);
+  else
+    flush_tile_s<kComp, 8>(list, padded, stream, pi, eps2, acc);
 }
 
 template <bool kComp, bool kHash>
@@ -363,17 +383,27 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   }
 }
 
-// One workgroup: interactions of the walked groups now and on their first
-// walk of this tree (recorded here), summed in a fixed order.
-__global__ __launch_bounds__(1024) void k_walk_stat(DevScalars *__restrict__ sc,
-                                                    const uint32_t *__restrict__ order,
-                                                    const uint32_t *__restrict__ gcount,
-                                                    const uint32_t *__restrict__ gent,
-                                                    uint32_t *__restrict__ gref) {
-  __shared__ unsigned long long s_cur[16], s_ref[16];
+__global__ void k_walk_stat_zero(DevScalars *sc) {
+  if (threadIdx.x == 0) {
+    sc->wstat.ngroup = sc->ngroup;
+    sc->wstat.queued = 0;
+    sc->wstat.inter = 0;
+    sc->wstat.inter_ref = 0;
+  }
+}
+
+// Interactions of the walked groups now and on their first walk of this
+// tree (recorded here); integer sums, so the atomics are exact.
+__global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
+                                                   const uint32_t *__restrict__ order,
+                                                   const uint32_t *__restrict__ gcount,
+                                                   const uint32_t *__restrict__ gent,
+                                                   uint32_t *__restrict__ gref) {
+  __shared__ unsigned long long s_cur[4], s_ref[4];
   const uint32_t nq = order ? sc->nqueue : sc->ngroup;
   unsigned long long cur = 0, ref = 0;
-  for (uint32_t q = threadIdx.x; q < nq; q += blockDim.x) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq;
+       q += gridDim.x * blockDim.x) {
     const uint32_t g = order ? order[q] : q;
     const uint32_t e = gent[g], c = gcount[g];
     if (e == 0xffffffffu) continue;
@@ -400,10 +430,9 @@ __global__ __launch_bounds__(1024) void k_walk_stat(DevScalars *__restrict__ sc,
       a += s_cur[w];
       b += s_ref[w];
     }
-    sc->wstat.ngroup = sc->ngroup;
-    sc->wstat.queued = nq;
-    sc->wstat.inter = a;
-    sc->wstat.inter_ref = b;
+    atomicAdd(&sc->wstat.inter, a);
+    atomicAdd(&sc->wstat.inter_ref, b);
+    if (blockIdx.x == 0) sc->wstat.queued = nq;
   }
 }
 
@@ -435,7 +464,8 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
 }
 
 void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st) {
-  hipLaunchKernelGGL(k_walk_stat, dim3(1), dim3(1024), 0, st, P.sc, queued ? P.order : nullptr,
+  hipLaunchKernelGGL(k_walk_stat_zero, dim3(1), dim3(64), 0, st, P.sc);
+  hipLaunchKernelGGL(k_walk_stat, dim3(256), dim3(256), 0, st, P.sc, queued ? P.order : nullptr,
                      P.gcount, P.gent, P.gref);
 }
 

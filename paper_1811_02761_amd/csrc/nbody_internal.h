@@ -72,7 +72,8 @@ struct Layout {
       off_mom64, off_nodeA, off_nodeB, off_gbegin, off_gcount, off_gbox,
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
-      off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot;
+      off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
+      off_inv;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   size_t total = 0;
@@ -118,6 +119,7 @@ struct Ptrs {
   uint32_t *sysoff;     // batch: system offsets [kMaxSystems + 1]
   double4 *sysbox;      // batch: per system root cube lo x, y, z, side L
   uint32_t *groot;      // batch: per group the walk's root cell
+  uint32_t *inv;        // caller index -> sorted position of the current tree
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
@@ -173,9 +175,30 @@ void launch_direct(int64_t n, const float *x, const float *y, const float *z,
                    float *az, hipStream_t st);
 void launch_kick(int64_t n, float *vx, float *vy, float *vz, const float *ax,
                  const float *ay, const float *az, float hdt, hipStream_t st);
+// Where a drift puts the FP32 image of the new positions: with xyzm set,
+// straight into the key-ordered (x, y, z, m) array of the current tree
+// through inv (caller index -> sorted position), which a refit then uses as
+// is; otherwise into x32[3][n] in caller order (for a rebuild).
+struct SortedOut {
+  float4 *xyzm;
+  const uint32_t *inv;
+  const float *m;
+};
+__device__ __forceinline__ void store_position(int64_t i, int64_t n, float fx, float fy,
+                                               float fz, float *x32, const SortedOut &so) {
+  if (so.xyzm) {
+    so.xyzm[so.inv[i]] = make_float4(fx, fy, fz, so.m[i]);
+  } else {
+    x32[i] = fx;
+    x32[n + i] = fy;
+    x32[2 * n + i] = fz;
+  }
+}
 void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
-                  const float *vy, const float *vz, double dt, float *x32,
+                  const float *vy, const float *vz, double dt, float *x32, SortedOut so,
                   hipStream_t st);
+// inv[perm[s]] = s
+void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 // exclusive scan of rows[r][0 .. len) for r < nrows, row totals to totals[r]
 void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
@@ -231,7 +254,7 @@ void launch_blk_begin(DevScalars *sc, hipStream_t st);
 void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx, float *vy,
                            float *vz, const float *ax, const float *ay, const float *az,
                            const int8_t *level, double dt_max, const DevScalars *sc,
-                           float *x32, hipStream_t st);
+                           float *x32, SortedOut so, hipStream_t st);
 // walk queue = the groups holding a particle active at tick (group order)
 void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, const Ptrs &P,
                       hipStream_t st);
