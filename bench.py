@@ -10,9 +10,15 @@ block step: opening kicks, drift of every particle (FP64), tree rebuild or
 refit (keys, sort, build, moments), group boxes, walk of the groups holding
 particles whose step ends, closing kicks and new levels.
 
+After the warm-up the same state is stepped twice on fresh contexts: with the
+plain (Morton) walk queue, which gives `value`, and with the queue ordered by
+the learned cost model (trained on the device from the warm-up's last walk);
+forces, and so the two trajectories, are bit-identical.
+
 Prints one JSON line with s/step, interactions/s, the walk's fraction of the
 MI355X FP32 vector peak (22 Flop per interaction, rsqrt counted as 4), the
-walk's roofline record and the CPU oracle baseline on a bounded sample.
+walk's roofline record, the plain-vs-learned comparison and the CPU oracle
+baseline on a bounded sample.
 """
 from __future__ import annotations
 
@@ -124,55 +130,46 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
     }
 
 
-def plain_vs_learned(ctx, nb, torch, a_cur, ref_out, train_steps, hidden=32, reps=3):
-    """All-active walks of the same tree in plain (Morton) and learned queue
-    order. The model is trained on the device, by the library's kernels, on
-    statistics the walk itself records (features before, interaction counts
-    after an all-active walk at this state)."""
+def train_model(ctx, nb, torch, steps, hidden=32):
+    """Train the queue's cost model on the device, by the library's kernels,
+    on the statistics the last walk recorded (features before it, interaction
+    counts after it)."""
     import nbody_inputs as I
 
-    ctx.set_order(1)
-    ctx.calc_acc(a_cur)  # members learn their list length
-    ctx.calc_acc(a_cur)  # features use it; targets measured
-    ctx.sync()
     feat = ctx.export(nb.X.FEAT).reshape(-1, 4).contiguous()
     target = ctx.export(nb.X.TARGET).contiguous()
     w = torch.as_tensor(I.mlp_init(nb.mlp_nparams(hidden), nb.mlp_fan_in(hidden), 1),
                         device="cuda")
     t0 = time.perf_counter()
-    losses = ctx.train_cost_model(hidden, w, feat, target, train_steps, 1e-2)
+    losses = ctx.train_cost_model(hidden, w, feat, target, steps, 1e-2)
     t_train = time.perf_counter() - t0
-    ctx.set_cost_model(hidden, w)
-    ms = {0: [], 2: []}
-    same = True
-    for _ in range(reps):
-        for order in (0, 2):
-            ctx.set_order(order)
-            ctx.timing(True)
-            out = ctx.calc_acc(a_cur)
-            ctx.sync()
-            ms[order].append(ctx.stats()["walk_ms_sum"])
-            same &= all(bool(torch.equal(u, v)) for u, v in zip(out, ref_out))
-    pred = ctx.export(nb.X.PRED).cpu().numpy()
+    pred = ctx.mlp_forward(hidden, w, feat).cpu().numpy()
     t = target.cpu().numpy()
     f = feat.cpu().numpy()
-    ctx.set_order(0)
-    res = {
-        "plain_walk_ms": min(ms[0]),
-        "learned_walk_ms": min(ms[2]),
-        "plain_over_learned": min(ms[0]) / min(ms[2]),
-        "forces_bit_identical": bool(same),
+    report = {
         "train_rows": int(t.shape[0]),
-        "train_steps": int(train_steps),
+        "train_steps": int(steps),
         "train_s": t_train,
         "train_loss_first_last": [float(losses[0]), float(losses[-1])],
         "mean_abs_log2_miss_model": float(np.abs(pred - t).mean()),
         "mean_abs_log2_miss_size_based": float(np.abs(f[:, 0] + f[:, 3] - t).mean()),
     }
-    log("plain vs learned: %.3f ms vs %.3f ms (x%.3f), bit-identical %s, misses %.3f vs %.3f"
-        % (res["plain_walk_ms"], res["learned_walk_ms"], res["plain_over_learned"], same,
-           res["mean_abs_log2_miss_model"], res["mean_abs_log2_miss_size_based"]))
-    return res
+    log("cost model: %d rows, loss %.3g -> %.3g in %.2f s, mean |log2 miss| %.3f (size-based %.3f)"
+        % (report["train_rows"], losses[0], losses[-1], t_train,
+           report["mean_abs_log2_miss_model"], report["mean_abs_log2_miss_size_based"]))
+    return {"hidden": hidden, "w": w, "report": report}
+
+
+def snapshot(st):
+    return {k: (getattr(st, k).clone() if getattr(st, k) is not None else None)
+            for k in ("x", "y", "z", "vx", "vy", "vz", "m", "ax", "ay", "az", "level")} | {
+        k: getattr(st, k) for k in ("t", "dt", "have_acc", "rebuild_interval", "eta",
+                                    "level_min", "level_max", "tick")}
+
+
+def restore(snap, nb):
+    d = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in snap.items()}
+    return nb.State(**d)
 
 
 def main():
@@ -218,23 +215,43 @@ def main():
                        list_tile=args.tile, frontier_cap=args.frontier,
                        group_max=args.group_max, leaf_max=args.leaf_max,
                        group_merge=args.group_merge)
-    ctx = nb.Context(params, n_max=args.n)
     block = not args.global_steps
     st = nb.State.from_numpy(gal.pos, gal.vel, gal.mass, dt=args.dt,
                              rebuild_interval=args.rebuild, block_steps=block, eta=args.eta)
+    # warm-up on a context of its own, in the size-based order (which makes the
+    # walk record the cost model's features and targets)
+    ctx0 = nb.Context(params, n_max=args.n)
+    ctx0.set_order(1)
     log("warmup %d steps" % args.warmup)
-    ctx.step(st, max(args.warmup, 1))
-    ctx.sync()
-    ctx.timing(True)
-    s0 = ctx.stats()
-    torch.cuda.synchronize()
-    log("timing %d steps" % args.steps)
-    t0 = time.perf_counter()
-    ctx.step(st, args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s1 = ctx.stats()
+    ctx0.step(st, max(args.warmup, 1))
+    ctx0.sync()
+    model = train_model(ctx0, nb, torch, args.learn_steps) if args.learn_steps else None
+    snap = snapshot(st)
+    del ctx0
+
+    def timed_run(order):
+        """From the warm-up state: 2 untimed steps (the members learn their
+        list lengths), then the timed steps. Forces do not depend on the
+        order, so both runs follow the same trajectory."""
+        s = restore(snap, nb)
+        ctx = nb.Context(params, n_max=args.n)
+        if order == 2:
+            ctx.set_cost_model(model["hidden"], model["w"])
+        ctx.set_order(order)
+        ctx.step(s, 2)
+        ctx.sync()
+        ctx.timing(True)
+        s_0 = ctx.stats()
+        torch.cuda.synchronize()
+        log("timing %d steps, queue order %d" % (args.steps, order))
+        t_0 = time.perf_counter()
+        ctx.step(s, args.steps)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t_1 = time.perf_counter()
+        return ctx, s, s_0, ctx.stats(), t_0, t_1
+
+    ctx, st, s0, s1, t0, t1 = timed_run(0)
     sec_per_step = (t1 - t0) / args.steps
     walks = s1["walk_calls"]
     walk_ms = s1["walk_ms_sum"] / max(walks, 1)
@@ -248,6 +265,21 @@ def main():
         "rebuilds %d, build %.3f ms, walk share of time %.2f"
         % (sec_per_step, walk_ms, walks, inter_per_walk, walk_frac, rebuilds,
            s1["build_ms_sum"] / max(s1["build_calls"], 1), walk_share))
+    learned = None
+    if model is not None:
+        ctx2, st2, u0, u1, v0, v1 = timed_run(2)
+        same = all(bool(torch.equal(a, b)) for a, b in
+                   zip((st.x, st.y, st.z, st.vx, st.vy, st.vz), (st2.x, st2.y, st2.z, st2.vx,
+                                                                 st2.vy, st2.vz)))
+        l_walk = u1["walk_ms_sum"] / max(u1["walk_calls"], 1)
+        learned = {"s_per_step": (v1 - v0) / args.steps, "walk_ms": l_walk,
+                   "plain_over_learned_step": sec_per_step / ((v1 - v0) / args.steps),
+                   "plain_over_learned_walk": walk_ms / l_walk,
+                   "states_bit_identical": bool(same), **model["report"]}
+        log("learned order: s/step %.4g (plain/learned x%.3f), walk %.3f ms (x%.3f), "
+            "states bit-identical %s" % (learned["s_per_step"], learned["plain_over_learned_step"],
+                                         l_walk, learned["plain_over_learned_walk"], same))
+        del ctx2, st2
     levels = None
     if block:
         levels = np.bincount(st.level.cpu().numpy(), minlength=11).tolist()
@@ -260,7 +292,7 @@ def main():
     s2 = ctx.stats()
     full_ms = s2["walk_ms_sum"] / max(s2["walk_calls"], 1)
     log("all-active walk %.3f ms, %.3g interactions" % (full_ms, s2["interactions_sum"]))
-    pvl = plain_vs_learned(ctx, nb, torch, a_cur, full, args.learn_steps) if args.learn_steps else None
+    del full
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -309,7 +341,7 @@ def main():
         "all_active_walk_ms": full_ms,
         "all_active_interactions": s2["interactions_sum"],
         "all_active_interactions_per_s": s2["interactions_sum"] / (full_ms * 1e-3),
-        "plain_vs_learned": pvl,
+        "plain_vs_learned": learned,
         "build_ms": s1["build_ms_sum"] / max(s1["build_calls"], 1),
         "rebuilds_in_timed_steps": rebuilds,
         "pct_fp32_vector_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,

@@ -47,6 +47,10 @@ struct nbody_ctx {
   bool last_queued = false;  // the last walk used the queue (block steps)
   int64_t queued_sum = 0, ngroup_sum = 0;  // groups walked / present, summed over walks
   int order = 0;       // queue order in use (params.order, or nbody_set_order)
+  // P.asort mirrors (in key order, with |a|) the x component array asort_src
+  // of the tree of epoch asort_epoch; set and kept within one nbody_step call
+  const float *asort_src = nullptr;
+  int64_t asort_epoch = -1;
   int nsys = 1, sys_r = 0;      // batch of independent systems (nbody_set_systems)
   // graph-captured steps (nbody_step_graph): one graph per step kind
   bool capturing = false;
@@ -197,6 +201,7 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_sysbox = take(32 * (size_t)kMaxSystems);
   L.off_groot = take(4 * N);
   L.off_inv = take(4 * N);
+  L.off_asort = take(16 * N);
   L.total = o;
   return L;
 }
@@ -262,6 +267,7 @@ Ptrs carve(void *base, const Layout &L) {
   P.sysbox = reinterpret_cast<double4 *>(b + L.off_sysbox);
   P.groot = reinterpret_cast<uint32_t *>(b + L.off_groot);
   P.inv = reinterpret_cast<uint32_t *>(b + L.off_inv);
+  P.asort = reinterpret_cast<float4 *>(b + L.off_asort);
   return P;
 }
 
@@ -499,6 +505,15 @@ nbody_status do_refit_sorted(nbody_ctx *ctx) {
   return hip_status();
 }
 
+// Within a step: mirror the state's accelerations in key order for the
+// current tree (after a rebuild, or at the first step of a call).
+void ensure_asort(nbody_ctx *ctx, const nbody_state *st) {
+  if (ctx->asort_src == st->ax && ctx->asort_epoch == ctx->epoch) return;
+  launch_asort_gather(ctx->perm, ctx->n, st->ax, st->ay, st->az, ctx->P.asort, ctx->st);
+  ctx->asort_src = st->ax;
+  ctx->asort_epoch = ctx->epoch;
+}
+
 // Drift output: the key-ordered array of the current tree when the step
 // refits it (same particle set), else the caller-order FP32 image.
 SortedOut drift_out(const nbody_ctx *ctx, const nbody_state *st, bool rebuild) {
@@ -513,7 +528,12 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
                      float *ax, float *ay, float *az, bool queued = false) {
   const bool boot = axo == nullptr;
   const Ptrs &P = ctx->P;
-  launch_group_bounds(axo, ayo, azo, ctx->perm, ctx->n, ctx->p.delta_acc, P, ctx->st);
+  const bool mirrored = axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
+  launch_group_bounds(axo, ayo, azo, mirrored ? P.asort : nullptr, ctx->perm, ctx->n,
+                      ctx->p.delta_acc, P, ctx->st);
+  // outputs over the mirrored array keep the mirror; other writes to it end it
+  const bool keep_mirror = mirrored && ax == axo;
+  if (!keep_mirror && ax && ax == ctx->asort_src) ctx->asort_src = nullptr;
   // the learned order needs an installed model; until then the queue is plain
   const int mode = (ctx->order == 2 && ctx->mlp_hidden == 0) ? 0 : ctx->order;
   if (mode != 0) {
@@ -522,7 +542,8 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   }
   const bool use_queue = queued || mode != 0;
   launch_fill_u32(&P.sc->queue_head, 0u, 1, ctx->st);
-  const WalkCfg wc = walk_cfg(ctx, boot, use_queue);
+  WalkCfg wc = walk_cfg(ctx, boot, use_queue);
+  wc.asort_out = keep_mirror;
   const int sp = span_begin(ctx, 1);
   launch_walk(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
   span_end(ctx, sp);
@@ -756,9 +777,10 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
     }
     launch_blk_queue(n, st->level, ctx->perm, ctx->P, ctx->st);
+    ensure_asort(ctx, st);
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, tx, ty, tz, true)) != NBODY_OK) return s;
     launch_blk_close(n, st->ax, st->ay, st->az, tx, ty, tz, st->vx, st->vy, st->vz,
-                     st->level, bc, sc, ctx->st);
+                     st->level, bc, ctx->P.asort, ctx->P.inv, sc, ctx->st);
     ctx->since_rebuild++;
     ctx->steps++;
     if ((s = hip_status()) != NBODY_OK) return s;
@@ -787,6 +809,7 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
        st->level_min > st->level_max || st->level_max > kTickBits || st->tick < 0))
     return NBODY_EINVAL;
   if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
+  ctx->asort_src = nullptr;  // the caller may have changed the state since the last call
   if (st->level) return step_block(ctx, st, n_steps);
   const int64_t n = st->n;
   float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
@@ -816,6 +839,7 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     } else {
       if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
     }
+    ensure_asort(ctx, st);
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
     launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
@@ -1088,9 +1112,11 @@ nbody_status step_body(nbody_ctx *ctx, nbody_state *st, bool rebuild) {
   } else {
     if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
   }
+  ensure_asort(ctx, st);
   if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
     return s;
   launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
+  if (ctx->capturing) ctx->asort_src = nullptr;  // the next captured step mirrors afresh
   return hip_status();
 }
 
@@ -1112,6 +1138,9 @@ nbody_status capture_step(nbody_ctx *ctx, nbody_state *st, int kind) {
   ctx->capturing = true;
   nbody_status s = NBODY_OK;
   hipGraph_t g = nullptr;
+  // a replay may follow changes to the state made between calls: every
+  // captured step mirrors the accelerations afresh
+  ctx->asort_src = nullptr;
   if (hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     s = NBODY_EHIP;
   } else {

@@ -235,7 +235,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
     int64_t n, float *__restrict__ ax, float *__restrict__ ay, float *__restrict__ az,
     const float *__restrict__ nax, const float *__restrict__ nay,
     const float *__restrict__ naz, float *__restrict__ vx, float *__restrict__ vy,
-    float *__restrict__ vz, int8_t *__restrict__ level, BlkTables t, DevScalars *sc) {
+    float *__restrict__ vz, int8_t *__restrict__ level, BlkTables t,
+    float4 *__restrict__ asort, const uint32_t *__restrict__ inv, DevScalars *sc) {
   const long long t1 = sc->tick;
   const int lo = max(t.level_min, align_level(t1));
   int kmax = 0;
@@ -253,6 +254,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
       vx[i] = vx[i] + kx;
       vy[i] = vy[i] + ky;
       vz[i] = vz[i] + kz;
+      asort[inv[i]] =
+          make_float4(a0, a1, a2, sqrt_rn(__builtin_fmaf(a2, a2, __builtin_fmaf(a1, a1, a0 * a0))));
       k = level_of(a0, a1, a2, t, lo);
       level[i] = (int8_t)k;
       ++cnt;
@@ -319,9 +322,10 @@ void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, cons
 
 void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
                       const float *nay, const float *naz, float *vx, float *vy, float *vz,
-                      int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st) {
+                      int8_t *level, const BlockCfg &c, float4 *asort, const uint32_t *inv,
+                      DevScalars *sc, hipStream_t st) {
   hipLaunchKernelGGL(k_blk_close, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, ax, ay, az,
-                     nax, nay, naz, vx, vy, vz, level, make_tables(c), sc);
+                     nax, nay, naz, vx, vy, vz, level, make_tables(c), asort, inv, sc);
 }
 
 }  // namespace nb

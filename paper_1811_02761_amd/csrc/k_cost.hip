@@ -94,11 +94,12 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ w
                                                      const float4 *__restrict__ feat,
                                                      float *__restrict__ y) {
   __shared__ float sw[mlp_np(H)];
+  const int64_t nr = rows_dev ? min(rows, (int64_t)*rows_dev) : rows;
+  if ((int64_t)blockIdx.x * blockDim.x >= nr) return;  // whole workgroup: no rows
   for (int i = threadIdx.x; i < mlp_np(H); i += blockDim.x) sw[i] = w[i];
   __syncthreads();
   const float *mu = sw, *is = sw + 4, *W1 = sw + 8, *b1 = W1 + 4 * H, *W2 = b1 + H,
               *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + H;
-  const int64_t nr = rows_dev ? (int64_t)*rows_dev : rows;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr;
        r += (int64_t)gridDim.x * blockDim.x) {
     const float4 fr = feat[r];
@@ -274,28 +275,23 @@ __global__ __launch_bounds__(256) void k_adam(int64_t np, float *__restrict__ w,
 }
 
 // Queue sort keys: one 8-bit digit, larger predicted cost first (quarter-octave
-// buckets); equal digits keep group order in the stable digit sort. Entries
-// beyond the queue sort last and are never read.
+// buckets); equal digits keep group order in the stable digit sort, which
+// covers the queue's entries only (the count is read on the device).
 __global__ __launch_bounds__(256) void k_cost_keys(
     const DevScalars *__restrict__ sc, const uint32_t *__restrict__ queue, int mode,
     const float4 *__restrict__ feat, const float *__restrict__ pred, int64_t n_upper,
     uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   const uint32_t nq = queue ? sc->nqueue : sc->ngroup;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_upper;
+  (void)n_upper;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq;
        i += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t key = 255u;
-    uint32_t val = 0xffffffffu;
-    if (i < nq) {
-      const uint32_t g = queue ? queue[i] : (uint32_t)i;
-      const float4 f = feat[g];
-      // mode 1: log2(count) + log2(1 + previous list length); mode 2: the model
-      const float c = mode == 2 ? pred[g] : f.x + f.w;
-      const float q = fminf(fmaxf(c * 4.0f, 0.0f), 254.0f);  // NaN -> 0
-      key = 254u - (uint32_t)q;
-      val = g;
-    }
-    keys[i] = key;
-    vals[i] = val;
+    const uint32_t g = queue ? queue[i] : (uint32_t)i;
+    const float4 f = feat[g];
+    // mode 1: log2(count) + log2(1 + previous list length); mode 2: the model
+    const float c = mode == 2 ? pred[g] : f.x + f.w;
+    const float q = fminf(fmaxf(c * 4.0f, 0.0f), 254.0f);  // NaN -> 0
+    keys[i] = 254u - (uint32_t)q;
+    vals[i] = g;
   }
 }
 
@@ -381,9 +377,10 @@ void launch_cost_order(int64_t n, bool queued, int mode, int H, const Ptrs &P,
                        hipStream_t st) {
   if (mode == 2)
     launch_mlp_forward(H, P.mlpw, n, &P.sc->ngroup, P.feat, P.pred, st);
-  hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P.sc,
+  hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(n, 256 * 8, 8192)), dim3(256), 0, st, P.sc,
                      queued ? P.order : nullptr, mode, P.feat, P.pred, n, P.okeys, P.qtmp);
-  launch_digit_sort(n, 0, P.okeys, P.qtmp, P.okeys + n, P.order, P.hist, st);
+  launch_digit_sort(n, queued ? &P.sc->nqueue : &P.sc->ngroup, 0, P.okeys, P.qtmp, P.okeys + n,
+                    P.order, P.hist, st);
   hipLaunchKernelGGL(k_cost_qtotal, dim3(1), dim3(64), 0, st, P.sc, queued ? 1 : 0);
 }
 

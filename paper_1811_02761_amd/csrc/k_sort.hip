@@ -28,7 +28,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(
     const uint64_t *__restrict__ keys, int64_t n, int shift,
-    uint32_t *__restrict__ hist, int64_t nblk) {
+    uint32_t *__restrict__ hist, int64_t nblk, const uint32_t *__restrict__ n_dev) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);  // a count known on the device only
   __shared__ uint32_t cnt[kWaves][kSortRadix];
   for (int t = threadIdx.x; t < kWaves * kSortRadix; t += kSortThreads)
     (&cnt[0][0])[t] = 0;
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
     int shift, const uint32_t *__restrict__ hist, int64_t nblk,
     const uint32_t *__restrict__ totals, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout) {
+    uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
   __shared__ uint32_t cnt[kWaves][kSortRadix];
   __shared__ uint32_t dbase[kSortRadix];
   __shared__ uint32_t wsum[kWaves];
@@ -155,16 +157,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   }
 }
 
-void launch_digit_sort(int64_t n, int shift, const uint64_t *kin, const uint32_t *vin,
-                       uint64_t *kout, uint32_t *vout, uint32_t *hist, hipStream_t st) {
+void launch_digit_sort(int64_t n, const uint32_t *n_dev, int shift, const uint64_t *kin,
+                       const uint32_t *vin, uint64_t *kout, uint32_t *vout, uint32_t *hist,
+                       hipStream_t st) {
   const int64_t nblk = cdiv(n, kSortTile);
   uint32_t *totals = hist + (int64_t)kSortRadix * nblk;
   hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortThreads), 0, st, kin, n, shift, hist,
-                     nblk);
+                     nblk, n_dev);
   hipLaunchKernelGGL(k_sort_scan, dim3(kSortRadix), dim3(kSortThreads), 0, st, hist, nblk,
                      totals);
   hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortThreads), 0, st, kin, vin, n, shift,
-                     hist, nblk, totals, kout, vout);
+                     hist, nblk, totals, kout, vout, n_dev);
 }
 
 void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
@@ -178,11 +181,11 @@ void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
   for (int pass = 0; pass < 8; ++pass) {
     const int shift = pass * kSortBits;
     hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(kSortThreads), 0, st, ki, n, shift,
-                       hist, nblk);
+                       hist, nblk, nullptr);
     hipLaunchKernelGGL(k_sort_scan, dim3(kSortRadix), dim3(kSortThreads), 0, st, hist,
                        nblk, totals);
     hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(kSortThreads), 0, st, ki, vi, n,
-                       shift, hist, nblk, totals, ko, vo);
+                       shift, hist, nblk, totals, ko, vo, nullptr);
     uint64_t *tk = ki; ki = ko; ko = tk;
     uint32_t *tv = vi; vi = vo; vo = tv;
   }

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(256) void k_group_bounds(
     const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
     const uint32_t *__restrict__ gcount, const float4 *__restrict__ xyzm,
     const uint32_t *__restrict__ perm, const float *__restrict__ axo,
-    const float *__restrict__ ayo, const float *__restrict__ azo, float delta_acc,
+    const float *__restrict__ ayo, const float *__restrict__ azo,
+    const float4 *__restrict__ asort, float delta_acc,
     float4 *__restrict__ gbox) {
   const uint32_t ng = sc->ngroup;
   const uint32_t wstride = gridDim.x * (blockDim.x >> 6);
@@ -53,7 +54,9 @@ __global__ __launch_bounds__(256) void k_group_bounds(
     const float4 p = xyzm[b + (ok ? k : 0)];
     float lx = p.x, ly = p.y, lz = p.z;
     float amin = INFINITY;
-    if (axo && ok) {
+    if (asort && ok) {  // key-ordered copy of a_old with |a| in w
+      amin = asort[b + k].w;
+    } else if (axo && ok) {
       const uint32_t o = perm[b + k];
       const float ax = axo[o], ay = ayo[o], az = azo[o];
       amin = sqrt_rn(__builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
@@ -80,6 +83,7 @@ struct WalkArgs {
   const uint32_t *order;   // queue -> group (nullptr: identity)
   const uint32_t *qcount;  // queue length (device)
   const uint32_t *groot;   // per group root cell (nullptr: the root, cell 0)
+  float4 *asort;           // key-ordered copy of the outputs with |a| (nullptr: none)
   uint32_t *retry;         // overflowing groups go here (nullptr: report instead)
   uint32_t *nretry;
   uint32_t *frontier;
@@ -364,9 +368,13 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
     }
     if (lane < gc) {  // lane == member here (stream 0)
       const uint32_t o = a.perm[gb + lane];
-      a.ax[o] = a.G * sx;
-      a.ay[o] = a.G * sy;
-      a.az[o] = a.G * sz;
+      const float gx = a.G * sx, gy = a.G * sy, gz = a.G * sz;
+      a.ax[o] = gx;
+      a.ay[o] = gy;
+      a.az[o] = gz;
+      if (a.asort)
+        a.asort[gb + lane] =
+            make_float4(gx, gy, gz, sqrt_rn(__builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gx * gx))));
     }
     if (kHash) {
       uint32_t lo = (uint32_t)hsum, hi = (uint32_t)(hsum >> 32);
@@ -470,13 +478,35 @@ void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st) {
 }
 
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
-                         const uint32_t *perm, int64_t n, float delta_acc, const Ptrs &P,
-                         hipStream_t st) {
+                         const float4 *asort, const uint32_t *perm, int64_t n,
+                         float delta_acc, const Ptrs &P, hipStream_t st) {
   int64_t g = cdiv(n, 4 * 8);  // up to n groups, 4 waves per block
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_group_bounds, dim3(g), dim3(256), 0, st, P.sc, P.gbegin, P.gcount,
-                     P.xyzm, perm, axo, ayo, azo, delta_acc, P.gbox);
+                     P.xyzm, perm, axo, ayo, azo, asort, delta_acc, P.gbox);
+}
+
+// asort[s] = (a, |a|) of caller index perm[s]; |a| rounded as in the MAC.
+__global__ __launch_bounds__(256) void k_asort_gather(const uint32_t *__restrict__ perm,
+                                                      int64_t n, const float *__restrict__ ax,
+                                                      const float *__restrict__ ay,
+                                                      const float *__restrict__ az,
+                                                      float4 *__restrict__ asort) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = perm[s];
+    const float x = ax[o], y = ay[o], z = az[o];
+    asort[s] = make_float4(x, y, z, sqrt_rn(__builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x))));
+  }
+}
+
+void launch_asort_gather(const uint32_t *perm, int64_t n, const float *ax, const float *ay,
+                         const float *az, float4 *asort, hipStream_t st) {
+  int64_t g = cdiv(n, 256 * 4);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_asort_gather, dim3(g), dim3(256), 0, st, perm, n, ax, ay, az, asort);
 }
 
 namespace {
@@ -493,6 +523,7 @@ WalkArgs walk_args(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
   a.order = c.use_order ? P.order : nullptr;
   a.qcount = c.use_order ? &P.sc->nqueue : &P.sc->ngroup;
   a.groot = c.batch ? P.groot : nullptr;
+  a.asort = c.asort_out ? P.asort : nullptr;
   a.retry = P.retry;
   a.nretry = &P.sc->nretry;
   a.frontier = P.frontier;

@@ -73,7 +73,7 @@ struct Layout {
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
-      off_inv;
+      off_inv, off_asort;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   size_t total = 0;
@@ -120,6 +120,7 @@ struct Ptrs {
   double4 *sysbox;      // batch: per system root cube lo x, y, z, side L
   uint32_t *groot;      // batch: per group the walk's root cell
   uint32_t *inv;        // caller index -> sorted position of the current tree
+  float4 *asort;        // key-ordered copy of the state's accelerations, |a| in w
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
@@ -147,7 +148,11 @@ void launch_sys_keys(const float *x, const float *y, const float *z, int64_t n, 
 constexpr int kMaxSystems = 4096;
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L,
                     hipStream_t st);
+// asort (may be null): key-ordered a_old with |a|, read instead of a gather
+void launch_asort_gather(const uint32_t *perm, int64_t n, const float *ax, const float *ay,
+                         const float *az, float4 *asort, hipStream_t st);
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
+                         const float4 *asort,
                          const uint32_t *perm, int64_t n, float delta_acc,
                          const Ptrs &P, hipStream_t st);
 struct WalkCfg {
@@ -163,6 +168,7 @@ struct WalkCfg {
   int64_t frontier2_cap;
   int retry_waves;
   bool batch;     // per-group roots (several systems in one tree)
+  bool asort_out;  // also write the outputs, with |a|, to P.asort in key order
 };
 // enqueue the walk kernel (the queue head must already be zero), then its
 // retry pass for groups whose stack overflowed
@@ -207,9 +213,11 @@ void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
 // sc->wstat of the walk just finished (queued: order[0 .. nqueue), else all)
 void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st);
 
-// single 8-bit digit pass of the stable radix sort (digit = key >> shift)
-void launch_digit_sort(int64_t n, int shift, const uint64_t *kin, const uint32_t *vin,
-                       uint64_t *kout, uint32_t *vout, uint32_t *hist, hipStream_t st);
+// single 8-bit digit pass of the stable radix sort (digit = key >> shift) of
+// the first min(n, *n_dev) entries (n_dev may be null); n bounds the grid
+void launch_digit_sort(int64_t n, const uint32_t *n_dev, int shift, const uint64_t *kin,
+                       const uint32_t *vin, uint64_t *kout, uint32_t *vout, uint32_t *hist,
+                       hipStream_t st);
 
 // cost model of the walk queue
 constexpr int kMlpMaxHidden = 64;
@@ -258,10 +266,12 @@ void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx
 // walk queue = the groups holding a particle active at tick (group order)
 void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, const Ptrs &P,
                       hipStream_t st);
-// active particles: a = anew, closing kick, new level; kmax_next, nactive
+// active particles: a = anew (also into the key-ordered mirror asort through
+// inv), closing kick, new level; kmax_next, nactive
 void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
                       const float *nay, const float *naz, float *vx, float *vy, float *vz,
-                      int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st);
+                      int8_t *level, const BlockCfg &c, float4 *asort, const uint32_t *inv,
+                      DevScalars *sc, hipStream_t st);
 void launch_order_by_count(int64_t n, const Ptrs &P, hipStream_t st);
 
 // ---- device helpers ----
