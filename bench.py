@@ -64,12 +64,11 @@ def walk_traffic():
     return float(m2.group(1))
 
 
-def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_frac=1.0,
-                 seconds=12.0):
+def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_frac=1.0):
     """The oracle (FP64 C, OpenMP) on this host: the full tree pipeline on all
-    particles, then the walk on a random sample of groups sized to about
-    `seconds`; the step time is build + walk scaled to all groups times
-    `walk_frac`, the mean share of the groups a step walks."""
+    particles (keys, sort, cells, moments, groups), a bootstrap walk of every
+    group for a_old, then the timed MAC walk of every group; the step time is
+    build + walk x `walk_frac`, the mean share of the groups a step walks."""
     import oracle
 
     x, y, z = (np.ascontiguousarray(pos32[:, k]) for k in range(3))
@@ -82,50 +81,39 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
     mom = oracle.moments(cells, sx, sy, sz, sm, 1.0)
     grp = oracle.groups(cells, group_max, group_merge)
     t_build = time.perf_counter() - t0
-    rng = np.random.default_rng(7)
     n = len(x)
 
-    def walk(sel, sa):
-        """Walk the selected groups; sa = previous accelerations (sorted order)
-        or None for the bootstrap criterion. Returns time, interactions, acc."""
-        g = oracle.Groups(grp.begin[sel], grp.count[sel], grp.cell[sel])
-        lo, hi, amin, dA = oracle.group_bounds(g, sx, sy, sz, sa, dacc)
+    def walk(sa):
+        """Walk every group; sa = previous accelerations (sorted order) or None
+        for the bootstrap criterion. Returns time, interactions, acc."""
+        lo, hi, amin, dA = oracle.group_bounds(grp, sx, sy, sz, sa, dacc)
         ax, ay, az = (np.zeros(n) for _ in range(3))
-        ent = np.empty(g.n, np.int64)
-        gh = np.empty(g.n, np.uint64)
+        ent = np.empty(grp.n, np.int64)
+        gh = np.empty(grp.n, np.uint64)
         t = time.perf_counter()
         oracle.lib().orc_walk(n, sx, sy, sz, sm, cells.n, cells.pbegin, cells.pcount,
                               cells.first_child, cells.n_child, mom.m32,
                               np.ascontiguousarray(mom.com[:, 0]),
                               np.ascontiguousarray(mom.com[:, 1]),
-                              np.ascontiguousarray(mom.com[:, 2]), mom.b2, mom.q, g.n,
-                              g.begin, g.count, np.ascontiguousarray(lo.reshape(-1)),
+                              np.ascontiguousarray(mom.com[:, 2]), mom.b2, mom.q, grp.n,
+                              grp.begin, grp.count, np.ascontiguousarray(lo.reshape(-1)),
                               np.ascontiguousarray(hi.reshape(-1)), dA, None, int(sa is None),
                               1.0, eps, ax, ay, az, ent, gh, nth)
-        return (time.perf_counter() - t, int((ent * g.count).sum()),
+        return (time.perf_counter() - t, int((ent * grp.count).sum()),
                 np.stack([ax, ay, az], 1).astype(np.float32))
 
-    def mac_walk(sel):
-        # a_old of the sampled members from the oracle's own bootstrap walk
-        _, _, a0 = walk(sel, None)
-        return walk(sel, a0)
-
-    probe = rng.choice(grp.n, size=min(64, grp.n), replace=False)
-    tp, _, _ = mac_walk(probe)
-    per_group = max(tp / len(probe), 1e-7)
-    ns = int(min(grp.n, max(64, seconds / per_group)))
-    sel = np.sort(rng.choice(grp.n, size=ns, replace=False))
-    tw, inter, _ = mac_walk(sel)
-    t_walk_full = tw * grp.n / ns
+    _, _, a0 = walk(None)
+    tw, inter, _ = walk(a0)
     return {
-        "value": t_build + t_walk_full * walk_frac,
+        "value": t_build + tw * walk_frac,
         "unit": "s/step",
         "cores": nth,
         "kind": "oracle",
-        "sample": ("FP64 oracle: full tree build of all %d particles (%.1f s, 1 thread) + "
-                   "walk of %d of %d groups (%.1f s, %d threads), walk scaled to all groups "
-                   "x %.3f (mean share of groups walked per step)"
-                   % (len(x), t_build, ns, grp.n, tw, nth, walk_frac)),
+        "sample": ("FP64 oracle, one step's tree work on all %d particles: tree build "
+                   "(keys, sort, cells, moments, groups; %.1f s, 1 thread) + MAC walk of all "
+                   "%d groups (%.1f s, %d threads) x %.3f (mean share of groups a block step "
+                   "walks); a_old from its own bootstrap walk (untimed)"
+                   % (n, t_build, grp.n, tw, nth, walk_frac)),
         "interactions_per_s": inter / tw if tw > 0 else None,
     }
 
@@ -229,16 +217,22 @@ def main():
     snap = snapshot(st)
     del ctx0
 
+    # untimed steps before each timed run: one period of the longest occupied
+    # block step, so that every particle has been walked in the run's own
+    # context (its previous list length, an input of the cost model, is known)
+    lv = snap["level"]
+    settle = max(2, 1 << int(lv.max().item())) if lv is not None else 2
+
     def timed_run(order):
-        """From the warm-up state: 2 untimed steps (the members learn their
-        list lengths), then the timed steps. Forces do not depend on the
-        order, so both runs follow the same trajectory."""
+        """From the warm-up state: `settle` untimed steps, then the timed
+        steps. Forces do not depend on the order, so every run follows the
+        same trajectory."""
         s = restore(snap, nb)
         ctx = nb.Context(params, n_max=args.n)
         if order == 2:
             ctx.set_cost_model(model["hidden"], model["w"])
         ctx.set_order(order)
-        ctx.step(s, 2)
+        ctx.step(s, settle)
         ctx.sync()
         ctx.timing(True)
         s_0 = ctx.stats()
@@ -280,6 +274,11 @@ def main():
             "states bit-identical %s" % (learned["s_per_step"], learned["plain_over_learned_step"],
                                          l_walk, learned["plain_over_learned_walk"], same))
         del ctx2, st2
+        ctx3, st3, w0, w1, y0, y1 = timed_run(1)
+        s_walk = w1["walk_ms_sum"] / max(w1["walk_calls"], 1)
+        learned["size_based"] = {"s_per_step": (y1 - y0) / args.steps, "walk_ms": s_walk}
+        log("size-based order: s/step %.4g, walk %.3f ms" % ((y1 - y0) / args.steps, s_walk))
+        del ctx3, st3
     levels = None
     if block:
         levels = np.bincount(st.level.cpu().numpy(), minlength=11).tolist()

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define NBODY_ABI_VERSION 1
+#define NBODY_ABI_VERSION 2
 
 typedef int32_t nbody_status;
 enum {
@@ -74,7 +74,7 @@ enum {
  *                outgrows a smaller cap is walked again by a few wavefronts
  *                with a 16384-cell stack, so the results never depend on it.
  *  list_tile   : interaction-list entries held in LDS per wavefront before a
- *                flush (multiple of 8, 64..2048; 0 = 192).
+ *                flush (multiple of 64, 64..2048; 0 = 192).
  *  waves_per_cu: resident wavefronts per compute unit of the persistent walk
  *                (1..32; 0 = 32).
  *  checks      : 0 none; 1 also record, per group, an order-independent hash
@@ -85,6 +85,17 @@ enum {
  *                count stays within group_max (fewer, fuller groups, hence
  *                fewer interaction lists; results change only through the
  *                grouping).
+ *  walk_split  : wavefronts sharing one group's interaction list: 0 chosen
+ *                per walk from the queued group count q and the walk's
+ *                wavefront count w (4 if q < 2w, 2 if q < 4w, else 1), or
+ *                1, 2, 4 fixed (1 whenever q > 4w).
+ *                A group's list is cut into blocks of 64 entries in
+ *                traversal order and each lane keeps 4 FP32 partial sums,
+ *                block b adding into sum b mod 4, which are added in that
+ *                order at the end; with k wavefronts per group, wavefront j
+ *                adds the blocks b with b mod k == j and a second kernel
+ *                adds the sums. Results are bit-identical for every value.
+ *                The compensated sum (compensated = 1) is never split.
  */
 typedef struct {
   float G;
@@ -99,6 +110,7 @@ typedef struct {
   int32_t waves_per_cu;
   int32_t checks;
   int32_t group_merge;
+  int32_t walk_split;
 } nbody_params;
 
 typedef struct nbody_ctx nbody_ctx; /* opaque; one per HIP stream */

@@ -54,7 +54,7 @@ class _Params(C.Structure):
                 ("compensated", C.c_int32), ("order", C.c_int32),
                 ("frontier_cap", C.c_int32), ("list_tile", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("checks", C.c_int32),
-                ("group_merge", C.c_int32)]
+                ("group_merge", C.c_int32), ("walk_split", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -90,6 +90,7 @@ HEADER_FUNCTIONS = [
 ]
 
 _lib = None
+ABI_VERSION = 2  # NBODY_ABI_VERSION of include/nbody.h
 
 
 def lib():
@@ -102,6 +103,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.nbody_abi_version.restype = i32
+        if L.nbody_abi_version() != ABI_VERSION:
+            raise ImportError("%s has ABI version %d, this binding expects %d: rebuild it"
+                              % (LIB_PATH, L.nbody_abi_version(), ABI_VERSION))
         L.nbody_strerror.argtypes = [i32]
         L.nbody_strerror.restype = C.c_char_p
         L.nbody_params_default.argtypes = [C.POINTER(_Params)]
@@ -181,6 +185,7 @@ class Params:
     waves_per_cu: int = 0
     checks: int = 0
     group_merge: int = 1
+    walk_split: int = 0
 
     def c(self) -> _Params:
         return _Params(*[getattr(self, f.name) for f in fields(self)])

@@ -94,11 +94,13 @@ nbody_status check_params(const nbody_params *p) {
   if (p->frontier_cap != 0 &&
       (p->frontier_cap < 64 || (p->frontier_cap & (p->frontier_cap - 1)) != 0))
     return NBODY_EINVAL;
-  if (p->list_tile != 0 && (p->list_tile < 64 || p->list_tile > 2048 || p->list_tile % 8))
+  if (p->list_tile != 0 && (p->list_tile < 64 || p->list_tile > 2048 || p->list_tile % 64))
     return NBODY_EINVAL;
   if (p->waves_per_cu < 0 || p->waves_per_cu > 32) return NBODY_EINVAL;
   if (p->checks != 0 && p->checks != 1) return NBODY_EINVAL;
   if (p->group_merge != 0 && p->group_merge != 1) return NBODY_EINVAL;
+  if (p->walk_split != 0 && p->walk_split != 1 && p->walk_split != 2 && p->walk_split != 4)
+    return NBODY_EINVAL;
   return NBODY_OK;
 }
 
@@ -202,6 +204,10 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_groot = take(4 * N);
   L.off_inv = take(4 * N);
   L.off_asort = take(16 * N);
+  // split walk: one slot per queued group while the queue is shorter than
+  // 4 x the walk's wavefronts (no walk splits a longer queue)
+  L.split_slots = std::max<int64_t>(1, std::min<int64_t>(4 * L.walk_waves, n));
+  L.off_split = take((size_t)kSplitSlotBytes * (size_t)L.split_slots);
   L.total = o;
   return L;
 }
@@ -268,6 +274,7 @@ Ptrs carve(void *base, const Layout &L) {
   P.groot = reinterpret_cast<uint32_t *>(b + L.off_groot);
   P.inv = reinterpret_cast<uint32_t *>(b + L.off_inv);
   P.asort = reinterpret_cast<float4 *>(b + L.off_asort);
+  P.split = reinterpret_cast<float *>(b + L.off_split);
   return P;
 }
 
@@ -382,6 +389,9 @@ WalkCfg walk_cfg(const nbody_ctx *ctx, bool bootstrap, bool queued) {
   c.frontier2_cap = ctx->L.frontier2_cap;
   c.retry_waves = ctx->L.retry_waves;
   c.batch = ctx->sys_r > 0;
+  c.asort_out = false;
+  c.split = ctx->p.walk_split;
+  c.split_slots = ctx->L.split_slots;
   return c;
 }
 

@@ -15,10 +15,24 @@
 // Eq. 1 over the tile for its particle, in FP32.
 //
 // Canonical order: list entries appear in the order of this traversal (a
-// function of the tree and the group alone) and a flush only cuts that
-// sequence, so each lane's summation order is fixed by the group alone. It
-// does not depend on the tile size, the stack capacity, the queue order or
-// which wave runs the group: results are bit-identical across them.
+// function of the tree and the group alone). Entry j belongs to block j / 64;
+// each lane keeps four FP32 running sums and adds the entries of block b, in
+// list order, to sum b mod 4; the four sums are added in that order at the
+// end. A flush only cuts the sequence at block boundaries (tiles are
+// multiples of 64 entries), so each lane's summation order is fixed by the
+// group alone: it does not depend on the tile size, the stack capacity, the
+// queue order, which wave runs the group, or the split below. Results are
+// bit-identical across all of them. (The compensated sum keeps one running
+// sum over the whole list and is never split.)
+//
+// Split walk: when few groups are queued (block steps often walk a few
+// thousand heavy groups, fewer than the resident wavefronts), K = 2 or 4
+// wavefronts take the same group: each traverses the whole tree (the MAC
+// decisions are the same in each) but adds only the blocks b with
+// b mod K == its part, i.e. the running sums r with r mod K == its part, and
+// stores them; a second kernel (k_walk_join) adds the four sums per lane in
+// order and writes the results. This turns a queue of q heavy groups into
+// K q tasks of a quarter or half the arithmetic each.
 //
 // Lane layout: groups of at most 8, 16 or 32 members use S = 8, 4 or 2
 // "streams": lane = stream * (64 / S) + member, stream s adds the entries
@@ -91,12 +105,23 @@ struct WalkArgs {
   unsigned long long *ghash;
   DevScalars *sc;
   float *ax, *ay, *az;
+  float *split;            // partial sums of split groups, per queue position
   float G, eps2;
   uint32_t n;
   uint32_t tile;
   uint32_t fmask;
   int bootstrap;
+  int split_mode;          // -1 never (retry pass), 0 by queue length, else 1, 2, 4
+  uint32_t split_slots;
 };
+
+// Wavefronts per group for a queue of ng groups walked by `waves` wavefronts.
+__device__ __forceinline__ uint32_t split_factor(uint32_t ng, uint32_t waves, uint32_t slots,
+                                                 int mode, bool comp) {
+  if (comp || mode < 0 || ng > slots || ng > 4u * waves) return 1u;
+  if (mode > 0) return (uint32_t)mode;
+  return ng < 2u * waves ? 4u : ng < 4u * waves ? 2u : 1u;
+}
 
 __device__ __forceinline__ uint64_t mix64(uint64_t v) {
   v += 0x9E3779B97F4A7C15ull;
@@ -141,7 +166,50 @@ struct Acc3<true> {
   }
 };
 
-// Entries of zero mass pad a flushed tile to a multiple of S * kFlushUnroll,
+// The running sums of a lane: four for the plain FP32 sum (block b of the
+// list adds into sum b mod 4), one for the compensated sum. The sum of the
+// block being added is always u0: after each block the sums rotate, so that
+// no register is ever selected by a run-time index. A wavefront taking every
+// K-th block (part p of K) holds the 4 / K sums p, p + K, ... in u0, u1, ...
+// (rotating among those); after a whole number of rotation periods u_k holds
+// sum p + K k.
+constexpr uint32_t kBlk = 64;  // list entries per block
+template <bool kComp>
+struct RunSums;
+template <>
+struct RunSums<false> {
+  static constexpr uint32_t kNum = 4;
+  Acc3<false> u0, u1, u2, u3;
+  __device__ __forceinline__ void advance(uint32_t K) {
+    if (K == 1u) {
+      const Acc3<false> t = u0;
+      u0 = u1;
+      u1 = u2;
+      u2 = u3;
+      u3 = t;
+    } else if (K == 2u) {
+      const Acc3<false> t = u0;
+      u0 = u1;
+      u1 = t;
+    }
+  }
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+    ox = ((u0.x + u1.x) + u2.x) + u3.x;
+    oy = ((u0.y + u1.y) + u2.y) + u3.y;
+    oz = ((u0.z + u1.z) + u2.z) + u3.z;
+  }
+};
+template <>
+struct RunSums<true> {
+  static constexpr uint32_t kNum = 1;
+  Acc3<true> u0;
+  __device__ __forceinline__ void advance(uint32_t) {}
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+    u0.total(ox, oy, oz);
+  }
+};
+
+// Entries of zero mass pad a flushed block to a multiple of S * kFlushUnroll,
 // so every lane runs the same trip count and the loads of one trip are
 // issued together. A padding entry adds exactly +0 to each sum (r^2 >= eps^2
 // keeps it finite), and each lane still adds its entries in list order.
@@ -164,9 +232,9 @@ __device__ __forceinline__ void eq1_term(const float4 e, float4 pi, float eps2, 
 // offsets of one trip (u * S entries past the trip's base) are then uniform
 // and immediate.
 template <bool kComp, uint32_t S>
-__device__ __forceinline__ void flush_tile_s(const float4 *__restrict__ list, uint32_t padded,
-                                             uint32_t stream, float4 pi, float eps2,
-                                             Acc3<kComp> &acc) {
+__device__ __forceinline__ void flush_run_s(const float4 *__restrict__ list, uint32_t padded,
+                                            uint32_t stream, float4 pi, float eps2,
+                                            Acc3<kComp> &acc) {
   constexpr uint32_t step = S * kFlushUnroll;
   const float4 *p = list + stream;
   for (uint32_t j0 = 0; j0 < padded; j0 += step) {
@@ -183,24 +251,74 @@ __device__ __forceinline__ void flush_tile_s(const float4 *__restrict__ list, ui
 }
 
 template <bool kComp>
-__device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t cnt,
-                                           uint32_t lane, uint32_t stream, uint32_t S,
-                                           float4 pi, float eps2, Acc3<kComp> &acc) {
+__device__ __forceinline__ void flush_run(const float4 *__restrict__ list, uint32_t cnt,
+                                          uint32_t stream, uint32_t S, float4 pi, float eps2,
+                                          Acc3<kComp> &acc) {
   const uint32_t step = S * kFlushUnroll;
   const uint32_t padded = (cnt + step - 1) / step * step;
+  // S is wave-uniform: these branches are not lane-predicated
+  if (S == 1)
+    flush_run_s<kComp, 1>(list, padded, stream, pi, eps2, acc);
+  else if (S == 2)
+    flush_run_s<kComp, 2>(list, padded, stream, pi, eps2, acc);
+  else if (S == 4)
+    flush_run_s<kComp, 4>(list, padded, stream, pi, eps2, acc);
+  else
+    flush_run_s<kComp, 8>(list, padded, stream, pi, eps2, acc);
+}
+
+// Flush the tile's cnt entries: whole blocks of 64 entries (the last one
+// possibly short), each into u0 followed by a rotation of the sums (the
+// compensated sum: all into its one sum). nblk counts the blocks added.
+template <bool kComp>
+__device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t cnt, uint32_t K,
+                                           uint32_t lane, uint32_t stream, uint32_t S,
+                                           float4 pi, float eps2, RunSums<kComp> &R,
+                                           uint32_t &nblk) {
   // every lane stores (two lanes per slot, same value): no lane-predicated
   // region; slots [cnt, cnt + kListPad) are free
   list[cnt + (lane & (kListPad - 1))] = make_float4(0.f, 0.f, 0.f, 0.f);
   __builtin_amdgcn_wave_barrier();
-  // S is wave-uniform: these branches are not lane-predicated
-  if (S == 1)
-    flush_tile_s<kComp, 1>(list, padded, stream, pi, eps2, acc);
-  else if (S == 2)
-    flush_tile_s<kComp, 2>(list, padded, stream, pi, eps2, acc);
-  else if (S == 4)
-    flush_tile_s<kComp, 4>(list, padded, stream, pi, eps2, acc);
-  else
-    flush_tile_s<kComp, 8>(list, padded, stream, pi, eps2, acc);
+  if constexpr (kComp) {
+    flush_run<kComp>(list, cnt, stream, S, pi, eps2, R.u0);
+    return;
+  }
+  for (uint32_t off = 0; off < cnt; off += kBlk) {
+    flush_run<kComp>(list + off, min(kBlk, cnt - off), stream, S, pi, eps2, R.u0);
+    R.advance(K);
+    ++nblk;
+  }
+}
+
+// Per lane: the group member, the list stream, and (after adding the running
+// sums) the butterfly over the streams; every lane ends with its member's sum.
+__device__ __forceinline__ uint32_t stream_count(uint32_t gc) {
+  return gc <= 8 ? 8u : gc <= 16 ? 4u : gc <= 32 ? 2u : 1u;
+}
+
+__device__ __forceinline__ void stream_reduce(uint32_t Wd, float &sx, float &sy, float &sz) {
+  for (uint32_t d = Wd; d < 64u; d <<= 1) {
+    sx += __shfl_xor(sx, (int)d, 64);
+    sy += __shfl_xor(sy, (int)d, 64);
+    sz += __shfl_xor(sz, (int)d, 64);
+  }
+}
+
+// The results of member `lane` (< gc) of group (gb, gc): G times the sum, in
+// caller order, and with |a| into the key-ordered mirror when there is one.
+__device__ __forceinline__ void store_group_result(const WalkArgs &a, uint32_t gb, uint32_t gc,
+                                                   uint32_t lane, float sx, float sy,
+                                                   float sz) {
+  if (lane < gc) {  // lane == member here (stream 0)
+    const uint32_t o = a.perm[gb + lane];
+    const float gx = a.G * sx, gy = a.G * sy, gz = a.G * sz;
+    a.ax[o] = gx;
+    a.ay[o] = gy;
+    a.az[o] = gz;
+    if (a.asort)
+      a.asort[gb + lane] =
+          make_float4(gx, gy, gz, sqrt_rn(__builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gx * gx))));
+  }
 }
 
 template <bool kComp, bool kHash>
@@ -220,6 +338,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   const uint32_t ng = *a.qcount;
   const uint32_t ncell = a.sc->ncell;
   const uint32_t npart = a.n;
+  // K wavefronts per group (a power of two); task t is part t mod K of
+  // queue position t / K
+  const uint32_t K = split_factor(ng, gridDim.x * kWalkWavesPerWG, a.split_slots, a.split_mode,
+                                  kComp);
+  const uint32_t kshift = K == 4u ? 2u : K == 2u ? 1u : 0u;
   // No lane-predicated region may sit in this loop: the compiler threads such
   // regions across the back-edge, and a wave that re-enters with lane 0 masked
   // off reads a stale queue index. Every lane joins the queue atomic (lane 0
@@ -227,23 +350,26 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   // lane (same value, same address).
   for (;;) {
     const uint32_t claim = atomicAdd(&a.sc->queue_head, lane == 0 ? 1u : 0u);
-    const uint32_t qi = __builtin_amdgcn_readfirstlane(claim);
+    const uint32_t task = __builtin_amdgcn_readfirstlane(claim);
+    const uint32_t qi = task >> kshift;
+    const uint32_t part = task & (K - 1u);
     if (qi >= ng) break;
     const uint32_t g = a.order ? a.order[qi] : qi;
     const uint32_t gb = a.gbegin[g], gc = a.gcount[g];
     const float4 glo = a.gbox[2 * g], ghi = a.gbox[2 * g + 1];
     const float dA = glo.w;
-    const uint32_t S = gc <= 8 ? 8u : gc <= 16 ? 4u : gc <= 32 ? 2u : 1u;
+    const uint32_t S = stream_count(gc);
     const uint32_t Wd = 64u / S;
     const uint32_t member = lane & (Wd - 1);
     const uint32_t stream = lane / Wd;
     const bool mem_ok = member < gc;
     const float4 pi = a.xyzm[gb + (mem_ok ? member : 0u)];
-    Acc3<kComp> acc;
+    RunSums<kComp> R;
     uint64_t hsum = 0;
     stk[0] = a.groot ? a.groot[g] : 0u;  // the walk's root (same value in every lane)
     uint32_t top = 1, visited = 0, cnt = 0;
-    uint32_t entries = 0;
+    uint32_t entries = 0;  // list entries so far (list index of the next one)
+    uint32_t nblk = 0;     // list blocks this wavefront has added
     bool overflow = false, corrupt = false;
     while (top > 0) {
       const uint32_t nc = min(64u, top);
@@ -306,7 +432,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
       top += chtot;
       // entries -> LDS list (flushing full tiles). Lane k owns entries
       // [incl_k - ne_k, incl_k); the copy is cooperative: lane r of the wave
-      // fetches entry done + r, finding its owner by binary search.
+      // fetches entry done + r, finding its owner by binary search. With
+      // K > 1 only this part's blocks are copied.
       const uint32_t ei = wave_incl_scan_dpp(ne);
       const uint32_t etot = wave_last(ei);
       if (kHash) {
@@ -320,8 +447,20 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
       __builtin_amdgcn_wave_barrier();
       uint32_t done = 0;
       while (done < etot) {
-        const uint32_t take = min(a.tile - cnt, etot - done);
-        for (uint32_t r = lane; r < take; r += 64u) {
+        const uint32_t J = entries + done;  // list index of the next entry
+        uint32_t seg;
+        if (K == 1u) {
+          seg = min(a.tile - cnt, etot - done);
+        } else {
+          // the rest of block J / 64 within this chunk; the tile (a multiple
+          // of 64 entries) holds whole blocks, so it always has room
+          seg = min(kBlk - (J & (kBlk - 1u)), etot - done);
+          if (((J / kBlk) & (K - 1u)) != part) {
+            done += seg;
+            continue;
+          }
+        }
+        for (uint32_t r = lane; r < seg; r += 64u) {
           const uint32_t j = done + r;
           uint32_t k = 0;
 #pragma unroll
@@ -331,11 +470,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
           const uint32_t first = k ? s_incl[k - 1] : 0u;
           list[cnt + r] = (src == 0xffffffffu) ? s_ent[k] : a.xyzm[src + (j - first)];
         }
-        cnt += take;
-        done += take;
+        cnt += seg;
+        done += seg;
         if (cnt == a.tile) {
           __builtin_amdgcn_wave_barrier();
-          flush_tile<kComp>(list, cnt, lane, stream, S, pi, a.eps2, acc);
+          flush_tile<kComp>(list, cnt, K, lane, stream, S, pi, a.eps2, R, nblk);
           __builtin_amdgcn_wave_barrier();
           cnt = 0;
         }
@@ -346,48 +485,86 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // overflow and corrupt are wave-uniform: these branches are not
-    // lane-predicated; every lane joins the atomics and stores
+    // lane-predicated; every lane joins the atomics and stores. Every part
+    // of a split group meets the same overflow (same traversal); part 0
+    // alone hands the group to the retry pass.
     const bool handoff = overflow && !corrupt && a.retry != nullptr;
     if (handoff) {
-      const uint32_t slot = __builtin_amdgcn_readfirstlane(
-          atomicAdd(a.nretry, lane == 0 ? 1u : 0u));
-      a.retry[slot] = g;
+      if (part == 0u) {
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(
+            atomicAdd(a.nretry, lane == 0 ? 1u : 0u));
+        a.retry[slot] = g;
+      }
     } else if (overflow || corrupt) {
       atomicOr(&a.sc->status, overflow ? kStOverflow : kStCorrupt);
     }
     if (overflow || corrupt) cnt = 0;
     __builtin_amdgcn_wave_barrier();
-    flush_tile<kComp>(list, cnt, lane, stream, S, pi, a.eps2, acc);
+    flush_tile<kComp>(list, cnt, K, lane, stream, S, pi, a.eps2, R, nblk);
     __builtin_amdgcn_wave_barrier();
-    float sx, sy, sz;
-    acc.total(sx, sy, sz);
-    for (uint32_t d = Wd; d < 64u; d <<= 1) {
-      sx += __shfl_xor(sx, (int)d, 64);
-      sy += __shfl_xor(sy, (int)d, 64);
-      sz += __shfl_xor(sz, (int)d, 64);
-    }
-    if (lane < gc) {  // lane == member here (stream 0)
-      const uint32_t o = a.perm[gb + lane];
-      const float gx = a.G * sx, gy = a.G * sy, gz = a.G * sz;
-      a.ax[o] = gx;
-      a.ay[o] = gy;
-      a.az[o] = gz;
-      if (a.asort)
-        a.asort[gb + lane] =
-            make_float4(gx, gy, gz, sqrt_rn(__builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gx * gx))));
-    }
-    if (kHash) {
-      uint32_t lo = (uint32_t)hsum, hi = (uint32_t)(hsum >> 32);
-      // 64-bit wave sum by 32-bit halves with carries
-      for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t olo = __shfl_xor(lo, d, 64), ohi = __shfl_xor(hi, d, 64);
-        const uint32_t nlo = lo + olo;
-        hi = hi + ohi + (nlo < lo ? 1u : 0u);
-        lo = nlo;
+    // complete the rotation period (4 / K blocks): then u_k is sum part + K k
+    if constexpr (!kComp)
+      for (; nblk & (RunSums<kComp>::kNum / K - 1u); ++nblk) R.advance(K);
+    if (K == 1u) {
+      float sx, sy, sz;
+      R.total(sx, sy, sz);
+      stream_reduce(Wd, sx, sy, sz);
+      store_group_result(a, gb, gc, lane, sx, sy, sz);
+    } else if constexpr (!kComp) {
+      // this part's running sums into the queue slot: [sum][component][lane]
+      float *slot = a.split + (size_t)qi * (kSplitSlotBytes / 4);
+      slot[((part + 0u) * 3 + 0) * 64 + lane] = R.u0.x;
+      slot[((part + 0u) * 3 + 1) * 64 + lane] = R.u0.y;
+      slot[((part + 0u) * 3 + 2) * 64 + lane] = R.u0.z;
+      if (K == 2u) {
+        slot[((part + 2u) * 3 + 0) * 64 + lane] = R.u1.x;
+        slot[((part + 2u) * 3 + 1) * 64 + lane] = R.u1.y;
+        slot[((part + 2u) * 3 + 2) * 64 + lane] = R.u1.z;
       }
-      a.ghash[g] = ((uint64_t)hi << 32) | lo;  // butterfly: every lane holds the sum
     }
-    a.gent[g] = (overflow || corrupt) ? 0xffffffffu : entries;
+    if (part == 0u) {
+      if (kHash) {
+        uint32_t lo = (uint32_t)hsum, hi = (uint32_t)(hsum >> 32);
+        // 64-bit wave sum by 32-bit halves with carries
+        for (int d = 32; d >= 1; d >>= 1) {
+          const uint32_t olo = __shfl_xor(lo, d, 64), ohi = __shfl_xor(hi, d, 64);
+          const uint32_t nlo = lo + olo;
+          hi = hi + ohi + (nlo < lo ? 1u : 0u);
+          lo = nlo;
+        }
+        a.ghash[g] = ((uint64_t)hi << 32) | lo;  // butterfly: every lane holds the sum
+      }
+      a.gent[g] = (overflow || corrupt) ? 0xffffffffu : entries;
+    }
+  }
+}
+
+// Second kernel of a split walk: per queue position, the four running sums
+// of each lane added in order, then the stream butterfly and the results, as
+// an unsplit walk ends. Groups the walk handed to its retry pass (entry
+// count 0xffffffff) are left to it.
+__global__ __launch_bounds__(256) void k_walk_join(WalkArgs a, uint32_t walk_waves) {
+  const uint32_t ng = *a.qcount;
+  if (split_factor(ng, walk_waves, a.split_slots, a.split_mode, false) == 1u) return;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t qi = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+                                                    (threadIdx.x >> 6));
+       qi < ng; qi += nw) {
+    const uint32_t g = a.order ? a.order[qi] : qi;
+    if (a.gent[g] == 0xffffffffu) continue;
+    const uint32_t gb = a.gbegin[g], gc = a.gcount[g];
+    const float *slot = a.split + (size_t)qi * (kSplitSlotBytes / 4);
+    float v[4][3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[r][k] = slot[(r * 3 + k) * 64 + lane];
+    float sx = ((v[0][0] + v[1][0]) + v[2][0]) + v[3][0];
+    float sy = ((v[0][1] + v[1][1]) + v[2][1]) + v[3][1];
+    float sz = ((v[0][2] + v[1][2]) + v[2][2]) + v[3][2];
+    stream_reduce(64u / stream_count(gc), sx, sy, sz);
+    store_group_result(a, gb, gc, lane, sx, sy, sz);
   }
 }
 
@@ -539,6 +716,9 @@ WalkArgs walk_args(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
   a.tile = (uint32_t)c.list_tile;
   a.fmask = (uint32_t)c.frontier_cap - 1u;
   a.bootstrap = c.bootstrap;
+  a.split = P.split;
+  a.split_mode = c.split;
+  a.split_slots = (uint32_t)c.split_slots;
   return a;
 }
 
@@ -571,6 +751,10 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
   launch_fill_u32(&P.sc->nretry, 0u, 1, st);
   NB_WALK_LAUNCH(k_walk, c, dim3(blocks), walk_lds(c), st, a);
+  // a split walk's results (the kernel returns at once when the walk was not split)
+  if (!c.compensated)
+    hipLaunchKernelGGL(k_walk_join, dim3(512), dim3(256), 0, st, a,
+                       (uint32_t)(blocks * kWalkWavesPerWG));
 }
 
 // Retry pass: the groups that outgrew a small stack (frontier_cap below the
@@ -584,6 +768,7 @@ void launch_walk_retry(const WalkCfg &c, const uint32_t *perm, int64_t n, float 
   r.retry = nullptr;
   r.frontier = P.frontier2;
   r.fmask = (uint32_t)c.frontier2_cap - 1u;
+  r.split_mode = -1;  // results written by the pass itself
   launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
   NB_WALK_LAUNCH(k_walk_retry, c, dim3(c.retry_waves / kWalkWavesPerWG), walk_lds(c), st, r);
 }

@@ -18,6 +18,8 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // keys per workgroup
 constexpr int kBuildThreads = 256;                   // particles per build block
 constexpr int kBuildHalo = 64;                       // >= max(leaf_max, group_max)
 constexpr int kWalkWavesPerWG = 4;
+// split walk: 4 partial sums x 3 components x 64 lanes (FP32) per queue position
+constexpr int kSplitSlotBytes = 4 * 3 * 64 * 4;
 
 // device status bits (sticky)
 constexpr int32_t kStNonFinite = 1;
@@ -73,9 +75,10 @@ struct Layout {
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
-      off_inv, off_asort;
+      off_inv, off_asort, off_split;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
+  int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
   size_t total = 0;
 };
 
@@ -121,6 +124,7 @@ struct Ptrs {
   uint32_t *groot;      // batch: per group the walk's root cell
   uint32_t *inv;        // caller index -> sorted position of the current tree
   float4 *asort;        // key-ordered copy of the state's accelerations, |a| in w
+  float *split;         // split walk: per queue position 4 x 3 x 64 partial sums
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
@@ -169,6 +173,8 @@ struct WalkCfg {
   int retry_waves;
   bool batch;     // per-group roots (several systems in one tree)
   bool asort_out;  // also write the outputs, with |a|, to P.asort in key order
+  int split;       // wavefronts per group: 0 by queue length, else 1, 2 or 4
+  int64_t split_slots;
 };
 // enqueue the walk kernel (the queue head must already be zero), then its
 // retry pass for groups whose stack overflowed

@@ -38,7 +38,7 @@ def test_header_symbols_exported(nb):
 
 def test_abi_version_and_strings(nb):
     L = nb.lib()
-    assert L.nbody_abi_version() == 1
+    assert L.nbody_abi_version() == 2
     for code in range(0, -8, -1):
         assert len(L.nbody_strerror(code)) > 0
 
@@ -55,7 +55,8 @@ def test_create_rejects_bad_params_without_gpu(nb):
     # parameter validation happens before any device call
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(delta_acc=-1.0), dict(group_max=65),
                 dict(leaf_max=0), dict(leaf_max=65, group_max=64), dict(compensated=2),
-                dict(order=3), dict(frontier_cap=100), dict(list_tile=60),
+                dict(order=3), dict(frontier_cap=100), dict(list_tile=60), dict(list_tile=136),
+                dict(walk_split=3),
                 dict(waves_per_cu=33), dict(checks=2), dict(group_merge=2)):
         p = nb.Params(**bad).c()
         h = ctypes.c_void_p()

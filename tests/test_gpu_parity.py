@@ -216,13 +216,18 @@ def test_zero_delta_equals_direct(nb, torch, orc):
     _assert_rule(e, et)
 
 
-def test_results_independent_of_tile_waves_and_frontier(nb, torch, orc):
+def test_results_independent_of_tile_waves_frontier_and_split(nb, torch, orc):
+    # the walk's summation order is fixed by the group alone: list tile,
+    # resident wavefronts, stack capacity (with its retry pass) and the number
+    # of wavefronts sharing a group never change a bit
     g = I.galaxy(30000, 12)
     x, y, z, _, _, _, m = g.f32()
     a_old = _ref(orc, x, y, z, m, nb.Params()).acc.astype(np.float32)
     outs = []
-    for tile, waves, fc in ((256, 8, 0), (64, 4, 4096), (2048, 16, 1 << 18), (136, 12, 0)):
-        params = nb.Params(list_tile=tile, waves_per_cu=waves, frontier_cap=fc)
+    for tile, waves, fc, split in ((256, 8, 0, 1), (64, 4, 4096, 1), (2048, 16, 1 << 18, 2),
+                                   (320, 12, 0, 4), (192, 32, 0, 0), (128, 32, 64, 4),
+                                   (192, 32, 64, 2)):
+        params = nb.Params(list_tile=tile, waves_per_cu=waves, frontier_cap=fc, walk_split=split)
         _, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
         outs.append(acc)
     for o in outs[1:]:
