@@ -223,11 +223,14 @@ def main():
     lv = snap["level"]
     settle = max(2, 1 << int(lv.max().item())) if lv is not None else 2
 
-    def timed_run(order):
+    def timed_run(order, rebuild=None):
         """From the warm-up state: `settle` untimed steps, then the timed
-        steps. Forces do not depend on the order, so every run follows the
-        same trajectory."""
+        steps; `rebuild` overrides the state's rebuild interval. Forces do not
+        depend on the order, so runs with the same tree schedule follow the
+        same trajectory bit for bit."""
         s = restore(snap, nb)
+        if rebuild is not None:
+            s.rebuild_interval = rebuild
         ctx = nb.Context(params, n_max=args.n)
         if order == 2:
             ctx.set_cost_model(model["hidden"], model["w"])
@@ -237,7 +240,8 @@ def main():
         ctx.timing(True)
         s_0 = ctx.stats()
         torch.cuda.synchronize()
-        log("timing %d steps, queue order %d" % (args.steps, order))
+        log("timing %d steps, queue order %d, rebuild interval %s"
+            % (args.steps, order, "automatic" if s.rebuild_interval == 0 else s.rebuild_interval))
         t_0 = time.perf_counter()
         ctx.step(s, args.steps)
         ctx.sync()
@@ -261,24 +265,33 @@ def main():
            s1["build_ms_sum"] / max(s1["build_calls"], 1), walk_share))
     learned = None
     if model is not None:
-        ctx2, st2, u0, u1, v0, v1 = timed_run(2)
-        same = all(bool(torch.equal(a, b)) for a, b in
-                   zip((st.x, st.y, st.z, st.vx, st.vy, st.vz), (st2.x, st2.y, st2.z, st2.vx,
-                                                                 st2.vy, st2.vz)))
-        l_walk = u1["walk_ms_sum"] / max(u1["walk_calls"], 1)
-        learned = {"s_per_step": (v1 - v0) / args.steps, "walk_ms": l_walk,
-                   "plain_over_learned_step": sec_per_step / ((v1 - v0) / args.steps),
-                   "plain_over_learned_walk": walk_ms / l_walk,
+        # plain, learned and size-based orders on one tree schedule (every k-th
+        # step, k the automatic run's mean interval), so that the three runs
+        # are the same computation bit for bit and differ only in time
+        k = max(1, int(round(args.steps / max(rebuilds, 1)))) if args.rebuild == 0 else args.rebuild
+        runs = {}
+        for order, name in ((0, "plain"), (2, "learned"), (1, "size_based")):
+            c_, s_, a0_, a1_, b0_, b1_ = timed_run(order, rebuild=k)
+            runs[name] = {"s_per_step": (b1_ - b0_) / args.steps,
+                          "walk_ms": a1_["walk_ms_sum"] / max(a1_["walk_calls"], 1),
+                          "state": [t.clone() for t in (s_.x, s_.y, s_.z, s_.vx, s_.vy, s_.vz,
+                                                        s_.ax, s_.ay, s_.az)]}
+            log("%s order, rebuild every %d: s/step %.4g, walk %.3f ms"
+                % (name, k, runs[name]["s_per_step"], runs[name]["walk_ms"]))
+            del c_, s_
+        same = all(all(bool(torch.equal(u, v)) for u, v in zip(runs["plain"]["state"],
+                                                                   runs[o]["state"]))
+                   for o in ("learned", "size_based"))
+        for r in runs.values():
+            del r["state"]
+        learned = {"rebuild_interval": k, "plain": runs["plain"], "learned": runs["learned"],
+                   "size_based": runs["size_based"],
+                   "plain_over_learned_step": runs["plain"]["s_per_step"]
+                   / runs["learned"]["s_per_step"],
+                   "plain_over_learned_walk": runs["plain"]["walk_ms"] / runs["learned"]["walk_ms"],
                    "states_bit_identical": bool(same), **model["report"]}
-        log("learned order: s/step %.4g (plain/learned x%.3f), walk %.3f ms (x%.3f), "
-            "states bit-identical %s" % (learned["s_per_step"], learned["plain_over_learned_step"],
-                                         l_walk, learned["plain_over_learned_walk"], same))
-        del ctx2, st2
-        ctx3, st3, w0, w1, y0, y1 = timed_run(1)
-        s_walk = w1["walk_ms_sum"] / max(w1["walk_calls"], 1)
-        learned["size_based"] = {"s_per_step": (y1 - y0) / args.steps, "walk_ms": s_walk}
-        log("size-based order: s/step %.4g, walk %.3f ms" % ((y1 - y0) / args.steps, s_walk))
-        del ctx3, st3
+        log("plain/learned: step x%.3f, walk x%.3f; states bit-identical %s"
+            % (learned["plain_over_learned_step"], learned["plain_over_learned_walk"], same))
     levels = None
     if block:
         levels = np.bincount(st.level.cpu().numpy(), minlength=11).tolist()

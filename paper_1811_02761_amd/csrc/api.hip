@@ -208,6 +208,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   // 4 x the walk's wavefronts (no walk splits a longer queue)
   L.split_slots = std::max<int64_t>(1, std::min<int64_t>(4 * L.walk_waves, n));
   L.off_split = take((size_t)kSplitSlotBytes * (size_t)L.split_slots);
+  L.off_gid = take(4 * N);
+  L.off_gflag = take(4 * N);
   L.total = o;
   return L;
 }
@@ -275,6 +277,8 @@ Ptrs carve(void *base, const Layout &L) {
   P.inv = reinterpret_cast<uint32_t *>(b + L.off_inv);
   P.asort = reinterpret_cast<float4 *>(b + L.off_asort);
   P.split = reinterpret_cast<float *>(b + L.off_split);
+  P.gid = reinterpret_cast<uint32_t *>(b + L.off_gid);
+  P.gflag = reinterpret_cast<uint32_t *>(b + L.off_gflag);
   return P;
 }
 
@@ -714,6 +718,7 @@ nbody_status nbody_bind_workspace(nbody_ctx *ctx, void *dev_ptr, size_t bytes,
   ctx->sticky = NBODY_OK;
   hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
   launch_fill_u32(ctx->P.plast, 0u, n_max, ctx->st);
+  launch_fill_u32(ctx->P.gflag, 0u, n_max, ctx->st);  // cleared again by each queue build
   return hip_status();
 }
 

@@ -178,29 +178,50 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_open_drift(
   }
 }
 
-__device__ __forceinline__ bool group_active(uint32_t g, uint32_t ng,
-                                             const uint32_t *__restrict__ gbegin,
-                                             const uint32_t *__restrict__ gcount,
-                                             const uint32_t *__restrict__ perm,
-                                             const int8_t *__restrict__ level, long long tick) {
-  if (g >= ng) return false;
-  const uint32_t b = gbegin[g], c = gcount[g];
-  bool act = false;
-  for (uint32_t j = 0; j < c && !act; ++j)
-    act = on_boundary(tick, clamp_level(level[perm[b + j]]));
-  return act;
+// Groups holding a particle whose step ends at the current tick: one thread
+// per sorted particle flags its group (same value, any order).
+__global__ __launch_bounds__(kBlkThreads) void k_blk_mark(int64_t n,
+                                                          const DevScalars *__restrict__ sc,
+                                                          const uint32_t *__restrict__ perm,
+                                                          const uint32_t *__restrict__ gid,
+                                                          const int8_t *__restrict__ level,
+                                                          uint32_t *__restrict__ gflag) {
+  const long long tick = sc->tick;
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    if (on_boundary(tick, clamp_level(level[perm[s]]))) gflag[gid[s]] = 1u;
 }
 
-// Active groups per block of kBlkThreads groups.
-__global__ __launch_bounds__(kBlkThreads) void k_blk_qcount(
-    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
-    const uint32_t *__restrict__ gcount, const uint32_t *__restrict__ perm,
-    const int8_t *__restrict__ level, uint32_t *__restrict__ blk) {
+// Flagged groups per block of kQGroups groups (kQPer consecutive groups per
+// thread).
+constexpr int kQPer = 8;
+constexpr int kQGroups = kBlkThreads * kQPer;
+
+__device__ __forceinline__ uint32_t flagged_run(const DevScalars *__restrict__ sc, uint32_t g0,
+                                                const uint32_t *__restrict__ gflag,
+                                                uint32_t *bits) {
+  const uint32_t ng = sc->ngroup;
+  uint32_t c = 0, m = 0;
+#pragma unroll
+  for (int k = 0; k < kQPer; ++k) {
+    const uint32_t g = g0 + (uint32_t)k;
+    const bool f = g < ng && gflag[g] != 0u;
+    m |= (f ? 1u : 0u) << k;
+    c += f ? 1u : 0u;
+  }
+  *bits = m;
+  return c;
+}
+
+__global__ __launch_bounds__(kBlkThreads) void k_blk_qcount(const DevScalars *__restrict__ sc,
+                                                            const uint32_t *__restrict__ gflag,
+                                                            uint32_t *__restrict__ blk) {
   __shared__ uint32_t wc[kBlkThreads / 64];
-  const uint32_t g = blockIdx.x * kBlkThreads + threadIdx.x;
-  const bool act = group_active(g, sc->ngroup, gbegin, gcount, perm, level, sc->tick);
-  const uint64_t b = __ballot(act);
-  if (lane_id() == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+  const uint32_t g0 = (blockIdx.x * kBlkThreads + threadIdx.x) * kQPer;
+  uint32_t bits;
+  uint32_t c = flagged_run(sc, g0, gflag, &bits);
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if (lane_id() == 0) wc[threadIdx.x >> 6] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t s = 0;
@@ -209,22 +230,27 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_qcount(
   }
 }
 
-// Active groups in group order (blk holds exclusive block offsets).
-__global__ __launch_bounds__(kBlkThreads) void k_blk_qemit(
-    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
-    const uint32_t *__restrict__ gcount, const uint32_t *__restrict__ perm,
-    const int8_t *__restrict__ level, const uint32_t *__restrict__ blk,
-    uint32_t *__restrict__ order) {
+// The flagged groups in group order (blk holds exclusive block offsets); the
+// flags are cleared for the next step.
+__global__ __launch_bounds__(kBlkThreads) void k_blk_qemit(const DevScalars *__restrict__ sc,
+                                                           uint32_t *__restrict__ gflag,
+                                                           const uint32_t *__restrict__ blk,
+                                                           uint32_t *__restrict__ order) {
   __shared__ uint32_t wc[kBlkThreads / 64];
-  const uint32_t g = blockIdx.x * kBlkThreads + threadIdx.x;
-  const bool act = group_active(g, sc->ngroup, gbegin, gcount, perm, level, sc->tick);
-  const uint64_t b = __ballot(act);
+  const uint32_t g0 = (blockIdx.x * kBlkThreads + threadIdx.x) * kQPer;
+  uint32_t bits;
+  const uint32_t c = flagged_run(sc, g0, gflag, &bits);
+  const uint32_t inc = wave_incl_scan(c);
   const int w = threadIdx.x >> 6;
-  if (lane_id() == 0) wc[w] = (uint32_t)__popcll(b);
+  if (lane_id() == 63) wc[w] = inc;
   __syncthreads();
-  uint32_t off = blk[blockIdx.x];
+  uint32_t off = blk[blockIdx.x] + inc - c;
   for (int q = 0; q < w; ++q) off += wc[q];
-  if (act) order[off + (uint32_t)__popcll(b & lanemask_lt())] = g;
+  for (int k = 0; k < kQPer; ++k)
+    if (bits & (1u << k)) {
+      order[off++] = g0 + (uint32_t)k;
+      gflag[g0 + (uint32_t)k] = 0u;
+    }
 }
 
 __global__ void k_blk_qtotal(const uint32_t *__restrict__ total, DevScalars *sc) {
@@ -308,15 +334,19 @@ void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx
 
 void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, const Ptrs &P,
                       hipStream_t st) {
-  // ngroup <= n: one thread per possible group; the build's block-count
-  // buffer (free outside the build) holds the per-block counts and the total
-  const uint32_t nblk = (uint32_t)cdiv(n, kBlkThreads);
+  int64_t gm = cdiv(n, 4 * kBlkThreads);
+  if (gm > 16384) gm = 16384;
+  if (gm < 1) gm = 1;
+  hipLaunchKernelGGL(k_blk_mark, dim3((unsigned)gm), dim3(kBlkThreads), 0, st, n, P.sc, perm,
+                     P.gid, level, P.gflag);
+  // ngroup <= n: blocks for n groups; the build's block-count buffer (free
+  // outside the build) holds the per-block counts and the total
+  const uint32_t nblk = (uint32_t)cdiv(n, kQGroups);
   uint32_t *blk = P.blkcnt, *total = P.blkcnt + nblk;
-  hipLaunchKernelGGL(k_blk_qcount, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gbegin,
-                     P.gcount, perm, level, blk);
+  hipLaunchKernelGGL(k_blk_qcount, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gflag, blk);
   launch_scan_rows(blk, nblk, 1, total, st);
-  hipLaunchKernelGGL(k_blk_qemit, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gbegin,
-                     P.gcount, perm, level, blk, P.order);
+  hipLaunchKernelGGL(k_blk_qemit, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gflag, blk,
+                     P.order);
   hipLaunchKernelGGL(k_blk_qtotal, dim3(1), dim3(64), 0, st, total, P.sc);
 }
 

@@ -344,11 +344,13 @@ __global__ __launch_bounds__(kB) void k_group_count(uint32_t n,
   }
 }
 
-// Group begins in particle order (gblk holds exclusive block offsets).
+// Group begins in particle order (gblk holds exclusive block offsets), and
+// each particle's group (the number of group starts up to it, minus one).
 __global__ __launch_bounds__(kB) void k_group_emit(uint32_t n,
                                                    const uint32_t *__restrict__ pinfo,
                                                    const uint32_t *__restrict__ gblk,
-                                                   uint32_t *__restrict__ gbegin) {
+                                                   uint32_t *__restrict__ gbegin,
+                                                   uint32_t *__restrict__ gid) {
   __shared__ uint32_t wc[kB / 64];
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
   const bool mk = i < n && (pinfo[i] & kGroupMark);
@@ -358,7 +360,9 @@ __global__ __launch_bounds__(kB) void k_group_emit(uint32_t n,
   __syncthreads();
   uint32_t off = gblk[blockIdx.x];
   for (int q = 0; q < w; ++q) off += wc[q];
-  if (mk) gbegin[off + (uint32_t)__popcll(b & lanemask_lt())] = (uint32_t)i;
+  const uint32_t before = (uint32_t)__popcll(b & lanemask_lt());
+  if (mk) gbegin[off + before] = (uint32_t)i;
+  if (i < n) gid[i] = off + before + (mk ? 1u : 0u) - 1u;  // particle 0 starts group 0
 }
 
 __global__ void k_group_total(const uint32_t *__restrict__ total, uint32_t n,
@@ -426,7 +430,7 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   hipLaunchKernelGGL(k_group_count, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk);
   hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, st, gblk, nblk, gtot);
   hipLaunchKernelGGL(k_group_emit, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk,
-                     P.gbegin);
+                     P.gbegin, P.gid);
   hipLaunchKernelGGL(k_group_total, dim3(1), dim3(64), 0, st, gtot, (uint32_t)n, P.sc,
                      P.gbegin);
   hipLaunchKernelGGL(k_group_size, dim3(ge), dim3(256), 0, st, P.sc, P.gbegin, P.gcount);

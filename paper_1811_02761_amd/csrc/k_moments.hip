@@ -93,105 +93,117 @@ __global__ __launch_bounds__(256) void k_mom_level(DevScalars *__restrict__ sc,
   }
 }
 
-// b2 of internal cells: every particle visits its ancestors (leaf excluded)
-// level by level; lanes of one block that share a cell reduce in LDS first,
-// then one atomic max per (block, cell) on the bit pattern (b2 >= 0, so the
-// float order equals the unsigned order).
+// b2 of internal cells: every particle visits its ancestors (leaf excluded),
+// deepest first. One wavefront takes kB2Chunks x 64 consecutive particles,
+// 64 at a time. At each level the lanes whose ancestor sits at that level
+// form runs of equal cell (cells are contiguous particle ranges and numbered
+// in particle order); a segmented max over the runs leaves each run's
+// maximum in its last lane. A run that reaches lane 63 may go on in the next
+// 64 particles: it is carried (lane l of the wave keeps the cell and maximum
+// of level l) instead of stored. Every finished run makes one atomic max on
+// the cell's bit pattern (b2 >= 0, so the float order equals the unsigned
+// order), skipped when the stored value is already as large.
+constexpr int kB2Chunks = 16;
+constexpr uint32_t kNoCell = 0xffffffffu;
+
+__device__ __forceinline__ void b2_store(float4 *__restrict__ nodeA, uint32_t c, uint32_t v) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(&nodeA[c].w);
+  if (v > *w) atomicMax(w, v);
+}
+
 __global__ __launch_bounds__(256) void k_mom_b2(DevScalars *__restrict__ sc, uint32_t n,
                                                 const uint32_t *__restrict__ pinfo,
                                                 const uint32_t *__restrict__ leafof,
                                                 const int32_t *__restrict__ cparent,
                                                 const float4 *__restrict__ xyzm,
                                                 float4 *__restrict__ nodeA) {
-  __shared__ uint32_t slot[256];
-  __shared__ uint32_t red[3][4];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool valid = i < n;
-  slot[threadIdx.x] = 0u;
-  float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-  int lvl = -1;
-  int32_t cur = -1;
-  if (valid) {
-    p = xyzm[i];
-    const int D = (pinfo[i] >> 5) & 31;
-    const uint32_t lf = leafof[i];
-    if (D > 0 && lf < sc->ncell) {
-      cur = cparent[lf];
-      lvl = D - 1;
-    }
-  }
-  const int w = threadIdx.x >> 6;
-  // highest starting level in the block
-  {
-    const uint32_t m = wave_max_u32((uint32_t)(lvl + 1));
-    if (lane_id() == 0) red[0][w] = m;
-  }
-  __syncthreads();
-  int top = (int)max(max(red[0][0], red[0][1]), max(red[0][2], red[0][3])) - 1;
-  __syncthreads();
-  for (int l = top; l >= 0; --l) {
-    bool act = valid && lvl == l;
-    // range of active cells in the block
-    uint32_t cmin = act ? (uint32_t)cur : 0xffffffffu;
-    uint32_t cmax = act ? (uint32_t)cur : 0u;
-    {
-      uint32_t a = cmin, b = cmax;
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t oa = __shfl_xor(a, d, 64), ob = __shfl_xor(b, d, 64);
-        a = oa < a ? oa : a;
-        b = ob > b ? ob : b;
-      }
-      if (lane_id() == 0) {
-        red[1][w] = a;
-        red[2][w] = b;
+  const uint32_t lane = lane_id();
+  const uint32_t ncell = sc->ncell;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t r0 = wave * 64u * kB2Chunks;
+  // carried run of level `lane` (lanes 0 .. kMaxLevel - 1)
+  uint32_t cc = kNoCell, cm = 0u;
+  for (int ch = 0; ch < kB2Chunks; ++ch) {
+    const uint64_t i = r0 + (uint64_t)ch * 64u + lane;
+    if (r0 + (uint64_t)ch * 64u >= n) break;  // wave-uniform
+    const bool valid = i < n;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    int lvl = -1;
+    uint32_t cur = kNoCell;
+    if (valid) {
+      p = xyzm[i];
+      const int D = (pinfo[i] >> 5) & 31;
+      const uint32_t lf = leafof[i];
+      if (D > 0 && lf < ncell) {
+        const int32_t pc = cparent[lf];
+        if (pc >= 0 && (uint32_t)pc < ncell) {
+          cur = (uint32_t)pc;
+          lvl = D - 1;
+        } else {
+          atomicOr(&sc->status, kStCorrupt);
+        }
       }
     }
-    __syncthreads();
-    uint32_t bmin = red[1][0], bmax = red[2][0];
-    for (int q = 1; q < 4; ++q) {
-      bmin = red[1][q] < bmin ? red[1][q] : bmin;
-      bmax = red[2][q] > bmax ? red[2][q] : bmax;
+    const int top = (int)wave_max_u32((uint32_t)(lvl + 1)) - 1;
+    // carried runs above this chunk's deepest ancestor level have ended
+    if ((int)lane > top && lane < (uint32_t)kMaxLevel && cc != kNoCell) {
+      b2_store(nodeA, cc, cm);
+      cc = kNoCell;
+      cm = 0u;
     }
-    uint32_t d2bits = 0u;
-    if (act && (cur < 0 || (uint32_t)cur >= sc->ncell)) {
-      atomicOr(&sc->status, kStCorrupt);
-      act = false;
-    }
-    if (act) {
-      const float4 c = nodeA[cur];
-      const float dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
-      d2bits = __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
-    }
-    // whole wave on one cell: reduce in registers first
-    const uint64_t am = __ballot(act);
-    const int32_t c0 = __shfl(cur, (int)(am ? __builtin_ctzll(am) : 0), 64);
-    const bool same = am != 0 && __ballot(act && cur == c0) == am;
-    if (same) {
-      const uint32_t m = wave_max_u32(d2bits);
-      if (lane_id() == (uint32_t)__builtin_ctzll(am) && (uint32_t)cur - bmin < 256u)
-        atomicMax(&slot[(uint32_t)cur - bmin], m);
-    } else if (act && (uint32_t)cur - bmin < 256u) {
-      atomicMax(&slot[(uint32_t)cur - bmin], d2bits);
-    }
-    __syncthreads();
-    if (bmin != 0xffffffffu && threadIdx.x <= bmax - bmin && bmin + threadIdx.x < sc->ncell) {
-      const uint32_t v = slot[threadIdx.x];
-      const uint32_t c = bmin + threadIdx.x;
-      if (v > __float_as_uint(nodeA[c].w))
-        atomicMax(reinterpret_cast<uint32_t *>(&nodeA[c].w), v);
-      slot[threadIdx.x] = 0u;
-    }
-    __syncthreads();
-    if (act) {
-      cur = cparent[cur];
-      lvl = l - 1;
-      if (l > 0 && (cur < 0 || (uint32_t)cur >= sc->ncell)) {
-        atomicOr(&sc->status, kStCorrupt);
-        lvl = -1;
+    for (int l = top; l >= 0; --l) {
+      const bool act = lvl == l;
+      // inactive lanes get keys of their own (above any cell index)
+      const uint32_t key = act ? cur : (kNoCell ^ lane);
+      uint32_t v = 0u;
+      if (act) {
+        const float4 c = nodeA[cur];
+        const float dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
+        v = __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+      }
+      const uint32_t kprev = __shfl_up(key, 1, 64);
+      const uint32_t knext = __shfl_down(key, 1, 64);
+      const bool first = lane == 0 || kprev != key;
+      const bool last = lane == 63 || knext != key;
+      // start lane of each run, then the segmented inclusive max
+      uint32_t st = first ? lane : 0u;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(st, d, 64);
+        if (lane >= (uint32_t)d && o > st) st = o;
+      }
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= st + (uint32_t)d && o > v) v = o;
+      }
+      // the carried run of level l goes on iff lane 0 continues its cell
+      const uint32_t ccl = __builtin_amdgcn_readlane(cc, l);
+      const uint32_t cml = __builtin_amdgcn_readlane(cm, l);
+      const uint32_t k0 = __builtin_amdgcn_readfirstlane(key);
+      const bool merge = ccl != kNoCell && k0 == ccl;
+      if (ccl != kNoCell && !merge && lane == 0) b2_store(nodeA, ccl, cml);
+      if (merge && st == 0u && cml > v) v = cml;
+      // runs ending before lane 63 are finished; the run at lane 63 is carried
+      if (act && last && lane != 63) b2_store(nodeA, key, v);
+      const uint32_t k63 = __builtin_amdgcn_readlane(key, 63);
+      const uint32_t v63 = __builtin_amdgcn_readlane(v, 63);
+      const bool act63 = k63 < ncell;
+      if (lane == (uint32_t)l) {
+        cc = act63 ? k63 : kNoCell;
+        cm = act63 ? v63 : 0u;
+      }
+      if (act) {
+        const uint32_t up = l > 0 ? (uint32_t)cparent[cur] : kNoCell;
+        if (l > 0 && up >= ncell) {
+          atomicOr(&sc->status, kStCorrupt);
+          lvl = -1;
+        } else {
+          cur = up;
+          lvl = l - 1;
+        }
       }
     }
   }
+  if (lane < (uint32_t)kMaxLevel && cc != kNoCell) b2_store(nodeA, cc, cm);
 }
 
 __global__ __launch_bounds__(256) void k_mom_final(const DevScalars *__restrict__ sc,
@@ -218,8 +230,8 @@ void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L, hipStrea
   for (int l = kMaxLevel - 1; l >= 0; --l)
     hipLaunchKernelGGL(k_mom_level, dim3(gl), dim3(256), 0, st, P.sc, l, P.cpbegin,
                        P.cfchild, P.cnchild, P.xyzm, P.mom64, P.nodeA, P.nodeB);
-  hipLaunchKernelGGL(k_mom_b2, dim3(cdiv(n, 256)), dim3(256), 0, st, P.sc, (uint32_t)n,
-                     P.pinfo, P.leafof, P.cparent, P.xyzm, P.nodeA);
+  hipLaunchKernelGGL(k_mom_b2, dim3(cdiv(n, 4 * 64 * kB2Chunks)), dim3(256), 0, st, P.sc,
+                     (uint32_t)n, P.pinfo, P.leafof, P.cparent, P.xyzm, P.nodeA);
   hipLaunchKernelGGL(k_mom_final, dim3(gc), dim3(256), 0, st, P.sc, G, P.nodeA, P.nodeB);
 }
 

@@ -75,7 +75,7 @@ struct Layout {
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
-      off_inv, off_asort, off_split;
+      off_inv, off_asort, off_split, off_gid, off_gflag;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
@@ -125,6 +125,8 @@ struct Ptrs {
   uint32_t *inv;        // caller index -> sorted position of the current tree
   float4 *asort;        // key-ordered copy of the state's accelerations, |a| in w
   float *split;         // split walk: per queue position 4 x 3 x 64 partial sums
+  uint32_t *gid;        // group of each sorted particle
+  uint32_t *gflag;      // block steps: group holds a particle whose step ends (zero between steps)
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
