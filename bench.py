@@ -118,14 +118,12 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
     }
 
 
-def train_model(ctx, nb, torch, steps, hidden=32):
+def train_model(ctx, nb, torch, feat, target, steps, hidden=32):
     """Train the queue's cost model on the device, by the library's kernels,
-    on the statistics the last walk recorded (features before it, interaction
-    counts after it)."""
+    on walk statistics the method recorded (per walked group: features
+    before the walk, log2 interactions after it)."""
     import nbody_inputs as I
 
-    feat = ctx.export(nb.X.FEAT).reshape(-1, 4).contiguous()
-    target = ctx.export(nb.X.TARGET).contiguous()
     w = torch.as_tensor(I.mlp_init(nb.mlp_nparams(hidden), nb.mlp_fan_in(hidden), 1),
                         device="cuda")
     t0 = time.perf_counter()
@@ -146,6 +144,14 @@ def train_model(ctx, nb, torch, steps, hidden=32):
         % (report["train_rows"], losses[0], losses[-1], t_train,
            report["mean_abs_log2_miss_model"], report["mean_abs_log2_miss_size_based"]))
     return {"hidden": hidden, "w": w, "report": report}
+
+
+def walk_rows(ctx, nb, torch):
+    """(features, log2 interactions) of the groups the last walk took."""
+    q = ctx.export(nb.X.QUEUE).long()
+    feat = ctx.export(nb.X.FEAT).reshape(-1, 4)[q]
+    target = ctx.export(nb.X.TARGET)[q]
+    return feat, target
 
 
 def snapshot(st):
@@ -181,6 +187,9 @@ def main():
     ap.add_argument("--group-max", type=int, default=64)
     ap.add_argument("--group-merge", type=int, default=1, choices=(0, 1))
     ap.add_argument("--leaf-max", type=int, default=16)
+    ap.add_argument("--order", type=int, default=0, choices=(0, 1, 2),
+                    help="queue order of the headline run: 0 plain (Morton), 1 size-based, "
+                         "2 learned (needs --learn-steps > 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learn-steps", type=int, default=300,
                     help="Adam steps of the cost model for the plain-vs-learned walks (0: skip)")
@@ -211,9 +220,17 @@ def main():
     ctx0 = nb.Context(params, n_max=args.n)
     ctx0.set_order(1)
     log("warmup %d steps" % args.warmup)
-    ctx0.step(st, max(args.warmup, 1))
+    rows = []
+    for _ in range(max(args.warmup, 1)):
+        ctx0.step(st, 1)
+        if args.learn_steps:
+            rows.append(walk_rows(ctx0, nb, torch))  # every step type of the block cycle
     ctx0.sync()
-    model = train_model(ctx0, nb, torch, args.learn_steps) if args.learn_steps else None
+    model = None
+    if args.learn_steps:
+        feat = torch.cat([r[0] for r in rows]).contiguous()
+        target = torch.cat([r[1] for r in rows]).contiguous()
+        model = train_model(ctx0, nb, torch, feat, target, args.learn_steps)
     snap = snapshot(st)
     del ctx0
 
@@ -249,7 +266,9 @@ def main():
         t_1 = time.perf_counter()
         return ctx, s, s_0, ctx.stats(), t_0, t_1
 
-    ctx, st, s0, s1, t0, t1 = timed_run(0)
+    if args.order == 2 and model is None:
+        sys.exit("--order 2 needs a trained cost model (--learn-steps > 0)")
+    ctx, st, s0, s1, t0, t1 = timed_run(args.order)
     sec_per_step = (t1 - t0) / args.steps
     walks = s1["walk_calls"]
     walk_ms = s1["walk_ms_sum"] / max(walks, 1)
@@ -341,7 +360,7 @@ def main():
             "leaf_max": params.leaf_max,
             "group_max": params.group_max,
             "group_merge": params.group_merge,
-            "order": "plain",
+            "order": ("plain", "size_based", "learned")[args.order],
         },
         "interactions_per_s": inter_per_walk / (walk_ms * 1e-3),
         "interactions_per_step": inter_per_walk,

@@ -198,8 +198,9 @@ enum {
   NBODY_X_XYZM = 17,     /* float32[n][4] sorted positions and masses */
   NBODY_X_BOX = 18,      /* float64[4]: root cube lo x, y, z, side L */
   NBODY_X_QUEUE = 19,    /* uint32[queued] groups walked by the last walk, in order */
-  NBODY_X_FEAT = 20,     /* float32[ngroup][4] cost-model features (orders 1, 2) */
-  NBODY_X_TARGET = 21,   /* float32[ngroup] log2 interactions of the last walk */
+  NBODY_X_FEAT = 20,     /* float32[ngroup][4] cost-model features (orders 1, 2;
+                            set for the groups of the last walk's queue) */
+  NBODY_X_TARGET = 21,   /* float32[ngroup] log2 interactions (groups of the last walk) */
   NBODY_X_PRED = 22,     /* float32[ngroup] the model's prediction (order 2) */
   NBODY_X_SYSBOX = 23,   /* float64[n_sys][4] batch: each system's root cube lo, L */
   NBODY_X_GROOT = 24     /* uint32[ngroup] batch: each group's walk root cell */
@@ -302,14 +303,17 @@ nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable);
 /* Host-only rebuild rule used by nbody_step when rebuild_interval == 0
  * (the paper tunes the rebuild interval to minimise tree-construction plus
  * gravity time, Sec. 1 and Sec. 4.1). excess_ms is the measured extra walk
- * time of the current tree: each walk adds t_walk (1 - I_ref / I), with I
- * the interactions of the groups it walked and I_ref the same groups'
- * interactions on their first walk of this tree. Returns 1 (rebuild) iff
+ * time of the current tree: each walk adds t_walk (1 - I_ref / I), where,
+ * over the groups this walk and the tree's reference walk (its first walk
+ * with the acceleration criterion) both took, I is their interactions now and
+ * I_ref then (the whole walk is taken to have grown by the same factor; with
+ * block steps the groups walked every step are the heavy ones that dominate
+ * the walk time). Returns 1 (rebuild) iff
  * steps_since >= max_interval or excess_ms >= t_build_ms; 0 if steps_since
  * <= 0. For an excess growing linearly per step this rebuilds at the interval
  * that minimises the mean cost per step (the cumulative excess then equals
- * the build time). nbody_step lets at most one walk go unmeasured before it
- * decides. Pure function, no device access. */
+ * the build time). nbody_step decides once every earlier walk is measured.
+ * Pure function, no device access. */
 int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms,
                              int32_t steps_since, int32_t max_interval);
 
@@ -318,17 +322,21 @@ int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms,
  * group's log2 interaction count from NBODY_X_FEAT-style features: log2 of
  * the member count, log2(h + 2^-40) with h half the diagonal of the members'
  * box, log2 of the group mass minus 3x the previous value, and log2(1 + the
- * members' mean list length from their last walk). Weights: FP32, row-major
+ * members' mean list length from their last walk on the current tree; 0 for
+ * members not walked since the tree was built). Weights: FP32, row-major
  * output-major, mu[4] is[4] W1[H][4] b1[H] W2[H][H] b2[H] W3[H] b3; the
  * inputs are standardised first, z = (f - mu) * is, with mu, is constants of
- * the model (their gradient entries are 0). All arrays are
+ * the model (their gradient entries are 0). The network's output is a
+ * correction to the size-based estimate f0 + f3 (log2 count + log2(1 + mean
+ * previous list length)): the prediction is y = net(z) + (f0 + f3). All arrays are
  * device memory; feat is [rows][4] FP32, 16-byte aligned. Calls enqueue on
  * the context's stream (they need a bound workspace for scratch). */
 
 /* Number of weights for `hidden`, or -1 if hidden is not supported. */
 int64_t nbody_mlp_nparams(int32_t hidden);
 
-/* y[r] = the network's output for feat[r]. */
+/* y[r] = the model's prediction for feat[r] (the network's output plus
+ * feat[r][0] + feat[r][3]). */
 nbody_status nbody_mlp_forward(nbody_ctx *ctx, int32_t hidden, const float *w,
                                int64_t rows, const float *feat, float *y);
 

@@ -31,6 +31,7 @@ struct nbody_ctx {
   int32_t since_rebuild = 0;
   int64_t epoch = 0;      // tree builds so far (tags the spans of each tree)
   double excess_ms = 0.0;  // measured extra walk time of the current tree
+  int64_t mac_walks = 0;   // walks of the current tree with the acceleration criterion
   double t_build_ms = 0.0, t_walk_ms = 0.0;  // latest measured (events)
   // timed spans: a ring of (start, end, done) events around each tree build
   // and each walk launch; a walk span's done event follows the copy of its
@@ -421,9 +422,9 @@ void span_end(nbody_ctx *ctx, int i) {
 
 // After the end event of walk span i: its statistics to pinned memory, then
 // the span's done event.
-void span_stats(nbody_ctx *ctx, int i, bool queued) {
+void span_stats(nbody_ctx *ctx, int i, bool queued, bool record) {
   if (i < 0) return;
-  launch_walk_stat(queued, ctx->P, ctx->st);
+  launch_walk_stat(queued, record, ctx->P, ctx->st);
   (void)hipMemcpyAsync(&ctx->aux[i], &ctx->P.sc->wstat, sizeof(WalkStat),
                        hipMemcpyDeviceToHost, ctx->st);
 }
@@ -464,9 +465,11 @@ void harvest(nbody_ctx *ctx, bool block) {
         ctx->walk_calls++;
         ctx->queued_sum += w.queued;
         ctx->ngroup_sum += w.ngroup;
-        // extra time of this walk over the same groups on a fresh tree
-        if (ctx->span_epoch[i] == ctx->epoch && w.inter > 0 && w.inter_ref < w.inter)
-          ctx->excess_ms += ms * (1.0 - (double)w.inter_ref / (double)w.inter);
+        // extra time of this walk over a walk on the fresh tree: the groups
+        // that the reference walk also took have grown from inter_ref to
+        // inter_a interactions; the whole walk is taken to have grown alike
+        if (ctx->span_epoch[i] == ctx->epoch && w.inter_ref > 0 && w.inter_ref < w.inter_a)
+          ctx->excess_ms += ms * (1.0 - (double)w.inter_ref / (double)w.inter_a);
       }
     }
     ctx->sp_head = (ctx->sp_head + 1) % nbody_ctx::kSpans;
@@ -480,6 +483,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
   if (ctx->sys_r > 0 && n != ctx->sys_n) return NBODY_EINVAL;  // not the configured batch
   ctx->epoch++;
   ctx->excess_ms = 0.0;
+  ctx->mac_walks = 0;
   const int sp = span_begin(ctx, 0);
   if (ctx->sys_r > 0) {
     launch_sys_keys(x, y, z, n, ctx->nsys, ctx->sys_r, P, ctx->st);
@@ -499,6 +503,8 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
   span_end(ctx, sp);
   span_done(ctx, sp);
   launch_fill_u32(P.gref, 0u, n, ctx->st);
+  // previous list lengths are those of walks on the current tree (0: none yet)
+  launch_fill_u32(P.plast, 0u, n, ctx->st);
   ctx->keys = ks;
   ctx->perm = pm;
   ctx->n = n;
@@ -551,7 +557,7 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   // the learned order needs an installed model; until then the queue is plain
   const int mode = (ctx->order == 2 && ctx->mlp_hidden == 0) ? 0 : ctx->order;
   if (mode != 0) {
-    launch_cost_features(ctx->n, ctx->perm, P, ctx->st);
+    launch_cost_features(ctx->n, queued, ctx->perm, P, ctx->st);
     launch_cost_order(ctx->n, queued, mode, ctx->mlp_hidden, P, ctx->st);
   }
   const bool use_queue = queued || mode != 0;
@@ -562,7 +568,10 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   launch_walk(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
   span_end(ctx, sp);
   launch_walk_retry(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
-  span_stats(ctx, sp, use_queue);
+  // the tree's first walk with the acceleration criterion is its reference
+  const bool record = !boot && ctx->mac_walks == 0;
+  if (!boot) ctx->mac_walks++;
+  span_stats(ctx, sp, use_queue, record);
   span_done(ctx, sp);
   ctx->last_queued = use_queue;
   if (mode != 0) launch_cost_after(ctx->n, true, ctx->perm, P, ctx->st);
@@ -626,11 +635,13 @@ int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms, int32_t steps_
 }  // extern "C"
 
 namespace {
-// Before a step's decision: wait until at most one walk is unmeasured (the
-// previous step's), so the rule never runs far behind the device.
+// Before a step's decision: wait until every walk so far is measured (the
+// previous step's included). Deciding one walk behind rebuilt a step late,
+// and the walk cost grows fast with the age of the tree; the wait costs little
+// because the previous step's closing kernels are still queued behind its walk.
 bool rebuild_due(nbody_ctx *ctx, int32_t max_interval) {
   harvest(ctx, false);
-  while (pending_walks(ctx) > 1) harvest(ctx, true);
+  while (pending_walks(ctx) > 0) harvest(ctx, true);
   return nbody_rebuild_decide(ctx->t_build_ms, ctx->excess_ms, ctx->since_rebuild,
                               max_interval) != 0;
 }

@@ -29,15 +29,16 @@ __device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
 
 // One wavefront per group (wave-uniform loop; all lanes store the result).
 __global__ __launch_bounds__(256) void k_cost_features(
-    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
-    const uint32_t *__restrict__ gcount, const float4 *__restrict__ xyzm,
-    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ plast,
-    float4 *__restrict__ feat) {
-  const uint32_t ng = sc->ngroup;
+    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ queue,
+    const uint32_t *__restrict__ gbegin, const uint32_t *__restrict__ gcount,
+    const float4 *__restrict__ xyzm, const uint32_t *__restrict__ perm,
+    const uint32_t *__restrict__ plast, float4 *__restrict__ feat) {
+  const uint32_t nq = queue ? sc->nqueue : sc->ngroup;
   const uint32_t wstride = gridDim.x * (blockDim.x >> 6);
-  const uint32_t g0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+  const uint32_t q0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
                                                      (threadIdx.x >> 6));
-  for (uint32_t g = g0; g < ng; g += wstride) {
+  for (uint32_t q = q0; q < nq; q += wstride) {
+    const uint32_t g = queue ? queue[q] : q;
     const uint32_t b = gbegin[g], c = gcount[g];
     const uint32_t k = lane_id();
     const bool ok = k < c;
@@ -83,7 +84,9 @@ __global__ __launch_bounds__(256) void k_cost_after(
 // Weight layout (row-major, output-major): mu[4] is[4] W1[H][4] b1[H]
 // W2[H][H] b2[H] W3[H] b3. The inputs are standardised first, z = (f - mu)
 // * is; mu and is are constants of the model (set from the training data),
-// not trained.
+// not trained. The network's output is a correction to the size-based
+// estimate f.x + f.w (log2 of the group size times one plus the members' mean
+// previous list length): prediction = net(z) + (f.x + f.w).
 __host__ __device__ constexpr int mlp_np(int H) { return 8 + 7 * H + H * H + 1; }
 
 // Forward, one thread per row; the weights are staged in LDS. rows_dev
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ w
       for (int k = 0; k < H; ++k) s = __builtin_fmaf(W2[u * H + k], h1[k], s);
       out = __builtin_fmaf(W3[u], tanhf(s), out);
     }
-    y[r] = out;
+    y[r] = out + (fr.x + fr.w);
   }
 }
 
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ w, i
 #pragma unroll
     for (int k = 0; k < H; ++k) s2 = __builtin_fmaf(sW2[uu * H + k], __shfl(h1, k, 64), s2);
     const float h2 = on ? tanhf(s2) : 0.0f;
-    const float yv = bb3 + wave_sum_f(w3 * h2);
+    const float yv = (bb3 + wave_sum_f(w3 * h2)) + (fr.x + fr.w);
     const float e = yv - target[r];
     const float dy = 2.0f * e * inv_rows;
     loss = __builtin_fmaf(e, e, loss);
@@ -361,9 +364,11 @@ void launch_mlp_standardize(const float4 *feat, int64_t rows, float *w, hipStrea
   hipLaunchKernelGGL(k_mlp_standardize, dim3(1), dim3(256), 0, st, feat, rows, w);
 }
 
-void launch_cost_features(int64_t n, const uint32_t *perm, const Ptrs &P, hipStream_t st) {
+void launch_cost_features(int64_t n, bool queued, const uint32_t *perm, const Ptrs &P,
+                          hipStream_t st) {
   hipLaunchKernelGGL(k_cost_features, dim3(grid_for(n, 4 * 8, 8192)), dim3(256), 0, st, P.sc,
-                     P.gbegin, P.gcount, P.xyzm, perm, P.plast, P.feat);
+                     queued ? P.order : nullptr, P.gbegin, P.gcount, P.xyzm, perm, P.plast,
+                     P.feat);
 }
 
 void launch_cost_after(int64_t n, bool queued, const uint32_t *perm, const Ptrs &P,

@@ -161,35 +161,49 @@ __global__ __launch_bounds__(256) void k_mom_b2(DevScalars *__restrict__ sc, uin
         const float dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
         v = __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
       }
-      const uint32_t kprev = __shfl_up(key, 1, 64);
-      const uint32_t knext = __shfl_down(key, 1, 64);
-      const bool first = lane == 0 || kprev != key;
-      const bool last = lane == 63 || knext != key;
-      // start lane of each run, then the segmented inclusive max
-      uint32_t st = first ? lane : 0u;
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(st, d, 64);
-        if (lane >= (uint32_t)d && o > st) st = o;
-      }
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= st + (uint32_t)d && o > v) v = o;
-      }
-      // the carried run of level l goes on iff lane 0 continues its cell
       const uint32_t ccl = __builtin_amdgcn_readlane(cc, l);
       const uint32_t cml = __builtin_amdgcn_readlane(cm, l);
       const uint32_t k0 = __builtin_amdgcn_readfirstlane(key);
-      const bool merge = ccl != kNoCell && k0 == ccl;
-      if (ccl != kNoCell && !merge && lane == 0) b2_store(nodeA, ccl, cml);
-      if (merge && st == 0u && cml > v) v = cml;
-      // runs ending before lane 63 are finished; the run at lane 63 is carried
-      if (act && last && lane != 63) b2_store(nodeA, key, v);
       const uint32_t k63 = __builtin_amdgcn_readlane(key, 63);
-      const uint32_t v63 = __builtin_amdgcn_readlane(v, 63);
-      const bool act63 = k63 < ncell;
-      if (lane == (uint32_t)l) {
-        cc = act63 ? k63 : kNoCell;
-        cm = act63 ? v63 : 0u;
+      if (__ballot(act) == ~0ull && k0 == k63) {
+        // the whole chunk is one run (the common case above the leaves)
+        v = wave_max_u32(v);
+        if (ccl == k0) {
+          v = cml > v ? cml : v;
+        } else if (ccl != kNoCell && lane == 0) {
+          b2_store(nodeA, ccl, cml);
+        }
+        if (lane == (uint32_t)l) {
+          cc = k0;
+          cm = v;
+        }
+      } else {
+        const uint32_t kprev = __shfl_up(key, 1, 64);
+        const uint32_t knext = __shfl_down(key, 1, 64);
+        const bool first = lane == 0 || kprev != key;
+        const bool last = lane == 63 || knext != key;
+        // start lane of each run, then the segmented inclusive max
+        uint32_t st = first ? lane : 0u;
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t o = __shfl_up(st, d, 64);
+          if (lane >= (uint32_t)d && o > st) st = o;
+        }
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t o = __shfl_up(v, d, 64);
+          if (lane >= st + (uint32_t)d && o > v) v = o;
+        }
+        // the carried run of level l goes on iff lane 0 continues its cell
+        const bool merge = ccl != kNoCell && k0 == ccl;
+        if (ccl != kNoCell && !merge && lane == 0) b2_store(nodeA, ccl, cml);
+        if (merge && st == 0u && cml > v) v = cml;
+        // runs ending before lane 63 are finished; the run at lane 63 is carried
+        if (act && last && lane != 63) b2_store(nodeA, key, v);
+        const uint32_t v63 = __builtin_amdgcn_readlane(v, 63);
+        const bool act63 = k63 < ncell;
+        if (lane == (uint32_t)l) {
+          cc = act63 ? k63 : kNoCell;
+          cm = act63 ? v63 : 0u;
+        }
       }
       if (act) {
         const uint32_t up = l > 0 ? (uint32_t)cparent[cur] : kNoCell;

@@ -573,50 +573,60 @@ __global__ void k_walk_stat_zero(DevScalars *sc) {
     sc->wstat.ngroup = sc->ngroup;
     sc->wstat.queued = 0;
     sc->wstat.inter = 0;
+    sc->wstat.inter_a = 0;
     sc->wstat.inter_ref = 0;
   }
 }
 
-// Interactions of the walked groups now and on their first walk of this
-// tree (recorded here); integer sums, so the atomics are exact.
+// Interactions of the walked groups, and of those the tree's reference walk
+// also took, now and then (the reference walk records them here); integer
+// sums, so the atomics are exact.
 __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
                                                    const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ gcount,
                                                    const uint32_t *__restrict__ gent,
-                                                   uint32_t *__restrict__ gref) {
-  __shared__ unsigned long long s_cur[4], s_ref[4];
+                                                   uint32_t *__restrict__ gref, int record) {
+  __shared__ unsigned long long s_cur[4], s_a[4], s_ref[4];
   const uint32_t nq = order ? sc->nqueue : sc->ngroup;
-  unsigned long long cur = 0, ref = 0;
+  unsigned long long cur = 0, cur_a = 0, ref = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq;
        q += gridDim.x * blockDim.x) {
     const uint32_t g = order ? order[q] : q;
     const uint32_t e = gent[g], c = gcount[g];
     if (e == 0xffffffffu) continue;
+    const unsigned long long ec = (unsigned long long)e * c;
+    cur += ec;
     uint32_t r = gref[g];
-    if (r == 0) {
+    if (record && r == 0) {
       r = e;
       gref[g] = e;
     }
-    cur += (unsigned long long)e * c;
-    ref += (unsigned long long)r * c;
+    if (r != 0) {
+      cur_a += ec;
+      ref += (unsigned long long)r * c;
+    }
   }
   for (int d = 32; d >= 1; d >>= 1) {
     cur += __shfl_xor(cur, d, 64);
+    cur_a += __shfl_xor(cur_a, d, 64);
     ref += __shfl_xor(ref, d, 64);
   }
   if (lane_id() == 0) {
     s_cur[threadIdx.x >> 6] = cur;
+    s_a[threadIdx.x >> 6] = cur_a;
     s_ref[threadIdx.x >> 6] = ref;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long a = 0, b = 0;
+    unsigned long long a = 0, b = 0, r = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
       a += s_cur[w];
-      b += s_ref[w];
+      b += s_a[w];
+      r += s_ref[w];
     }
     atomicAdd(&sc->wstat.inter, a);
-    atomicAdd(&sc->wstat.inter_ref, b);
+    atomicAdd(&sc->wstat.inter_a, b);
+    atomicAdd(&sc->wstat.inter_ref, r);
     if (blockIdx.x == 0) sc->wstat.queued = nq;
   }
 }
@@ -648,10 +658,10 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, v, n);
 }
 
-void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st) {
+void launch_walk_stat(bool queued, bool record, const Ptrs &P, hipStream_t st) {
   hipLaunchKernelGGL(k_walk_stat_zero, dim3(1), dim3(64), 0, st, P.sc);
   hipLaunchKernelGGL(k_walk_stat, dim3(256), dim3(256), 0, st, P.sc, queued ? P.order : nullptr,
-                     P.gcount, P.gent, P.gref);
+                     P.gcount, P.gent, P.gref, record ? 1 : 0);
 }
 
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,

@@ -31,8 +31,9 @@ constexpr int32_t kStCorrupt = 8;  // internal consistency check failed
 struct WalkStat {
   uint32_t ngroup, queued;
   unsigned long long inter;      // interactions of the walked groups
-  unsigned long long inter_ref;  // the same groups' interactions on their first
-                                 // walk since the tree was built
+  unsigned long long inter_a;    // interactions of those walked groups that the
+                                 // tree's first (reference) walk also took
+  unsigned long long inter_ref;  // the same groups' interactions in that walk
 };
 
 // Device scalars kept in the workspace.
@@ -118,7 +119,7 @@ struct Ptrs {
   float *mlpw;          // weights in use (largest model)
   float *mlpm, *mlpv, *mlpg;  // Adam moments, gradient + loss (training)
   float *mlppart;       // per-wavefront gradient shares
-  uint32_t *gref;       // per group: list length of its first walk on this tree (0: none)
+  uint32_t *gref;       // per group: list length in the tree's reference walk (0: none)
   uint32_t *sysoff;     // batch: system offsets [kMaxSystems + 1]
   double4 *sysbox;      // batch: per system root cube lo x, y, z, side L
   uint32_t *groot;      // batch: per group the walk's root cell
@@ -219,7 +220,9 @@ void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
                       hipStream_t st);
 
 // sc->wstat of the walk just finished (queued: order[0 .. nqueue), else all)
-void launch_walk_stat(bool queued, const Ptrs &P, hipStream_t st);
+// record: this walk is the tree's reference walk (its first with the
+// acceleration criterion); it stores each walked group's list length in gref
+void launch_walk_stat(bool queued, bool record, const Ptrs &P, hipStream_t st);
 
 // single 8-bit digit pass of the stable radix sort (digit = key >> shift) of
 // the first min(n, *n_dev) entries (n_dev may be null); n bounds the grid
@@ -242,7 +245,9 @@ void launch_adam(int64_t np, float *w, const float *g, float *m, float *v, int s
                  float b1, float b2, float eps, hipStream_t st);
 // w[0 .. 8): the model's input standardisation from the training rows
 void launch_mlp_standardize(const float4 *feat, int64_t rows, float *w, hipStream_t st);
-void launch_cost_features(int64_t n, const uint32_t *perm, const Ptrs &P, hipStream_t st);
+// features of the queued groups (queued) or of every group
+void launch_cost_features(int64_t n, bool queued, const uint32_t *perm, const Ptrs &P,
+                          hipStream_t st);
 void launch_cost_after(int64_t n, bool queued, const uint32_t *perm, const Ptrs &P,
                        hipStream_t st);
 // order[0 .. nqueue) by predicted cost (mode 1: count and previous list

@@ -87,9 +87,10 @@ def test_training_on_device(nb, torch, orc):
     np.testing.assert_allclose(losses[:5], lo, rtol=1e-4)
 
 
-def _walk(nb, torch, ctx, x, y, z, m, a_old):
-    X, Y, Z, M = (_dev(torch, a) for a in (x, y, z, m))
-    ctx.build_tree(X, Y, Z, M)
+def _walk(nb, torch, ctx, x, y, z, m, a_old, build=True):
+    if build:
+        X, Y, Z, M = (_dev(torch, a) for a in (x, y, z, m))
+        ctx.build_tree(X, Y, Z, M)
     acc = ctx.calc_acc(tuple(_dev(torch, a_old[:, k]) for k in range(3)))
     ctx.sync()
     return np.stack([a.cpu().numpy() for a in acc], 1)
@@ -104,10 +105,11 @@ def test_orders_bit_identical_features_and_targets(nb, torch, orc):
     a_old = ref0.acc.astype(np.float32)
     r = orc.tree_forces(x, y, z, m, a_old=a_old, group_merge=params.group_merge)
     ctx = nb.Context(params, n_max=n)
-    plain = _walk(nb, torch, ctx, x, y, z, m, a_old)
+    plain = _walk(nb, torch, ctx, x, y, z, m, a_old)  # builds the tree
     ctx.set_order(1)
-    o1 = _walk(nb, torch, ctx, x, y, z, m, a_old)   # members learn their list length
-    o1b = _walk(nb, torch, ctx, x, y, z, m, a_old)  # features use it
+    # previous list lengths count on the current tree only: walk it again
+    o1 = _walk(nb, torch, ctx, x, y, z, m, a_old, build=False)   # members learn them
+    o1b = _walk(nb, torch, ctx, x, y, z, m, a_old, build=False)  # features use them
     feat = ctx.export(nb.X.FEAT).reshape(-1, 4)
     target = ctx.export(nb.X.TARGET)
     q = ctx.export(nb.X.QUEUE).cpu().numpy()
@@ -128,7 +130,7 @@ def test_orders_bit_identical_features_and_targets(nb, torch, orc):
     losses = ctx.train_cost_model(H, W, feat.contiguous(), target.contiguous(), 300, 1e-2)
     ctx.set_cost_model(H, W)
     ctx.set_order(2)
-    o2 = _walk(nb, torch, ctx, x, y, z, m, a_old)
+    o2 = _walk(nb, torch, ctx, x, y, z, m, a_old, build=False)
     pred = ctx.export(nb.X.PRED).cpu().numpy()
     for a in (o1, o1b, o2):
         np.testing.assert_array_equal(a, plain)

@@ -78,21 +78,23 @@ def test_mlp_gradient_finite_differences(orc):
 
 
 def test_mlp_forward_special_case(orc):
-    # all weights zero except the output bias: the network is the constant b3;
-    # with W1 = 0 and b1 = atanh(0.5), every hidden unit of layer 1 is 0.5.
+    # all weights zero except the output bias: the network is the constant b3,
+    # and the prediction is b3 plus the size-based estimate f0 + f3; with
+    # W1 = 0 and b1 = atanh(0.5), every hidden unit of layer 1 is 0.5.
     H = 4
     npar = orc.mlp_nparams(H)
     w = np.zeros(npar)
     w[4:8] = 1.0  # identity standardisation
     w[-1] = 2.5
     f = np.random.default_rng(1).normal(size=(5, 4))
-    np.testing.assert_array_equal(orc.mlp_forward(w, f, hidden=H), np.full(5, 2.5))
+    skip = f[:, 0] + f[:, 3]
+    np.testing.assert_array_equal(orc.mlp_forward(w, f, hidden=H), 2.5 + skip)
     o = 8
     w[o + 4 * H:o + 5 * H] = math.atanh(0.5)  # b1
     w[o + 5 * H:o + 5 * H + H * H] = 1.0  # W2 = ones -> layer 2 pre-activation = H * 0.5
     w[o + 5 * H + H * H + H:o + 5 * H + H * H + 2 * H] = 1.0  # W3 = ones
     y = orc.mlp_forward(w, f, hidden=H)
-    np.testing.assert_allclose(y, 2.5 + H * math.tanh(H * 0.5), rtol=1e-14)
+    np.testing.assert_allclose(y, 2.5 + H * math.tanh(H * 0.5) + skip, rtol=1e-14, atol=1e-14)
 
 
 def test_mlp_standardisation(orc):
@@ -108,5 +110,7 @@ def test_mlp_standardisation(orc):
     w_id = w.copy()
     w_id[:4] = 0.0
     w_id[4:8] = 1.0
-    np.testing.assert_allclose(orc.mlp_forward(w, f, hidden=H), orc.mlp_forward(w_id, z, hidden=H),
+    # (the size-based term is added to the network's output from the raw inputs)
+    np.testing.assert_allclose(orc.mlp_forward(w, f, hidden=H) - (f[:, 0] + f[:, 3]),
+                               orc.mlp_forward(w_id, z, hidden=H) - (z[:, 0] + z[:, 3]),
                                rtol=1e-12, atol=1e-12)
