@@ -311,6 +311,18 @@ def main():
                    "states_bit_identical": bool(same), **model["report"]}
         log("plain/learned: step x%.3f, walk x%.3f; states bit-identical %s"
             % (learned["plain_over_learned_step"], learned["plain_over_learned_walk"], same))
+        if args.rebuild == 0 and args.order != 2:
+            # the learned order under the automatic rebuild rule, as the headline runs
+            c_, s_, a0_, a1_, b0_, b1_ = timed_run(2)
+            learned["learned_auto_rebuild"] = {
+                "s_per_step": (b1_ - b0_) / args.steps,
+                "walk_ms": a1_["walk_ms_sum"] / max(a1_["walk_calls"], 1),
+                "rebuilds": a1_["rebuilds"] - a0_["rebuilds"]}
+            log("learned order, automatic rebuild: s/step %.4g, walk %.3f ms, %d rebuilds"
+                % (learned["learned_auto_rebuild"]["s_per_step"],
+                   learned["learned_auto_rebuild"]["walk_ms"],
+                   learned["learned_auto_rebuild"]["rebuilds"]))
+            del c_, s_
     levels = None
     if block:
         levels = np.bincount(st.level.cpu().numpy(), minlength=11).tolist()

@@ -164,7 +164,7 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_valsB = take(4 * N);
   L.off_hist = take(4 * ((size_t)kSortRadix * L.sort_blocks + kSortRadix));
   L.off_xyzm = take(16 * N);
-  L.off_x32 = take(12 * N);
+  L.off_x32 = take(16 * N);  // (x, y, z, m) records in caller order
   L.off_pinfo = take(4 * N);
   L.off_leafof = take(4 * N);
   L.off_blkcnt = take(4 * ((size_t)(kLevels + 1) * L.build_blocks + kLevels + 1));
@@ -359,15 +359,14 @@ __global__ void k_scalars_init(DevScalars *sc) {
   sc->nactive = 0;
 }
 
-// FP32 image of FP64 positions (caller order) into x32[3][n].
+// FP32 image of FP64 positions with the masses, (x, y, z, m) records in
+// caller order, into x32.
 __global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *x, const double *y,
-                                                const double *z, float *x32) {
+                                                const double *z, const float *m,
+                                                float4 *x32) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    x32[i] = (float)x[i];
-    x32[n + i] = (float)y[i];
-    x32[2 * n + i] = (float)z[i];
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    x32[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
 }
 
 namespace {
@@ -477,25 +476,34 @@ void harvest(nbody_ctx *ctx, bool block) {
   }
 }
 
-nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
-                      const float *z, const float *m) {
+// The (x, y, z, m) records of x32 as coordinates.
+Coords records(const float *x32) { return Coords{x32, x32 + 1, x32 + 2, x32 + 3, 4}; }
+
+nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   const Ptrs &P = ctx->P;
   if (ctx->sys_r > 0 && n != ctx->sys_n) return NBODY_EINVAL;  // not the configured batch
+  // a mirror of the old tree's key order is carried over to the new one
+  const bool remap = ctx->asort_src && ctx->asort_epoch == ctx->epoch && ctx->have_tree &&
+                     ctx->n == n;
   ctx->epoch++;
   ctx->excess_ms = 0.0;
   ctx->mac_walks = 0;
   const int sp = span_begin(ctx, 0);
   if (ctx->sys_r > 0) {
-    launch_sys_keys(x, y, z, n, ctx->nsys, ctx->sys_r, P, ctx->st);
+    launch_sys_keys(c, n, ctx->nsys, ctx->sys_r, P, ctx->st);
   } else {
-    launch_bbox(x, y, z, n, P.sc, ctx->st);
-    launch_keys(x, y, z, n, P.sc, P.keysA, P.valsA, ctx->st);
+    launch_bbox(c, n, P.sc, ctx->st);
+    launch_keys(c, n, P.sc, P.keysA, P.valsA, ctx->st);
   }
   uint64_t *ks;
   uint32_t *pm;
   launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
               &ks, &pm);
-  launch_gather(x, y, z, m, pm, n, P.xyzm, ctx->st);
+  launch_gather(c, pm, n, P.xyzm, ctx->st);
+  if (remap) {  // (before inv is rewritten; okeys is free outside a walk)
+    launch_asort_remap(pm, P.inv, n, P.asort, reinterpret_cast<float4 *>(P.okeys), ctx->st);
+    ctx->asort_epoch = ctx->epoch;
+  }
   launch_invert(pm, n, P.inv, ctx->st);
   launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, ctx->nsys,
                ctx->sys_r, P, ctx->L, ctx->st);
@@ -512,9 +520,8 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
   return hip_status();
 }
 
-nbody_status do_refit(nbody_ctx *ctx, const float *x, const float *y, const float *z,
-                      const float *m) {
-  launch_gather(x, y, z, m, ctx->perm, ctx->n, ctx->P.xyzm, ctx->st);
+nbody_status do_refit(nbody_ctx *ctx, const Coords &c) {
+  launch_gather(c, ctx->perm, ctx->n, ctx->P.xyzm, ctx->st);
   launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, ctx->st);
   return hip_status();
 }
@@ -537,7 +544,7 @@ void ensure_asort(nbody_ctx *ctx, const nbody_state *st) {
 // Drift output: the key-ordered array of the current tree when the step
 // refits it (same particle set), else the caller-order FP32 image.
 SortedOut drift_out(const nbody_ctx *ctx, const nbody_state *st, bool rebuild) {
-  if (rebuild || !ctx->have_tree || ctx->n != st->n) return SortedOut{nullptr, nullptr, nullptr};
+  if (rebuild || !ctx->have_tree || ctx->n != st->n) return SortedOut{nullptr, nullptr, st->m};
   return SortedOut{ctx->P.xyzm, ctx->P.inv, st->m};
 }
 
@@ -739,7 +746,7 @@ nbody_status nbody_build_tree(nbody_ctx *ctx, int64_t n, const float *x, const f
   if (s != NBODY_OK) return s;
   if (!x || !y || !z || !m || n < 1) return NBODY_EINVAL;
   if (n > ctx->L.n_max) return NBODY_ENOMEM;
-  return do_build(ctx, n, x, y, z, m);
+  return do_build(ctx, n, Coords{x, y, z, m, 1});
 }
 
 nbody_status nbody_refit(nbody_ctx *ctx, const float *x, const float *y, const float *z,
@@ -748,7 +755,7 @@ nbody_status nbody_refit(nbody_ctx *ctx, const float *x, const float *y, const f
   if (s != NBODY_OK) return s;
   if (!ctx->have_tree) return NBODY_ENOTREE;
   if (!x || !y || !z || !m) return NBODY_EINVAL;
-  return do_refit(ctx, x, y, z, m);
+  return do_refit(ctx, Coords{x, y, z, m, 1});
 }
 
 nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *axo, const float *ayo,
@@ -768,15 +775,16 @@ namespace {
 nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   nbody_status s;
   const int64_t n = st->n;
-  float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
+  float *x32 = ctx->P.x32;
   float *tx = ctx->P.atmp, *ty = tx + n, *tz = tx + 2 * n;
   const BlockCfg bc{st->dt, st->eta, ctx->p.eps, st->level_min, st->level_max};
   DevScalars *sc = ctx->P.sc;
   launch_blk_setup((long long)st->tick, sc, ctx->st);
   if (!st->have_acc) {
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>(cdiv(n, 1024), 8192)),
-                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, x32);
-    if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, st->m,
+                       reinterpret_cast<float4 *>(x32));
+    if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
     if ((s = do_calc(ctx, nullptr, nullptr, nullptr, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
@@ -796,7 +804,7 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
                           st->az, st->level, st->dt, sc, x32, drift_out(ctx, st, rebuild),
                           ctx->st);
     if (rebuild) {
-      if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+      if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
     } else {
@@ -821,28 +829,16 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   return NBODY_OK;
 }
 
-}  // namespace
-
-nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
-  nbody_status s = pre(ctx);
-  if (s != NBODY_OK) return s;
-  if (!st || n_steps < 0 || st->n < 1 || !st->x || !st->y || !st->z || !st->vx || !st->vy ||
-      !st->vz || !st->m || !st->ax || !st->ay || !st->az || !(st->dt > 0.0) ||
-      !isfinite(st->dt) || st->rebuild_interval < 0)
-    return NBODY_EINVAL;
-  if (st->level &&
-      (!(st->eta > 0.0) || !isfinite(st->eta) || st->level_min < 0 ||
-       st->level_min > st->level_max || st->level_max > kTickBits || st->tick < 0))
-    return NBODY_EINVAL;
-  if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
-  ctx->asort_src = nullptr;  // the caller may have changed the state since the last call
-  if (st->level) return step_block(ctx, st, n_steps);
+// Global kick-drift-kick steps (no individual levels).
+nbody_status step_global(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
+  nbody_status s;
   const int64_t n = st->n;
-  float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
+  float *x32 = ctx->P.x32;
   if (!st->have_acc) {
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>(cdiv(n, 1024), 8192)),
-                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, x32);
-    if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, st->m,
+                       reinterpret_cast<float4 *>(x32));
+    if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
     if ((s = do_calc(ctx, nullptr, nullptr, nullptr, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
@@ -859,7 +855,7 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32,
                  drift_out(ctx, st, rebuild), ctx->st);
     if (rebuild) {
-      if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+      if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
     } else {
@@ -875,6 +871,26 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     if ((s = hip_status()) != NBODY_OK) return s;
   }
   return NBODY_OK;
+}
+
+}  // namespace
+
+nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!st || n_steps < 0 || st->n < 1 || !st->x || !st->y || !st->z || !st->vx || !st->vy ||
+      !st->vz || !st->m || !st->ax || !st->ay || !st->az || !(st->dt > 0.0) ||
+      !isfinite(st->dt) || st->rebuild_interval < 0)
+    return NBODY_EINVAL;
+  if (st->level &&
+      (!(st->eta > 0.0) || !isfinite(st->eta) || st->level_min < 0 ||
+       st->level_min > st->level_max || st->level_max > kTickBits || st->tick < 0))
+    return NBODY_EINVAL;
+  if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
+  ctx->asort_src = nullptr;  // the caller may have changed the state since the last call
+  s = st->level ? step_block(ctx, st, n_steps) : step_global(ctx, st, n_steps);
+  ctx->asort_src = nullptr;  // and may change it before the next call
+  return s;
 }
 
 nbody_status nbody_direct(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
@@ -1128,13 +1144,13 @@ namespace {
 nbody_status step_body(nbody_ctx *ctx, nbody_state *st, bool rebuild) {
   nbody_status s;
   const int64_t n = st->n;
-  float *x32 = ctx->P.x32, *y32 = x32 + n, *z32 = x32 + 2 * n;
+  float *x32 = ctx->P.x32;
   const float hdt = (float)(0.5 * st->dt);
   launch_kick(n, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, hdt, ctx->st);
   launch_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32,
                drift_out(ctx, st, rebuild), ctx->st);
   if (rebuild) {
-    if ((s = do_build(ctx, n, x32, y32, z32, st->m)) != NBODY_OK) return s;
+    if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
   } else {
     if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
   }

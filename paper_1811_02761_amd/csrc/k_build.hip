@@ -43,35 +43,6 @@ __device__ __forceinline__ int cpl_keys(uint64_t a, uint64_t b) {
   return (__clzll(x) - 1) / 3;
 }
 
-// First index j > i whose key differs from K[i] in the top 3l bits
-// (galloping, then bisection). Level 0: the whole array.
-__device__ uint32_t run_end(const uint64_t *__restrict__ K, uint32_t n, uint32_t i,
-                            int l) {
-  if (l == 0) return n;
-  const int sh = 3 * (kMaxLevel - l);
-  const uint64_t p = K[i] >> sh;
-  uint32_t lo = i, hi = n;
-  uint32_t step = 1;
-  while (true) {
-    const uint64_t j = (uint64_t)lo + step;
-    if (j >= n) break;
-    if ((K[j] >> sh) != p) {
-      hi = (uint32_t)j;
-      break;
-    }
-    lo = (uint32_t)j;
-    step <<= 1;
-  }
-  while (hi - lo > 1) {
-    const uint32_t mid = lo + (hi - lo) / 2;
-    if ((K[mid] >> sh) == p)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return hi;
-}
-
 // In-place doubling: t[s] <- max(t[s .. s + 2^k - 1]) for the valid prefix.
 __device__ void lds_window_max(int *t, int len, int k) {
   for (int j = 0; j < k; ++j) {
@@ -181,26 +152,90 @@ __global__ void k_build_c(const uint32_t *__restrict__ totals, DevScalars *sc,
   sc->ncell = o;
 }
 
-// Pass D: write every cell (l, i).
+// Pass D: write every cell (l, i). The level-l run from i (the cell's
+// particles) ends at the first j > i with s_j <= l, where s_j - 1 is the
+// number of leading octant digits K[j-1] and K[j] share: K[j] leaves i's
+// level-l prefix exactly there. So for the 512 positions from the block's
+// start the pass keeps, per level L, bit masks of {j : s_j <= L} (64-bit
+// ballots); a run end is the first set bit after i and a child count the
+// number of set bits inside the run (level l + 1). The cells starting in a
+// wavefront's 64 particles are dealt out to its lanes, one cell per lane and
+// round. A run longer than kShort goes to a queue that k_build_long serves
+// with a whole wavefront per cell (64 probes per round).
+constexpr uint32_t kShort = kB;
+constexpr uint32_t kLongCell = 0xffffffffu;   // cpcount of a cell left to k_build_long
+constexpr int kSpan = 2 * kB;                 // positions with masks: [b0, b0 + 2 kB)
+constexpr int kChunks = kSpan / 64;
+constexpr int kTasksPerWave = 64 * kLevels;   // (lane, level) pairs of one wavefront
+
+// First set bit of masks m[0 .. kChunks) at relative positions (r0, r1]; -1 if none.
+__device__ __forceinline__ int first_bit(const uint64_t *m, uint32_t r0, uint32_t r1) {
+  for (uint32_t c = (r0 + 1) >> 6; c <= (r1 >> 6); ++c) {
+    uint64_t v = m[c];
+    if (c == ((r0 + 1) >> 6)) v &= ~0ull << ((r0 + 1) & 63);
+    if (c == (r1 >> 6) && (r1 & 63) != 63) v &= (2ull << (r1 & 63)) - 1;
+    if (v) return (int)(c * 64 + __builtin_ctzll(v));
+  }
+  return -1;
+}
+
+// Number of set bits of m at relative positions (r0, r1).
+__device__ __forceinline__ uint32_t count_bits(const uint64_t *m, uint32_t r0, uint32_t r1) {
+  if (r1 <= r0 + 1) return 0;
+  const uint32_t lo = r0 + 1, hi = r1 - 1;  // inclusive
+  uint32_t t = 0;
+  for (uint32_t c = lo >> 6; c <= (hi >> 6); ++c) {
+    uint64_t v = m[c];
+    if (c == (lo >> 6)) v &= ~0ull << (lo & 63);
+    if (c == (hi >> 6) && (hi & 63) != 63) v &= (2ull << (hi & 63)) - 1;
+    t += (uint32_t)__popcll(v);
+  }
+  return t;
+}
+
 __global__ __launch_bounds__(kB) void k_build_d(
-    const uint64_t *__restrict__ K, uint32_t n, const uint32_t *__restrict__ pinfo,
-    const uint32_t *__restrict__ blkcnt, uint32_t nblk, const DevScalars *__restrict__ sc,
-    int64_t cell_cap, int32_t *__restrict__ clevel, uint32_t *__restrict__ cpbegin,
+    const uint32_t *__restrict__ pinfo, uint32_t n, const uint32_t *__restrict__ blkcnt,
+    uint32_t nblk, DevScalars *__restrict__ sc, int64_t cell_cap,
+    int32_t *__restrict__ clevel, uint32_t *__restrict__ cpbegin,
     uint32_t *__restrict__ cpcount, int32_t *__restrict__ cfchild,
     int32_t *__restrict__ cnchild, float4 *__restrict__ nodeB,
     uint32_t *__restrict__ leafof) {
   __shared__ uint32_t wpre[kLevels][kB / 64];
   __shared__ uint32_t lvl_off[kLevels + 1];
-  const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+  __shared__ uint64_t bound[kLevels][kChunks];       // bit j: s_{b0+j} <= level (or past n)
+  __shared__ uint64_t wbal[kB / 64][kLevels];        // per wave and level: lanes starting a cell
+  __shared__ uint8_t s_lo[kB];                       // per particle: first level it starts
+  __shared__ uint16_t tasks[kB / 64][kTasksPerWave];  // (lane << 5) | level
+  const uint32_t b0 = blockIdx.x * kB;
+  const int64_t i = (int64_t)b0 + threadIdx.x;
   const bool valid = i < n;
+  const int w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  // boundary masks: wave w covers chunks 2w and 2w + 1
+  for (int c = 2 * w; c < 2 * w + 2; ++c) {
+    const int64_t q = (int64_t)b0 + c * 64 + lane;
+    const int sq = q < n ? (int)(pinfo[q] & 31u) : 0;
+    for (int L = 0; L < kLevels; ++L) {
+      const uint64_t m = __ballot(sq <= L);
+      if (lane == 0) bound[L][c] = m;
+    }
+  }
   const uint32_t pi = valid ? pinfo[i] : 0u;
   const int s = pi & 31, D = (pi >> 5) & 31;
-  const int w = threadIdx.x >> 6;
   if (threadIdx.x <= kLevels) lvl_off[threadIdx.x] = sc->lvl_off[threadIdx.x];
   for (int l = 0; l < kLevels; ++l) {
     const uint64_t b = __ballot(valid && s <= l && l <= D);
-    if (lane_id() == 0) wpre[l][w] = (uint32_t)__popcll(b);
+    if (lane == 0) {
+      wpre[l][w] = (uint32_t)__popcll(b);
+      wbal[w][l] = b;
+    }
   }
+  s_lo[threadIdx.x] = (uint8_t)s;
+  // this lane's cells as tasks of its wave, in lane order
+  const uint32_t nt = (valid && s <= D) ? (uint32_t)(D - s + 1) : 0u;
+  const uint32_t tinc = wave_incl_scan(nt);
+  const uint32_t ntask = __builtin_amdgcn_readlane(tinc, 63);
+  for (uint32_t t = 0; t < nt; ++t) tasks[w][tinc - nt + t] = (uint16_t)((lane << 5) | (s + t));
   __syncthreads();
   if (threadIdx.x < kLevels) {
     uint32_t o = 0;
@@ -211,41 +246,134 @@ __global__ __launch_bounds__(kB) void k_build_d(
     }
   }
   __syncthreads();
-  const uint64_t lt = lanemask_lt();
-  uint32_t idx_prev = 0;
-  for (int l = 0; l < kLevels; ++l) {
-    const bool bit = valid && s <= l && l <= D;
-    const uint64_t b = __ballot(bit);
-    if (!bit) continue;
+  for (uint32_t t = lane; t < ntask; t += 64) {
+    const uint32_t code = tasks[w][t];
+    const uint32_t k = code >> 5;  // the lane (particle) starting the cell
+    const int l = (int)(code & 31u);
+    const uint32_t r = (uint32_t)w * 64u + k;  // position relative to b0
+    const uint32_t ip = b0 + r;
+    const uint64_t below = (k == 0) ? 0ull : (~0ull >> (64 - k));
     const uint32_t rank = blkcnt[(int64_t)l * nblk + blockIdx.x] + wpre[l][w] +
-                          (uint32_t)__popcll(b & lt);
+                          (uint32_t)__popcll(wbal[w][l] & below);
     const uint32_t idx = lvl_off[l] + rank;
     if ((int64_t)idx >= cell_cap) continue;
-    if (l > s) cfchild[idx_prev] = (int32_t)idx;  // (l-1, i) is internal
-    const uint32_t end = run_end(K, n, (uint32_t)i, l);
-    const uint32_t cnt = end - (uint32_t)i;
+    if (l > (int)s_lo[r]) {  // (l-1, ip) is internal: this is its first child
+      const uint32_t rp = blkcnt[(int64_t)(l - 1) * nblk + blockIdx.x] + wpre[l - 1][w] +
+                          (uint32_t)__popcll(wbal[w][l - 1] & below);
+      cfchild[lvl_off[l - 1] + rp] = (int32_t)idx;
+    }
     clevel[idx] = l;
-    cpbegin[idx] = (uint32_t)i;
+    cpbegin[idx] = ip;
+    const int e = first_bit(bound[l], r, r + kShort);
+    if (e < 0) {  // longer than kShort: counted by the cooperative pass
+      cpcount[idx] = kLongCell;
+      continue;
+    }
+    const uint32_t end = b0 + (uint32_t)e;
+    const uint32_t cnt = end - ip;
     cpcount[idx] = cnt;
     uint32_t *wB = reinterpret_cast<uint32_t *>(&nodeB[idx]);
-    if (l == D) {  // leaf
+    if (l == (int)((pinfo[ip] >> 5) & 31u)) {  // leaf
       cfchild[idx] = -1;
       cnchild[idx] = 0;
-      wB[2] = (uint32_t)i;
+      wB[2] = ip;
       wB[3] = cnt | kLeafBit;
-      for (uint32_t p = (uint32_t)i; p < end; ++p) leafof[p] = idx;
+      for (uint32_t p = ip; p < end; ++p) leafof[p] = idx;
     } else {
-      int nc = 0;
-      uint32_t j = (uint32_t)i;
-      while (j < end) {
-        j = run_end(K, n, j, l + 1);
-        ++nc;
-      }
+      // children: the level-(l+1) runs inside [ip, end)
+      const int nc = 1 + (int)count_bits(bound[l + 1], r, (uint32_t)e);
       cnchild[idx] = nc;
       wB[3] = (uint32_t)nc;
       // wB[2] (first child) is written by pass E
     }
-    idx_prev = idx;
+  }
+}
+
+// End of the level-l run from i, searched by the whole wavefront: a round of
+// 32 exponential probes, then rounds of 63 evenly spaced probes, each
+// narrowing the bracket (K[lo] in the run, position hi past it) 64-fold.
+// Every lane returns the same value; all lanes must call it together.
+__device__ uint32_t wave_run_end(const uint64_t *__restrict__ K, uint32_t n, uint32_t i, int l) {
+  if (l == 0) return n;
+  const int sh = 3 * (kMaxLevel - l);
+  const uint64_t p = K[i] >> sh;
+  const uint32_t lane = lane_id();
+  uint32_t lo = i, hi;
+  {
+    const uint64_t q = (uint64_t)i + (1ull << (lane & 31));
+    const bool past = lane < 32 && (q >= n || (K[q] >> sh) != p);
+    const uint64_t m = __ballot(past);  // lane 31 probes i + 2^31 >= n: never empty
+    const uint32_t t = (uint32_t)__builtin_ctzll(m);
+    const uint64_t e = (uint64_t)i + (1ull << t);
+    hi = e < n ? (uint32_t)e : n;
+    lo = t == 0 ? i : i + (1u << (t - 1));
+  }
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint64_t q = (uint64_t)lo + (uint64_t)(lane + 1) * step;
+    const bool in = lane < 63 && q < hi;
+    const bool past = in && (K[q] >> sh) != p;
+    const uint64_t m = __ballot(past);
+    const uint64_t mi = __ballot(in);
+    if (m == 0) {
+      lo = lo + (uint32_t)(64 - __builtin_clzll(mi)) * step;  // the last probe in range
+    } else {
+      const uint32_t t = (uint32_t)__builtin_ctzll(m);
+      hi = lo + (t + 1) * step;
+      lo = lo + t * step;
+    }
+  }
+  return hi;
+}
+
+// The cells pass D left (count still kLongCell): each wavefront checks 64
+// cells at a time, every nw-th cell (nw wavefronts; the long cells sit
+// together at the top levels, so striding spreads them), and serves the
+// marked ones one after the other, finding the cell's end and, for an
+// internal cell, its children's ends.
+__global__ __launch_bounds__(256) void k_build_long(
+    const uint64_t *__restrict__ K, uint32_t n, const uint32_t *__restrict__ pinfo,
+    const DevScalars *__restrict__ sc, const int32_t *__restrict__ clevel,
+    const uint32_t *__restrict__ cpbegin, uint32_t *__restrict__ cpcount,
+    int32_t *__restrict__ cfchild, int32_t *__restrict__ cnchild,
+    float4 *__restrict__ nodeB, uint32_t *__restrict__ leafof) {
+  const uint32_t nc = sc->ncell;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+                                                     (threadIdx.x >> 6));
+  for (uint64_t b = 0; wv + b * 64u * nw < nc; ++b) {
+    const uint64_t cl = wv + (b * 64u + lane) * nw;
+    uint64_t todo = __ballot(cl < nc && cpcount[cl] == kLongCell);
+    while (todo) {
+      const uint32_t idx = (uint32_t)(wv + (b * 64u + (uint64_t)__builtin_ctzll(todo)) * nw);
+      todo &= todo - 1;
+      const int l = clevel[idx];
+      const uint32_t i = cpbegin[idx];
+      const int D = (pinfo[i] >> 5) & 31;
+      const uint32_t end = wave_run_end(K, n, i, l);
+      const uint32_t cnt = end - i;
+      uint32_t *wB = reinterpret_cast<uint32_t *>(&nodeB[idx]);
+      if (l == D) {  // leaf (an oversized level-21 cell)
+        if (lane == 0) {
+          cfchild[idx] = -1;
+          cnchild[idx] = 0;
+          wB[2] = i;
+          wB[3] = cnt | kLeafBit;
+        }
+        for (uint32_t p = i + lane; p < end; p += 64) leafof[p] = idx;
+      } else {
+        int nch = 0;
+        for (uint32_t j = i; j < end; ++nch) j = wave_run_end(K, n, j, l + 1);
+        if (lane == 0) {
+          cnchild[idx] = nch;
+          wB[3] = (uint32_t)nch;
+        }
+      }
+      // every lane has read the marker before it is overwritten
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) cpcount[idx] = cnt;
+    }
   }
 }
 
@@ -415,9 +543,12 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                      P.pinfo, P.blkcnt, nblk);
   hipLaunchKernelGGL(k_scan_rows, dim3(kLevels), dim3(256), 0, st, P.blkcnt, nblk, totals);
   hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
-  hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, P.pinfo,
-                     P.blkcnt, nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount,
-                     P.cfchild, P.cnchild, P.nodeB, P.leafof);
+  hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, P.pinfo, (uint32_t)n, P.blkcnt,
+                     nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount, P.cfchild,
+                     P.cnchild, P.nodeB, P.leafof);
+  hipLaunchKernelGGL(k_build_long, dim3(1024), dim3(256), 0, st, keys, (uint32_t)n, P.pinfo,
+                     P.sc, P.clevel, P.cpbegin, P.cpcount, P.cfchild, P.cnchild, P.nodeB,
+                     P.leafof);
   int64_t ge = cdiv(n, 256);
   if (ge > 4096) ge = 4096;
   hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.cfchild, P.cnchild,

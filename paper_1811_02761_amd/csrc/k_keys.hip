@@ -18,16 +18,14 @@ __global__ void k_bbox_init(DevScalars *sc) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ x,
-                                              const float *__restrict__ y,
-                                              const float *__restrict__ z,
+__global__ __launch_bounds__(256) void k_bbox(Coords c,
                                               int64_t n, DevScalars *sc) {
   float lo[3] = {INFINITY, INFINITY, INFINITY};
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const float v[3] = {x[i], y[i], z[i]};
+    const float v[3] = {c.x[i * c.stride], c.y[i * c.stride], c.z[i * c.stride]};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       bad |= !isfinite(v[k]);
@@ -78,9 +76,7 @@ __device__ __forceinline__ uint32_t quantise21(float v, double lo, double scale)
   return (uint32_t)t;  // t > 0: truncation is floor
 }
 
-__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
-                                              const float *__restrict__ y,
-                                              const float *__restrict__ z,
+__global__ __launch_bounds__(256) void k_keys(Coords c,
                                               int64_t n, DevScalars *sc,
                                               uint64_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals) {
@@ -109,9 +105,9 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
   }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t qx = quantise21(x[i], lo[0], scale);
-    const uint32_t qy = quantise21(y[i], lo[1], scale);
-    const uint32_t qz = quantise21(z[i], lo[2], scale);
+    const uint32_t qx = quantise21(c.x[i * c.stride], lo[0], scale);
+    const uint32_t qy = quantise21(c.y[i * c.stride], lo[1], scale);
+    const uint32_t qz = quantise21(c.z[i * c.stride], lo[2], scale);
     keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
     vals[i] = (uint32_t)i;
   }
@@ -123,9 +119,7 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
 // Morton key in that cube.
 
 // One workgroup per system: exact bounds, then lo and L of its root cube.
-__global__ __launch_bounds__(256) void k_sys_bbox(const float *__restrict__ x,
-                                                  const float *__restrict__ y,
-                                                  const float *__restrict__ z,
+__global__ __launch_bounds__(256) void k_sys_bbox(Coords c,
                                                   const uint32_t *__restrict__ off,
                                                   double4 *__restrict__ sysbox,
                                                   DevScalars *sc) {
@@ -135,7 +129,7 @@ __global__ __launch_bounds__(256) void k_sys_bbox(const float *__restrict__ x,
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
   for (uint32_t i = a + threadIdx.x; i < b; i += blockDim.x) {
-    const float v[3] = {x[i], y[i], z[i]};
+    const float v[3] = {c.x[i * c.stride], c.y[i * c.stride], c.z[i * c.stride]};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       bad |= !isfinite(v[k]);
@@ -186,9 +180,7 @@ __device__ __forceinline__ uint32_t quantise_bits(float v, double lo, double sca
   return (uint32_t)t;
 }
 
-__global__ __launch_bounds__(256) void k_sys_keys(const float *__restrict__ x,
-                                                  const float *__restrict__ y,
-                                                  const float *__restrict__ z, int64_t n,
+__global__ __launch_bounds__(256) void k_sys_keys(Coords c, int64_t n,
                                                   const uint32_t *__restrict__ off, int nsys,
                                                   int r, const double4 *__restrict__ sysbox,
                                                   uint64_t *__restrict__ keys,
@@ -208,9 +200,9 @@ __global__ __launch_bounds__(256) void k_sys_keys(const float *__restrict__ x,
     }
     const double4 bx = sysbox[lo];
     const double scale = ldexp(1.0, bits) / bx.w;
-    const uint32_t qx = quantise_bits(x[i], bx.x, scale, top);
-    const uint32_t qy = quantise_bits(y[i], bx.y, scale, top);
-    const uint32_t qz = quantise_bits(z[i], bx.z, scale, top);
+    const uint32_t qx = quantise_bits(c.x[i * c.stride], bx.x, scale, top);
+    const uint32_t qy = quantise_bits(c.y[i * c.stride], bx.y, scale, top);
+    const uint32_t qz = quantise_bits(c.z[i * c.stride], bx.z, scale, top);
     keys[i] = ((uint64_t)lo << (3 * bits)) | (spread3(qx) << 2) | (spread3(qy) << 1) |
               spread3(qz);
     vals[i] = (uint32_t)i;
@@ -224,16 +216,14 @@ __global__ __launch_bounds__(256) void k_invert(const uint32_t *__restrict__ per
     inv[perm[s]] = (uint32_t)s;
 }
 
-__global__ __launch_bounds__(256) void k_gather(const float *__restrict__ x,
-                                                const float *__restrict__ y,
-                                                const float *__restrict__ z,
-                                                const float *__restrict__ m,
+__global__ __launch_bounds__(256) void k_gather(Coords c,
                                                 const uint32_t *__restrict__ perm,
                                                 int64_t n, float4 *__restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t p = perm[i];
-    out[i] = make_float4(x[p], y[p], z[p], m[p]);
+    out[i] = c.stride == 4 ? reinterpret_cast<const float4 *>(c.x)[p]
+                           : make_float4(c.x[p], c.y[p], c.z[p], c.m[p]);
   }
 }
 
@@ -244,18 +234,15 @@ static int grid_for(int64_t n, int per_thread, int cap) {
   return (int)g;
 }
 
-void launch_bbox(const float *x, const float *y, const float *z, int64_t n,
-                 DevScalars *sc, hipStream_t st) {
+void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, hipStream_t st) {
   hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, sc);
-  hipLaunchKernelGGL(k_bbox, dim3(grid_for(n, 8, 2048)), dim3(256), 0, st, x, y, z,
-                     n, sc);
+  hipLaunchKernelGGL(k_bbox, dim3(grid_for(n, 8, 2048)), dim3(256), 0, st, c, n, sc);
 }
 
-void launch_sys_keys(const float *x, const float *y, const float *z, int64_t n, int nsys,
-                     int r, const Ptrs &P, hipStream_t st) {
-  hipLaunchKernelGGL(k_sys_bbox, dim3(nsys), dim3(256), 0, st, x, y, z, P.sysoff, P.sysbox,
-                     P.sc);
-  hipLaunchKernelGGL(k_sys_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z, n,
+void launch_sys_keys(const Coords &c, int64_t n, int nsys, int r, const Ptrs &P,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_sys_bbox, dim3(nsys), dim3(256), 0, st, c, P.sysoff, P.sysbox, P.sc);
+  hipLaunchKernelGGL(k_sys_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, c, n,
                      P.sysoff, nsys, r, P.sysbox, P.keysA, P.valsA);
 }
 
@@ -263,16 +250,16 @@ void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t s
   hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, perm, n, inv);
 }
 
-void launch_keys(const float *x, const float *y, const float *z, int64_t n,
-                 DevScalars *sc, uint64_t *keys, uint32_t *vals, hipStream_t st) {
-  hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z, n,
-                     sc, keys, vals);
+void launch_keys(const Coords &c, int64_t n, DevScalars *sc, uint64_t *keys, uint32_t *vals,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, c, n, sc, keys,
+                     vals);
 }
 
-void launch_gather(const float *x, const float *y, const float *z, const float *m,
-                   const uint32_t *perm, int64_t n, float4 *xyzm, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, x, y, z,
-                     m, perm, n, xyzm);
+void launch_gather(const Coords &c, const uint32_t *perm, int64_t n, float4 *xyzm,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, c, perm, n,
+                     xyzm);
 }
 
 }  // namespace nb

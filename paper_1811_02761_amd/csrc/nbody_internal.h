@@ -89,7 +89,7 @@ struct Ptrs {
   uint32_t *valsA, *valsB;
   uint32_t *hist;       // sort histograms [radix][blocks] + totals[radix]
   float4 *xyzm;         // sorted x, y, z, m
-  float *x32;           // FP32 image of state positions [3][n] (caller order)
+  float *x32;           // FP32 (x, y, z, m) records of the state (caller order)
   uint32_t *pinfo;      // per sorted particle: s | D << 5 | group start << 15
   uint32_t *leafof;     // per sorted particle: its leaf cell
   uint32_t *blkcnt;     // build block counts [kLevels][blocks] + totals
@@ -133,29 +133,39 @@ struct Ptrs {
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
 Ptrs carve(void *base, const Layout &L);
 
+// FP32 coordinates and masses of particle i at x[i * stride], y[i * stride],
+// ...: stride 1 for separate arrays, 4 for (x, y, z, m) records (x + 1 = y).
+struct Coords {
+  const float *x, *y, *z, *m;
+  int64_t stride;
+};
+
 // ---- launchers (each enqueues on `st`; grid sizes depend only on n) ----
-void launch_bbox(const float *x, const float *y, const float *z, int64_t n,
-                 DevScalars *sc, hipStream_t st);
-void launch_keys(const float *x, const float *y, const float *z, int64_t n,
-                 DevScalars *sc, uint64_t *keys, uint32_t *vals, hipStream_t st);
+void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, hipStream_t st);
+void launch_keys(const Coords &c, int64_t n, DevScalars *sc, uint64_t *keys, uint32_t *vals,
+                 hipStream_t st);
 // returns pointer (A or B) holding the sorted result
 void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
                  uint32_t *valsB, uint32_t *hist, int64_t blocks, hipStream_t st,
                  uint64_t **keys_out, uint32_t **vals_out);
-void launch_gather(const float *x, const float *y, const float *z, const float *m,
-                   const uint32_t *perm, int64_t n, float4 *xyzm, hipStream_t st);
+void launch_gather(const Coords &c, const uint32_t *perm, int64_t n, float4 *xyzm,
+                   hipStream_t st);
 // r > 0: a batch of nsys systems (cells above level r always split, groups
 // at level r or deeper, per-group walk roots in P.groot)
 void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                   int group_merge, int nsys, int r, const Ptrs &P, const Layout &L,
                   hipStream_t st);
 // batch keys into P.keysA / P.valsA from P.sysoff; per-system cubes to P.sysbox
-void launch_sys_keys(const float *x, const float *y, const float *z, int64_t n, int nsys,
-                     int r, const Ptrs &P, hipStream_t st);
+void launch_sys_keys(const Coords &c, int64_t n, int nsys, int r, const Ptrs &P,
+                     hipStream_t st);
 constexpr int kMaxSystems = 4096;
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L,
                     hipStream_t st);
 // asort (may be null): key-ordered a_old with |a|, read instead of a gather
+// asort in a new key order from itself in the old one (inv_old: the old tree's
+// caller index -> position; tmp: n float4 of scratch)
+void launch_asort_remap(const uint32_t *perm, const uint32_t *inv_old, int64_t n,
+                        float4 *asort, float4 *tmp, hipStream_t st);
 void launch_asort_gather(const uint32_t *perm, int64_t n, const float *ax, const float *ay,
                          const float *az, float4 *asort, hipStream_t st);
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
@@ -193,7 +203,7 @@ void launch_kick(int64_t n, float *vx, float *vy, float *vz, const float *ax,
 // Where a drift puts the FP32 image of the new positions: with xyzm set,
 // straight into the key-ordered (x, y, z, m) array of the current tree
 // through inv (caller index -> sorted position), which a refit then uses as
-// is; otherwise into x32[3][n] in caller order (for a rebuild).
+// is; otherwise into the (x, y, z, m) records x32 in caller order (for a rebuild).
 struct SortedOut {
   float4 *xyzm;
   const uint32_t *inv;
@@ -201,13 +211,12 @@ struct SortedOut {
 };
 __device__ __forceinline__ void store_position(int64_t i, int64_t n, float fx, float fy,
                                                float fz, float *x32, const SortedOut &so) {
-  if (so.xyzm) {
-    so.xyzm[so.inv[i]] = make_float4(fx, fy, fz, so.m[i]);
-  } else {
-    x32[i] = fx;
-    x32[n + i] = fy;
-    x32[2 * n + i] = fz;
-  }
+  (void)n;
+  const float4 r = make_float4(fx, fy, fz, so.m[i]);
+  if (so.xyzm)
+    so.xyzm[so.inv[i]] = r;
+  else
+    reinterpret_cast<float4 *>(x32)[i] = r;  // (x, y, z, m) records in caller order
 }
 void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
                   const float *vy, const float *vz, double dt, float *x32, SortedOut so,
