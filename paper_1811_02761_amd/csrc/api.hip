@@ -557,7 +557,7 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   const Ptrs &P = ctx->P;
   const bool mirrored = axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
   launch_group_bounds(axo, ayo, azo, mirrored ? P.asort : nullptr, ctx->perm, ctx->n,
-                      ctx->p.delta_acc, P, ctx->st);
+                      ctx->p.delta_acc, queued, P, ctx->st);
   // outputs over the mirrored array keep the mirror; other writes to it end it
   const bool keep_mirror = mirrored && ax == axo;
   if (!keep_mirror && ax && ax == ctx->asort_src) ctx->asort_src = nullptr;

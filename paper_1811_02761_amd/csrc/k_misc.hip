@@ -106,4 +106,56 @@ void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
                      dt, x32, so);
 }
 
+
+// asort[s] = (a, |a|) of caller index perm[s]; |a| rounded as in the MAC.
+__global__ __launch_bounds__(256) void k_asort_gather(const uint32_t *__restrict__ perm,
+                                                      int64_t n, const float *__restrict__ ax,
+                                                      const float *__restrict__ ay,
+                                                      const float *__restrict__ az,
+                                                      float4 *__restrict__ asort) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = perm[s];
+    const float x = ax[o], y = ay[o], z = az[o];
+    asort[s] = make_float4(x, y, z, sqrt_rn(__builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x))));
+  }
+}
+
+void launch_asort_gather(const uint32_t *perm, int64_t n, const float *ax, const float *ay,
+                         const float *az, float4 *asort, hipStream_t st) {
+  int64_t g = cdiv(n, 256 * 4);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_asort_gather, dim3(g), dim3(256), 0, st, perm, n, ax, ay, az, asort);
+}
+
+// After a rebuild: the mirror in the new key order from the mirror in the
+// old one, tmp[s] = asort[inv_old[perm_new[s]]], then copied back. Particles
+// move little between builds, so the reads of the old mirror are nearly in
+// order (one random 4-byte read of inv_old instead of three of a_old).
+__global__ __launch_bounds__(256) void k_asort_remap(const uint32_t *__restrict__ perm,
+                                                     const uint32_t *__restrict__ inv_old,
+                                                     int64_t n, const float4 *__restrict__ asort,
+                                                     float4 *__restrict__ tmp) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    tmp[s] = asort[inv_old[perm[s]]];
+}
+
+__global__ __launch_bounds__(256) void k_copy_f4(const float4 *__restrict__ src, int64_t n,
+                                                 float4 *__restrict__ dst) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    dst[s] = src[s];
+}
+
+void launch_asort_remap(const uint32_t *perm, const uint32_t *inv_old, int64_t n,
+                        float4 *asort, float4 *tmp, hipStream_t st) {
+  int64_t g = cdiv(n, 256 * 4);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_asort_remap, dim3(g), dim3(256), 0, st, perm, inv_old, n, asort, tmp);
+  hipLaunchKernelGGL(k_copy_f4, dim3(g), dim3(256), 0, st, tmp, n, asort);
+}
+
 }  // namespace nb

@@ -92,6 +92,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t *__restrict
   if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
+// Scatter of one tile: ranks as in the histogram pass (stable: wave, item,
+// lane = input order), then the tile is reordered by digit in LDS and
+// written out from there, so consecutive threads store consecutive
+// addresses of each digit's run instead of 256 scattered runs per wave.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
     int shift, const uint32_t *__restrict__ hist, int64_t nblk,
@@ -99,8 +103,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev) {
   if (n_dev) n = min(n, (int64_t)*n_dev);
   __shared__ uint32_t cnt[kWaves][kSortRadix];
-  __shared__ uint32_t dbase[kSortRadix];
+  __shared__ uint32_t dbase[kSortRadix];   // global start of each digit's run of this tile
+  __shared__ uint32_t lstart[kSortRadix];  // tile-local start of each digit
   __shared__ uint32_t wsum[kWaves];
+  __shared__ uint64_t sk[kSortTile];
+  __shared__ uint32_t sv[kSortTile];
   for (int t = threadIdx.x; t < kWaves * kSortRadix; t += kSortThreads)
     (&cnt[0][0])[t] = 0;
   // digit start = exclusive scan of totals; plus this tile's offset
@@ -111,7 +118,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   }
   __syncthreads();
   const int w = threadIdx.x >> 6;
-  const int64_t base = blockIdx.x * (int64_t)kSortTile + w * kWaveKeys;
+  const int64_t tile0 = blockIdx.x * (int64_t)kSortTile;
+  const int64_t base = tile0 + w * kWaveKeys;
   uint64_t k[kSortItems];
   uint32_t v[kSortItems];
   uint32_t r[kSortItems];
@@ -133,7 +141,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     if (valid && below == 0) cnt[w][d] = c0 + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  // per digit: offsets of the waves within the tile
+  // per digit: offsets of the waves within the tile's digit, then the
+  // digit's start within the tile
+  uint32_t tot;
   {
     const int d = threadIdx.x;
     uint32_t o = 0;
@@ -143,17 +153,29 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
       cnt[q][d] = o;
       o += t;
     }
+    tot = o;
   }
+  const uint32_t ls = block_excl_scan(tot, nullptr, wsum);
+  lstart[threadIdx.x] = ls;
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const int64_t i = base + it * 64 + lane_id();
     if (i < n) {
       const uint32_t d = (uint32_t)(k[it] >> shift) & (kSortRadix - 1);
-      const uint32_t pos = dbase[d] + cnt[w][d] + r[it];
-      kout[pos] = k[it];
-      vout[pos] = v[it];
+      const uint32_t lp = lstart[d] + cnt[w][d] + r[it];
+      sk[lp] = k[it];
+      sv[lp] = v[it];
     }
+  }
+  __syncthreads();
+  const int64_t m = min((int64_t)kSortTile, n - tile0);  // valid items of the tile
+  for (int j = threadIdx.x; j < m; j += kSortThreads) {
+    const uint64_t key = sk[j];
+    const uint32_t d = (uint32_t)(key >> shift) & (kSortRadix - 1);
+    const uint32_t pos = dbase[d] + ((uint32_t)j - lstart[d]);
+    kout[pos] = key;
+    vout[pos] = sv[j];
   }
 }
 

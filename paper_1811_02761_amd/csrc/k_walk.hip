@@ -48,44 +48,6 @@
 
 namespace nb {
 
-__global__ __launch_bounds__(256) void k_group_bounds(
-    const DevScalars *__restrict__ sc, const uint32_t *__restrict__ gbegin,
-    const uint32_t *__restrict__ gcount, const float4 *__restrict__ xyzm,
-    const uint32_t *__restrict__ perm, const float *__restrict__ axo,
-    const float *__restrict__ ayo, const float *__restrict__ azo,
-    const float4 *__restrict__ asort, float delta_acc,
-    float4 *__restrict__ gbox) {
-  const uint32_t ng = sc->ngroup;
-  const uint32_t wstride = gridDim.x * (blockDim.x >> 6);
-  // wave-uniform loop (scalar index): the wave reductions below run with
-  // every lane active, and the results are stored by every lane
-  const uint32_t g0 = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
-                                                     (threadIdx.x >> 6));
-  for (uint32_t g = g0; g < ng; g += wstride) {
-    const uint32_t b = gbegin[g], c = gcount[g];
-    const uint32_t k = lane_id();
-    const bool ok = k < c;
-    const float4 p = xyzm[b + (ok ? k : 0)];
-    float lx = p.x, ly = p.y, lz = p.z;
-    float amin = INFINITY;
-    if (asort && ok) {  // key-ordered copy of a_old with |a| in w
-      amin = asort[b + k].w;
-    } else if (axo && ok) {
-      const uint32_t o = perm[b + k];
-      const float ax = axo[o], ay = ayo[o], az = azo[o];
-      amin = sqrt_rn(__builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
-    }
-    const float hx = wave_max(lx), hy = wave_max(ly), hz = wave_max(lz);
-    lx = wave_min(lx);
-    ly = wave_min(ly);
-    lz = wave_min(lz);
-    amin = axo ? wave_min(amin) : 0.0f;
-    const float dA = delta_acc * amin;
-    gbox[2 * g] = make_float4(lx, ly, lz, dA);
-    gbox[2 * g + 1] = make_float4(hx, hy, hz, amin);
-  }
-}
-
 struct WalkArgs {
   const float4 *nodeA;
   const float4 *nodeB;
@@ -664,66 +626,6 @@ void launch_walk_stat(bool queued, bool record, const Ptrs &P, hipStream_t st) {
                      P.gcount, P.gent, P.gref, record ? 1 : 0);
 }
 
-void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
-                         const float4 *asort, const uint32_t *perm, int64_t n,
-                         float delta_acc, const Ptrs &P, hipStream_t st) {
-  int64_t g = cdiv(n, 4 * 8);  // up to n groups, 4 waves per block
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_group_bounds, dim3(g), dim3(256), 0, st, P.sc, P.gbegin, P.gcount,
-                     P.xyzm, perm, axo, ayo, azo, asort, delta_acc, P.gbox);
-}
-
-// asort[s] = (a, |a|) of caller index perm[s]; |a| rounded as in the MAC.
-__global__ __launch_bounds__(256) void k_asort_gather(const uint32_t *__restrict__ perm,
-                                                      int64_t n, const float *__restrict__ ax,
-                                                      const float *__restrict__ ay,
-                                                      const float *__restrict__ az,
-                                                      float4 *__restrict__ asort) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t o = perm[s];
-    const float x = ax[o], y = ay[o], z = az[o];
-    asort[s] = make_float4(x, y, z, sqrt_rn(__builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x))));
-  }
-}
-
-void launch_asort_gather(const uint32_t *perm, int64_t n, const float *ax, const float *ay,
-                         const float *az, float4 *asort, hipStream_t st) {
-  int64_t g = cdiv(n, 256 * 4);
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_asort_gather, dim3(g), dim3(256), 0, st, perm, n, ax, ay, az, asort);
-}
-
-// After a rebuild: the mirror in the new key order from the mirror in the
-// old one, tmp[s] = asort[inv_old[perm_new[s]]], then copied back. Particles
-// move little between builds, so the reads of the old mirror are nearly in
-// order (one random 4-byte read of inv_old instead of three of a_old).
-__global__ __launch_bounds__(256) void k_asort_remap(const uint32_t *__restrict__ perm,
-                                                     const uint32_t *__restrict__ inv_old,
-                                                     int64_t n, const float4 *__restrict__ asort,
-                                                     float4 *__restrict__ tmp) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x)
-    tmp[s] = asort[inv_old[perm[s]]];
-}
-
-__global__ __launch_bounds__(256) void k_copy_f4(const float4 *__restrict__ src, int64_t n,
-                                                 float4 *__restrict__ dst) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x)
-    dst[s] = src[s];
-}
-
-void launch_asort_remap(const uint32_t *perm, const uint32_t *inv_old, int64_t n,
-                        float4 *asort, float4 *tmp, hipStream_t st) {
-  int64_t g = cdiv(n, 256 * 4);
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_asort_remap, dim3(g), dim3(256), 0, st, perm, inv_old, n, asort, tmp);
-  hipLaunchKernelGGL(k_copy_f4, dim3(g), dim3(256), 0, st, tmp, n, asort);
-}
 
 namespace {
 WalkArgs walk_args(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, float *ay,

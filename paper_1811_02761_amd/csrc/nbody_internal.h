@@ -168,9 +168,10 @@ void launch_asort_remap(const uint32_t *perm, const uint32_t *inv_old, int64_t n
                         float4 *asort, float4 *tmp, hipStream_t st);
 void launch_asort_gather(const uint32_t *perm, int64_t n, const float *ax, const float *ay,
                          const float *az, float4 *asort, hipStream_t st);
+// queued: the groups order[0 .. nqueue) only (block steps); else every group
 void launch_group_bounds(const float *axo, const float *ayo, const float *azo,
                          const float4 *asort,
-                         const uint32_t *perm, int64_t n, float delta_acc,
+                         const uint32_t *perm, int64_t n, float delta_acc, bool queued,
                          const Ptrs &P, hipStream_t st);
 struct WalkCfg {
   float G, eps;
