@@ -187,9 +187,20 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_mark(int64_t n,
                                                           const int8_t *__restrict__ level,
                                                           uint32_t *__restrict__ gflag) {
   const long long tick = sc->tick;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x)
-    if (on_boundary(tick, clamp_level(level[perm[s]]))) gflag[gid[s]] = 1u;
+  // four particles per trip: their index and level loads are issued together
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s0 < n; s0 += 4 * stride) {
+    uint32_t p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[u] = s0 + u * stride < n ? perm[s0 + u * stride] : 0u;
+    int8_t lv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) lv[u] = s0 + u * stride < n ? level[p[u]] : (int8_t)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (s0 + u * stride < n && on_boundary(tick, clamp_level(lv[u])))
+        gflag[gid[s0 + u * stride]] = 1u;
+  }
 }
 
 // Flagged groups per block of kQGroups groups (kQPer consecutive groups per
@@ -267,26 +278,41 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
   const int lo = max(t.level_min, align_level(t1));
   int kmax = 0;
   uint32_t cnt = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int k = clamp_level(level[i]);
-    if (on_boundary(t1, k)) {
-      const float a0 = nax[i], a1 = nay[i], a2 = naz[i];
-      ax[i] = a0;
-      ay[i] = a1;
-      az[i] = a2;
-      const float h = t.hdt[k];
-      const float kx = a0 * h, ky = a1 * h, kz = a2 * h;
-      vx[i] = vx[i] + kx;
-      vy[i] = vy[i] + ky;
-      vz[i] = vz[i] + kz;
-      asort[inv[i]] =
-          make_float4(a0, a1, a2, sqrt_rn(__builtin_fmaf(a2, a2, __builtin_fmaf(a1, a1, a0 * a0))));
-      k = level_of(a0, a1, a2, t, lo);
-      level[i] = (int8_t)k;
-      ++cnt;
+  // kCloseUnroll particles per trip, their levels loaded together (each
+  // thread takes many particles; one load at a time left it waiting on memory)
+  constexpr int kCloseUnroll = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n;
+       i0 += kCloseUnroll * stride) {
+    int8_t lv[kCloseUnroll];
+#pragma unroll
+    for (int u = 0; u < kCloseUnroll; ++u) {
+      const int64_t i = i0 + u * stride;
+      lv[u] = i < n ? level[i] : (int8_t)0;
     }
-    kmax = max(kmax, k);
+#pragma unroll
+    for (int u = 0; u < kCloseUnroll; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i >= n) break;
+      int k = clamp_level(lv[u]);
+      if (on_boundary(t1, k)) {
+        const float a0 = nax[i], a1 = nay[i], a2 = naz[i];
+        ax[i] = a0;
+        ay[i] = a1;
+        az[i] = a2;
+        const float h = t.hdt[k];
+        const float kx = a0 * h, ky = a1 * h, kz = a2 * h;
+        vx[i] = vx[i] + kx;
+        vy[i] = vy[i] + ky;
+        vz[i] = vz[i] + kz;
+        asort[inv[i]] =
+            make_float4(a0, a1, a2, sqrt_rn(__builtin_fmaf(a2, a2, __builtin_fmaf(a1, a1, a0 * a0))));
+        k = level_of(a0, a1, a2, t, lo);
+        level[i] = (int8_t)k;
+        ++cnt;
+      }
+      kmax = max(kmax, k);
+    }
   }
   block_fold(kmax, cnt, sc, true);
 }
@@ -325,8 +351,10 @@ void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx
                            const int8_t *level, double dt_max, const DevScalars *sc,
                            float *x32, SortedOut so, hipStream_t st) {
   BlockCfg c{dt_max, 1.0, 1.0f, 0, kTickBits};
-  int64_t g = cdiv(n, 4 * kBlkThreads);  // a few particles per thread
-  if (g > 16384) g = 16384;
+  // one particle per thread (no per-block reduction here): every thread's
+  // loads are in flight at once
+  int64_t g = cdiv(n, kBlkThreads);
+  if (g > 65536) g = 65536;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_blk_open_drift, dim3((unsigned)g), dim3(kBlkThreads), 0, st, n, x, y,
                      z, vx, vy, vz, ax, ay, az, level, make_tables(c), sc, x32, so);
