@@ -35,22 +35,37 @@ __global__ __launch_bounds__(256) void k_mom_leaf(DevScalars *__restrict__ sc, u
       atomicOr(&sc->status, kStCorrupt);
       continue;
     }
+    // four particles per trip: their loads are issued together; the sums
+    // still run over the particles one by one in key order
+    constexpr uint32_t U = 4;
     double mm = 0.0, xx = 0.0, yy = 0.0, zz = 0.0;
-    for (uint32_t i = b; i < e; ++i) {
-      const float4 p = xyzm[i];
-      const double m = (double)p.w;
-      mm += m;
-      xx += m * (double)p.x;
-      yy += m * (double)p.y;
-      zz += m * (double)p.z;
+    for (uint32_t i0 = b; i0 < e; i0 += U) {
+      float4 q[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) q[u] = xyzm[i0 + u < e ? i0 + u : b];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        if (i0 + u >= e) break;
+        const double m = (double)q[u].w;
+        mm += m;
+        xx += m * (double)q[u].x;
+        yy += m * (double)q[u].y;
+        zz += m * (double)q[u].z;
+      }
     }
     const float4 com = com_from(mm, xx, yy, zz, xyzm[b]);
     float bb = 0.0f;
-    for (uint32_t i = b; i < e; ++i) {
-      const float4 p = xyzm[i];
-      const float dx = p.x - com.x, dy = p.y - com.y, dz = p.z - com.z;
-      const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-      bb = d2 > bb ? d2 : bb;
+    for (uint32_t i0 = b; i0 < e; i0 += U) {
+      float4 q[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) q[u] = xyzm[i0 + u < e ? i0 + u : b];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        if (i0 + u >= e) break;
+        const float dx = q[u].x - com.x, dy = q[u].y - com.y, dz = q[u].z - com.z;
+        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+        bb = d2 > bb ? d2 : bb;
+      }
     }
     mom64[c] = make_double4(mm, xx, yy, zz);
     nodeA[c] = make_float4(com.x, com.y, com.z, bb);
