@@ -260,7 +260,8 @@ __global__ __launch_bounds__(kB) void k_build_d(
     if (l > (int)s_lo[r]) {  // (l-1, ip) is internal: this is its first child
       const uint32_t rp = blkcnt[(int64_t)(l - 1) * nblk + blockIdx.x] + wpre[l - 1][w] +
                           (uint32_t)__popcll(wbal[w][l - 1] & below);
-      cfchild[lvl_off[l - 1] + rp] = (int32_t)idx;
+      const uint32_t pidx = lvl_off[l - 1] + rp;
+      if ((int64_t)pidx < cell_cap) cfchild[pidx] = (int32_t)idx;
     }
     clevel[idx] = l;
     cpbegin[idx] = ip;
