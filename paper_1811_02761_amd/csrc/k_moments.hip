@@ -170,9 +170,12 @@ __global__ __launch_bounds__(256) void k_mom_b2(DevScalars *__restrict__ sc, uin
       const bool act = lvl == l;
       // inactive lanes get keys of their own (above any cell index)
       const uint32_t key = act ? cur : (kNoCell ^ lane);
-      uint32_t v = 0u;
+      uint32_t v = 0u, up = kNoCell;
       if (act) {
+        // the parent index is read with the centre of mass, so that both
+        // loads of a level share one memory round trip
         const float4 c = nodeA[cur];
+        if (l > 0) up = (uint32_t)cparent[cur];
         const float dx = p.x - c.x, dy = p.y - c.y, dz = p.z - c.z;
         v = __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
       }
@@ -221,7 +224,6 @@ __global__ __launch_bounds__(256) void k_mom_b2(DevScalars *__restrict__ sc, uin
         }
       }
       if (act) {
-        const uint32_t up = l > 0 ? (uint32_t)cparent[cur] : kNoCell;
         if (l > 0 && up >= ncell) {
           atomicOr(&sc->status, kStCorrupt);
           lvl = -1;
