@@ -98,7 +98,7 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
                               np.ascontiguousarray(mom.com[:, 2]), mom.b2, mom.q, grp.n,
                               grp.begin, grp.count, np.ascontiguousarray(lo.reshape(-1)),
                               np.ascontiguousarray(hi.reshape(-1)), dA, None, int(sa is None),
-                              1.0, eps, ax, ay, az, ent, gh, nth)
+                              1.0, eps, ax, ay, az, None, ent, gh, nth)
         return (time.perf_counter() - t, int((ent * grp.count).sum()),
                 np.stack([ax, ay, az], 1).astype(np.float32))
 
@@ -116,6 +116,39 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
                    % (n, t_build, grp.n, tw, nth, walk_frac)),
         "interactions_per_s": inter / tw if tw > 0 else None,
     }
+
+
+def accuracy(ctx, nb, torch, st, acc, delta, n_target=1 << 14):
+    """Error of the tree walk's accelerations `acc` (tensors, caller order)
+    at the state's positions, against Eq. 1 summed directly in FP64 (the
+    library's FP64 kernel, whose agreement with the CPU oracle's FP64 sum is a
+    GPU test) for a seeded random subset of targets: e = |da| / |a|, and
+    e~ = |da| / A with A the sum of the terms' magnitudes."""
+    n = st.n
+    x32, y32, z32 = st.x.float(), st.y.float(), st.z.float()
+    rng = np.random.default_rng(17)
+    tgt = np.sort(rng.choice(n, size=min(n_target, n), replace=False)).astype(np.int64)
+    T = torch.as_tensor(tgt, device="cuda")
+    t0 = time.perf_counter()
+    ref, aabs, _ = ctx.direct64(x32, y32, z32, st.m, T)
+    ctx.sync()
+    t_ref = time.perf_counter() - t0
+    got = torch.stack([a[T] for a in acc], 1).double()
+    d = torch.linalg.norm(got - ref, dim=1)
+    e = (d / torch.linalg.norm(ref, dim=1)).cpu().numpy()
+    et = (d / aabs).cpu().numpy()
+    out = {"delta_acc": delta, "targets": int(tgt.size),
+           "reference": "FP64 direct summation of Eq. 1 (nbody_direct64) over all %d "
+                        "particles" % n, "reference_s": t_ref}
+    for q, name in ((50, "e_p50"), (90, "e_p90"), (99, "e_p99"), (99.9, "e_p99_9")):
+        out[name] = float(np.percentile(e, q))
+    out["e_max"] = float(e.max())
+    out["etilde_max"] = float(et.max())
+    log("accuracy at delta_acc %g: e p50 %.3g p90 %.3g p99 %.3g p99.9 %.3g max %.3g, e~ max %.3g "
+        "(%d targets, reference %.2f s)" % (delta, out["e_p50"], out["e_p90"], out["e_p99"],
+                                             out["e_p99_9"], out["e_max"], out["etilde_max"],
+                                             out["targets"], t_ref))
+    return out
 
 
 def train_model(ctx, nb, torch, feat, target, steps, hidden=32):
@@ -335,6 +368,7 @@ def main():
     s2 = ctx.stats()
     full_ms = s2["walk_ms_sum"] / max(s2["walk_calls"], 1)
     log("all-active walk %.3f ms, %.3g interactions" % (full_ms, s2["interactions_sum"]))
+    acc_rep = accuracy(ctx, nb, torch, st, full, args.delta)
     del full
 
     cpu = None
@@ -384,6 +418,7 @@ def main():
         "all_active_walk_ms": full_ms,
         "all_active_interactions": s2["interactions_sum"],
         "all_active_interactions_per_s": s2["interactions_sum"] / (full_ms * 1e-3),
+        "accuracy": acc_rep,
         "plain_vs_learned": learned,
         "build_ms": s1["build_ms_sum"] / max(s1["build_calls"], 1),
         "rebuilds_in_timed_steps": rebuilds,

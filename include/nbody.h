@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define NBODY_ABI_VERSION 2
+#define NBODY_ABI_VERSION 3
 
 typedef int32_t nbody_status;
 enum {
@@ -96,6 +96,12 @@ enum {
  *                adds the blocks b with b mod k == j and a second kernel
  *                adds the sums. Results are bit-identical for every value.
  *                The compensated sum (compensated = 1) is never split.
+ *  calcnode_sync: how the moment pass ("calcNode", Sec. 2.2) waits for each
+ *                tree level's children before their parents (App. A):
+ *                0 = library default (1); 1 = one kernel launch per level;
+ *                2 = one persistent launch whose workgroups meet at a
+ *                lock-free grid barrier (Xiao and Feng 2010) between levels.
+ *                Results are bit-identical for every value.
  */
 typedef struct {
   float G;
@@ -111,6 +117,7 @@ typedef struct {
   int32_t checks;
   int32_t group_merge;
   int32_t walk_split;
+  int32_t calcnode_sync;
 } nbody_params;
 
 typedef struct nbody_ctx nbody_ctx; /* opaque; one per HIP stream */
@@ -132,7 +139,15 @@ typedef struct nbody_ctx nbody_ctx; /* opaque; one per HIP stream */
  * level is the smallest k >= level_min, allowed by the current time, with
  * dt 2^-k <= sqrt(2 eta eps / |a|) (eta > 0), at most level_max (<= 10).
  * tick: time since the start in units of dt * 2^-10 (host; must be >= 0;
- * advanced with t by nbody_step). */
+ * advanced with t by nbody_step).
+ *
+ * integrator: 0 kick-drift-kick leapfrog; 1 the second-order Runge-Kutta
+ * method in predict / correct form named in Sec. 2.2 (Heun's method, global
+ * steps only: level must be NULL): x_p = x + v dt (FP64), v_p = v + a dt
+ * (FP32); a_p = walk at x_p (a_old = a); x += (v + v_p) dt/2 (FP64),
+ * v += (a + a_p) dt/2 (FP32); a = walk at the new x (a_old = a_p). Two force
+ * evaluations per step; the tree is rebuilt (or refitted) for the first and
+ * refitted for the second. */
 typedef struct {
   int64_t n;
   double *x, *y, *z;
@@ -147,6 +162,7 @@ typedef struct {
   double eta;
   int32_t level_min, level_max;
   int64_t tick;
+  int32_t integrator;
 } nbody_state;
 
 /* Statistics (host struct filled by nbody_get_stats, BLOCKING).
@@ -203,7 +219,9 @@ enum {
   NBODY_X_TARGET = 21,   /* float32[ngroup] log2 interactions (groups of the last walk) */
   NBODY_X_PRED = 22,     /* float32[ngroup] the model's prediction (order 2) */
   NBODY_X_SYSBOX = 23,   /* float64[n_sys][4] batch: each system's root cube lo, L */
-  NBODY_X_GROOT = 24     /* uint32[ngroup] batch: each group's walk root cell */
+  NBODY_X_GROOT = 24,    /* uint32[ngroup] batch: each group's walk root cell */
+  NBODY_X_APRED = 25     /* float32[3][n] integrator 1: a_p of the last step
+                            (x, y, z rows, caller order) */
 };
 
 int32_t nbody_abi_version(void);
@@ -254,6 +272,17 @@ nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *ax_old,
                             const float *ay_old, const float *az_old,
                             float *ax, float *ay, float *az);
 
+/* nbody_calc_acc that also writes the potential of every particle (caller
+ * order, FP32) from the same interaction lists: phi_i = -G sum over the
+ * entries j of m_j / (r_ij^2 + eps^2)^(1/2), the particle's own entry left
+ * out (the softened potential of Eq. 1's force; W = sum_i m_i phi_i / 2 is
+ * the potential energy of long-run energy checks). The walk is never split
+ * across wavefronts; accelerations are bit-identical to nbody_calc_acc.
+ * Needs a tree (ENOTREE); phi must not be NULL. */
+nbody_status nbody_calc_acc_pot(nbody_ctx *ctx, const float *ax_old,
+                                const float *ay_old, const float *az_old,
+                                float *ax, float *ay, float *az, float *phi);
+
 /* Advance the state by n_steps kick-drift-kick leapfrog steps of length
  * st->dt: v += a dt/2 (FP32); x += v dt (FP64); tree rebuild or refit from
  * the FP32 image of x; a = walk(a_old = previous a); v += a dt/2.
@@ -282,6 +311,19 @@ nbody_status nbody_step_graph(nbody_ctx *ctx, nbody_state *st, int32_t n_steps);
 nbody_status nbody_direct(nbody_ctx *ctx, int64_t n, const float *x,
                           const float *y, const float *z, const float *m,
                           float *ax, float *ay, float *az);
+
+/* Eq. 1 by direct summation in FP64 for the n_target particles targets[k]
+ * (device int64, caller indices; an index outside [0, n) gives zeros): the
+ * accuracy reference of the tree walk (no tree needed). x, y, z, m are FP32
+ * (promoted to FP64); pairs j == i are skipped by index. Outputs per target,
+ * device FP64: acceleration (ax, ay, az), and when not NULL the scale
+ * aabs = sum_j G m_j |r_ij| / (r_ij^2 + eps^2)^(3/2) (the conditioning of the
+ * sum, used to normalise errors) and the potential
+ * phi = -sum_{j != i} G m_j / (r_ij^2 + eps^2)^(1/2). */
+nbody_status nbody_direct64(nbody_ctx *ctx, int64_t n, const float *x,
+                            const float *y, const float *z, const float *m,
+                            int64_t n_target, const int64_t *targets, double *ax,
+                            double *ay, double *az, double *aabs, double *phi);
 
 /* Copy an internal array (see NBODY_X_*) to caller device memory `dst`
  * holding at least `capacity` elements. Returns ENOMEM if too small.

@@ -77,7 +77,7 @@ def lib():
         L.orc_walk.argtypes = ([C.c_int64, f32p, f32p, f32p, f32p, C.c_int64, i64p,
                                 i64p, i64p, i32p, f32p, f32p, f32p, f32p, f32p, f32p,
                                 C.c_int64, i64p, i64p, f32p, f32p, f32p, C.c_void_p, C.c_int,
-                                C.c_double, C.c_double, f64p, f64p, f64p, i64p,
+                                C.c_double, C.c_double, f64p, f64p, f64p, C.c_void_p, i64p,
                                 u64p, C.c_int])
         L.orc_mix64.argtypes = [C.c_uint64]
         L.orc_mix64.restype = C.c_uint64
@@ -300,6 +300,7 @@ class TreeResult:
     acc: np.ndarray  # FP64, caller order
     gentries: np.ndarray
     ghash: np.ndarray
+    phi: np.ndarray  # FP64, caller order: potential over the same lists
 
     def interactions(self) -> int:
         return int((self.gentries * self.grp.count).sum())
@@ -341,7 +342,7 @@ def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 *
         groot = roots[np.searchsorted(off, grp.begin, side="right") - 1].astype(np.int64)
     sa = None if a_old is None else np.asarray(a_old, np.float32)[perm]
     glo, ghi, gamin, gdA = group_bounds(grp, sx, sy, sz, sa, delta_acc)
-    ax, ay, az = (np.empty(n) for _ in range(3))
+    ax, ay, az, ph = (np.empty(n) for _ in range(4))
     gent = np.empty(grp.n, np.int64)
     gh = np.empty(grp.n, np.uint64)
     lib().orc_walk(n, sx, sy, sz, sm, cells.n, cells.pbegin, cells.pcount,
@@ -349,12 +350,14 @@ def tree_forces(x, y, z, m, *, a_old=None, G=1.0, eps=2.0 ** -7, delta_acc=2.0 *
                    _c(mom.com[:, 1], np.float32), _c(mom.com[:, 2], np.float32), mom.b2,
                    mom.q, grp.n, grp.begin, grp.count, _c(glo.reshape(-1), np.float32),
                    _c(ghi.reshape(-1), np.float32), gdA, _ptr(groot), int(a_old is None), G,
-                   eps, ax, ay, az, gent, gh, nthreads or nthreads_default())
+                   eps, ax, ay, az, _ptr(ph), gent, gh, nthreads or nthreads_default())
     acc_s = np.stack([ax, ay, az], axis=1)
     acc = np.empty_like(acc_s)
     acc[perm] = acc_s
+    phi = np.empty(n)
+    phi[perm] = ph
     return TreeResult(box, k, perm, ks, cells, mom, grp, glo, ghi, gamin, gdA, acc_s, acc,
-                      gent, gh)
+                      gent, gh, phi)
 
 
 # ------------------------------------------------------------ leapfrog
@@ -371,6 +374,39 @@ def kdk_step(x64, v32, a32, m32, dt, force, *, nkick=None):
     a = np.asarray(force(x.astype(np.float32)), dtype=np.float32)
     v = (v + (a * hdt).astype(np.float32)).astype(np.float32)
     return x, v, a
+
+
+def rk2_step(x64, v32, a32, dt, force, *, a_pred_in=None):
+    """One step of the second-order Runge-Kutta method in its predict /
+    correct form (Heun's method, the explicit trapezoidal rule), the orbit
+    integration that Sec. 2.2 and Table 2 name ("predict", "correct"), for
+    y = (x, v) with y' = (v, a(x)):
+
+      predict:  x_p = x + v dt (FP64),  v_p = v + a dt (FP32);
+      evaluate: a_p = force(x_p as FP32, a_old = a);
+      correct:  x' = x + (v + v_p) dt/2 (FP64, the sum in FP64),
+                v' = v + (a + a_p) dt/2 (FP32, one rounding per operation);
+      and the slope of the next step, a' = force(x' as FP32, a_old = a_p).
+
+    ``force(p32, a_old)`` returns FP32 (n, 3) accelerations. ``a_pred_in``
+    replaces the computed a_p in the correction and as a_old of the second
+    evaluation (a test can feed another implementation's a_p, so that both
+    take the same decisions from then on). Returns (x', v', a', a_p)."""
+    dt32 = np.float32(dt)
+    hdt32 = np.float32(0.5 * dt)
+    hdt = np.float64(0.5 * dt)
+    v = np.asarray(v32, np.float32)
+    a = np.asarray(a32, np.float32)
+    x = np.asarray(x64, np.float64)
+    v_p = (v + (a * dt32).astype(np.float32)).astype(np.float32)
+    x_p = x + v.astype(np.float64) * np.float64(dt)
+    a_p = np.asarray(force(x_p.astype(np.float32), a), np.float32)
+    if a_pred_in is not None:
+        a_p = np.asarray(a_pred_in, np.float32)
+    x_n = x + (v.astype(np.float64) + v_p.astype(np.float64)) * hdt
+    v_n = (v + ((a + a_p).astype(np.float32) * hdt32).astype(np.float32)).astype(np.float32)
+    a_n = np.asarray(force(x_n.astype(np.float32), a_p), np.float32)
+    return x_n, v_n, a_n, a_p
 
 
 # ------------------------------------------------------------ block steps

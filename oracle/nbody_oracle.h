@@ -121,7 +121,9 @@ int orc_mac(const float lo[3], const float hi[3], float dA, int bootstrap,
 /* Group-wise walk: for each group, collect the accepted cells (as
  * pseudo-particles com, m32) and the particles of opened leaves, then sum
  * Eq. 1 over them in FP64 for every member. Outputs (sorted order) FP64
- * accelerations; per group the number of entries and an order-independent
+ * accelerations; when phi is not NULL the potential over the same entries,
+ * phi_i = -sum G m_j / sqrt(r_ij^2 + eps^2) with the particle's own entry
+ * left out; per group the number of entries and an order-independent
  * hash of the entry identities (cell c -> c, leaf particle s -> 2^40 + s).
  * groot (may be NULL: the root, cell 0) gives each group's starting cell. */
 void orc_walk(int64_t n, const float *sx, const float *sy, const float *sz,
@@ -132,8 +134,8 @@ void orc_walk(int64_t n, const float *sx, const float *sy, const float *sz,
               const float *q, int64_t ngroup, const int64_t *gbegin,
               const int64_t *gcount, const float *glo3, const float *ghi3,
               const float *gdA, const int64_t *groot, int bootstrap, double G,
-              double eps, double *ax, double *ay, double *az, int64_t *gentries,
-              uint64_t *ghash, int nthreads);
+              double eps, double *ax, double *ay, double *az, double *phi,
+              int64_t *gentries, uint64_t *ghash, int nthreads);
 
 /* Entry-identity mixer used by the per-group hash (splitmix64 finaliser). */
 uint64_t orc_mix64(uint64_t v);

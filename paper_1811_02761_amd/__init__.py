@@ -27,7 +27,7 @@ class X:
     KEYS, PERM, LEVEL, PBEGIN, PCOUNT, FCHILD, NCHILD, PARENT = 1, 2, 3, 4, 5, 6, 7, 8
     NODE, MQ, MOM64, GBEGIN, GCOUNT, GBOX, GENTRIES, GHASH, XYZM, BOX, QUEUE = (
         9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19)
-    FEAT, TARGET, PRED, SYSBOX, GROOT = 20, 21, 22, 23, 24
+    FEAT, TARGET, PRED, SYSBOX, GROOT, APRED = 20, 21, 22, 23, 24, 25
     # (dtype, unit: 'n' | 'cell' | 'group' | 'fixed', elements per unit)
     SPEC = {
         1: ("uint64", "n", 1), 2: ("int32", "n", 1), 3: ("int32", "cell", 1),
@@ -38,6 +38,7 @@ class X:
         16: ("uint64", "group", 1), 17: ("float32", "n", 4), 18: ("float64", "fixed", 4),
         19: ("int32", "queued", 1), 20: ("float32", "group", 4), 21: ("float32", "group", 1),
         22: ("float32", "group", 1), 23: ("float64", "sys", 4), 24: ("int32", "group", 1),
+        25: ("float32", "n", 3),
     }
 
 
@@ -54,7 +55,8 @@ class _Params(C.Structure):
                 ("compensated", C.c_int32), ("order", C.c_int32),
                 ("frontier_cap", C.c_int32), ("list_tile", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("checks", C.c_int32),
-                ("group_merge", C.c_int32), ("walk_split", C.c_int32)]
+                ("group_merge", C.c_int32), ("walk_split", C.c_int32),
+                ("calcnode_sync", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -64,7 +66,7 @@ class _State(C.Structure):
                 ("az", C.c_void_p), ("t", C.c_double), ("dt", C.c_double),
                 ("have_acc", C.c_int32), ("rebuild_interval", C.c_int32),
                 ("level", C.c_void_p), ("eta", C.c_double), ("level_min", C.c_int32),
-                ("level_max", C.c_int32), ("tick", C.c_int64)]
+                ("level_max", C.c_int32), ("tick", C.c_int64), ("integrator", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -86,11 +88,11 @@ HEADER_FUNCTIONS = [
     "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide", "nbody_timing",
     "nbody_mlp_nparams", "nbody_mlp_forward", "nbody_mlp_grad", "nbody_mlp_adam",
     "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order", "nbody_set_systems",
-    "nbody_step_graph",
+    "nbody_step_graph", "nbody_direct64", "nbody_calc_acc_pot",
 ]
 
 _lib = None
-ABI_VERSION = 2  # NBODY_ABI_VERSION of include/nbody.h
+ABI_VERSION = 3  # NBODY_ABI_VERSION of include/nbody.h
 
 
 def lib():
@@ -136,6 +138,8 @@ def lib():
         L.nbody_set_order.argtypes = [vp, i32]
         L.nbody_set_systems.argtypes = [vp, i32, vp]
         L.nbody_step_graph.argtypes = [vp, C.POINTER(_State), i32]
+        L.nbody_calc_acc_pot.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.nbody_direct64.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         for f in HEADER_FUNCTIONS:
             fn = getattr(L, f)
             if fn.restype is C.c_int or fn.restype is None and f != "nbody_destroy":
@@ -186,6 +190,7 @@ class Params:
     checks: int = 0
     group_merge: int = 1
     walk_split: int = 0
+    calcnode_sync: int = 0
 
     def c(self) -> _Params:
         return _Params(*[getattr(self, f.name) for f in fields(self)])
@@ -281,6 +286,19 @@ class Context:
                "nbody_calc_acc")
         return out
 
+    def calc_acc_pot(self, a_old=None):
+        """calc_acc that also returns the potential: ((ax, ay, az), phi)."""
+        import torch
+        n = self.n
+        out = tuple(torch.empty(n, dtype=torch.float32, device=self.device) for _ in range(4))
+        ao = (None, None, None) if a_old is None else a_old
+        if a_old is not None:
+            for t, nm in zip(ao, ("ax_old", "ay_old", "az_old")):
+                _need(t, torch.float32, n, nm)
+        _check(lib().nbody_calc_acc_pot(self._h, *[_ptr(t) for t in ao],
+                                        *[_ptr(t) for t in out]), "nbody_calc_acc_pot")
+        return out[:3], out[3]
+
     def direct(self, x, y, z, m, out=None):
         import torch
         n = x.numel()
@@ -291,6 +309,21 @@ class Context:
         _check(lib().nbody_direct(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(m),
                                   *[_ptr(t) for t in out]), "nbody_direct")
         return out
+
+    def direct64(self, x, y, z, m, targets):
+        """FP64 direct sum for targets (int64 CUDA tensor of caller indices):
+        returns (acc (nt, 3), aabs (nt,), phi (nt,)) float64 CUDA tensors."""
+        import torch
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
+            _need(t, torch.float32, n, nm)
+        nt = targets.numel()
+        _need(targets, torch.int64, nt, "targets")
+        out = torch.empty((5, max(nt, 1)), dtype=torch.float64, device=self.device)
+        _check(lib().nbody_direct64(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(m), nt,
+                                    _ptr(targets), *[_ptr(out[k]) for k in range(5)]),
+               "nbody_direct64")
+        return out[:3, :nt].T, out[3, :nt], out[4, :nt]
 
     def step(self, state: "State", n_steps: int = 1):
         cs = state._c()
@@ -410,6 +443,7 @@ class State:
     level_min: int = 0
     level_max: int = 10
     tick: int = 0
+    integrator: int = 0  # 0 kick-drift-kick leapfrog, 1 second-order Runge-Kutta
     _keep: list = field(default_factory=list, repr=False)
 
     @classmethod
@@ -445,4 +479,4 @@ class State:
         return _State(n, *(t.data_ptr() for t in (self.x, self.y, self.z, self.vx, self.vy,
                                                    self.vz, self.m, self.ax, self.ay, self.az)),
                       self.t, self.dt, self.have_acc, self.rebuild_interval, lev, self.eta,
-                      self.level_min, self.level_max, self.tick)
+                      self.level_min, self.level_max, self.tick, self.integrator)

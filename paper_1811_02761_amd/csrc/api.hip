@@ -102,7 +102,12 @@ nbody_status check_params(const nbody_params *p) {
   if (p->group_merge != 0 && p->group_merge != 1) return NBODY_EINVAL;
   if (p->walk_split != 0 && p->walk_split != 1 && p->walk_split != 2 && p->walk_split != 4)
     return NBODY_EINVAL;
+  if (p->calcnode_sync < 0 || p->calcnode_sync > 2) return NBODY_EINVAL;
   return NBODY_OK;
+}
+
+int eff_calcnode(const nbody_params &p) {
+  return p.calcnode_sync ? p.calcnode_sync : kCalcNodeLevels;
 }
 
 int eff_waves(const nbody_params &p) {
@@ -146,6 +151,7 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.sort_blocks = cdiv(n, kSortTile);
   L.build_blocks = cdiv(n, kBuildThreads);
   L.walk_waves = (int64_t)num_cu * eff_waves(p);
+  L.num_cu = num_cu;
   L.frontier_cap = eff_frontier(p, L.cell_cap);
   // the walk's stack holds at most 512 cells per tree level (22 levels)
   L.frontier2_cap = 16384;
@@ -168,6 +174,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_pinfo = take(4 * N);
   L.off_leafof = take(4 * N);
   L.off_blkcnt = take(4 * ((size_t)(kLevels + 1) * L.build_blocks + kLevels + 1));
+  L.off_lvlblk = take(4 * ((size_t)(kLevels + 1) * L.build_blocks + kLevels + 1));
+  L.off_bar = take(8 * 2 * (size_t)kBarSlots);
   L.off_clevel = take(4 * C);
   L.off_cpbegin = take(4 * C);
   L.off_cpcount = take(4 * C);
@@ -240,6 +248,8 @@ Ptrs carve(void *base, const Layout &L) {
   P.pinfo = reinterpret_cast<uint32_t *>(b + L.off_pinfo);
   P.leafof = reinterpret_cast<uint32_t *>(b + L.off_leafof);
   P.blkcnt = reinterpret_cast<uint32_t *>(b + L.off_blkcnt);
+  P.lvlblk = reinterpret_cast<uint32_t *>(b + L.off_lvlblk);
+  P.bar = reinterpret_cast<unsigned long long *>(b + L.off_bar);
   P.clevel = reinterpret_cast<int32_t *>(b + L.off_clevel);
   P.cpbegin = reinterpret_cast<uint32_t *>(b + L.off_cpbegin);
   P.cpcount = reinterpret_cast<uint32_t *>(b + L.off_cpcount);
@@ -357,6 +367,7 @@ __global__ void k_scalars_init(DevScalars *sc) {
   sc->kmax_next = 0;
   sc->nqueue = 0;
   sc->nactive = 0;
+  sc->bar_epoch = 0;
 }
 
 // FP32 image of FP64 positions with the masses, (x, y, z, m) records in
@@ -507,7 +518,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   launch_invert(pm, n, P.inv, ctx->st);
   launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, ctx->nsys,
                ctx->sys_r, P, ctx->L, ctx->st);
-  launch_moments(n, ctx->p.G, P, ctx->L, ctx->st);
+  launch_moments(n, ctx->p.G, P, ctx->L, eff_calcnode(ctx->p), ctx->st);
   span_end(ctx, sp);
   span_done(ctx, sp);
   launch_fill_u32(P.gref, 0u, n, ctx->st);
@@ -522,13 +533,13 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
 
 nbody_status do_refit(nbody_ctx *ctx, const Coords &c) {
   launch_gather(c, ctx->perm, ctx->n, ctx->P.xyzm, ctx->st);
-  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, ctx->st);
+  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, eff_calcnode(ctx->p), ctx->st);
   return hip_status();
 }
 
 // Refit after a drift that wrote the key-ordered positions itself.
 nbody_status do_refit_sorted(nbody_ctx *ctx) {
-  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, ctx->st);
+  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, eff_calcnode(ctx->p), ctx->st);
   return hip_status();
 }
 
@@ -552,7 +563,8 @@ SortedOut drift_out(const nbody_ctx *ctx, const nbody_state *st, bool rebuild) {
 // cost-ordered queue the groups are first sorted by predicted cost, and after
 // the walk each member keeps its list length and each group its target.
 nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const float *azo,
-                     float *ax, float *ay, float *az, bool queued = false) {
+                     float *ax, float *ay, float *az, bool queued = false,
+                     float *phi = nullptr) {
   const bool boot = axo == nullptr;
   const Ptrs &P = ctx->P;
   const bool mirrored = axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
@@ -571,6 +583,7 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   launch_fill_u32(&P.sc->queue_head, 0u, 1, ctx->st);
   WalkCfg wc = walk_cfg(ctx, boot, use_queue);
   wc.asort_out = keep_mirror;
+  wc.phi = phi;
   const int sp = span_begin(ctx, 1);
   launch_walk(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
   span_end(ctx, sp);
@@ -737,6 +750,8 @@ nbody_status nbody_bind_workspace(nbody_ctx *ctx, void *dev_ptr, size_t bytes,
   hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
   launch_fill_u32(ctx->P.plast, 0u, n_max, ctx->st);
   launch_fill_u32(ctx->P.gflag, 0u, n_max, ctx->st);  // cleared again by each queue build
+  // grid barrier flags start below every goal
+  launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->P.bar), 0u, 4 * (int64_t)kBarSlots, ctx->st);
   return hip_status();
 }
 
@@ -767,6 +782,18 @@ nbody_status nbody_calc_acc(nbody_ctx *ctx, const float *axo, const float *ayo,
   const int nnull = (axo == nullptr) + (ayo == nullptr) + (azo == nullptr);
   if (nnull != 0 && nnull != 3) return NBODY_EINVAL;
   return do_calc(ctx, axo, ayo, azo, ax, ay, az);
+}
+
+nbody_status nbody_calc_acc_pot(nbody_ctx *ctx, const float *axo, const float *ayo,
+                                const float *azo, float *ax, float *ay, float *az,
+                                float *phi) {
+  nbody_status s = pre(ctx);
+  if (s != NBODY_OK) return s;
+  if (!ctx->have_tree) return NBODY_ENOTREE;
+  if (!ax || !ay || !az || !phi) return NBODY_EINVAL;
+  const int nnull = (axo == nullptr) + (ayo == nullptr) + (azo == nullptr);
+  if (nnull != 0 && nnull != 3) return NBODY_EINVAL;
+  return do_calc(ctx, axo, ayo, azo, ax, ay, az, false, phi);
 }
 
 namespace {
@@ -829,6 +856,43 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   return NBODY_OK;
 }
 
+// Global steps of the second-order Runge-Kutta method (Heun, predict /
+// correct): the tree is rebuilt (or refitted) at the predicted positions and
+// refitted at the corrected ones; a_p of the predicted positions lives in
+// atmp between the two walks.
+nbody_status step_rk2(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
+  nbody_status s;
+  const int64_t n = st->n;
+  float *x32 = ctx->P.x32;
+  float *px = ctx->P.atmp, *py = px + n, *pz = px + 2 * n;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    bool rebuild = st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
+                                            : rebuild_due(ctx, 64);
+    if (ctx->n != n) rebuild = true;
+    launch_rk2_predict(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->dt, x32,
+                       drift_out(ctx, st, rebuild), ctx->st);
+    if (rebuild) {
+      if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
+      ctx->rebuilds++;
+      ctx->since_rebuild = 0;
+    } else {
+      if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
+    }
+    ensure_asort(ctx, st);
+    if ((s = do_calc(ctx, st->ax, st->ay, st->az, px, py, pz)) != NBODY_OK) return s;
+    launch_rk2_correct(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
+                       px, py, pz, st->dt, x32, drift_out(ctx, st, false), ctx->st);
+    if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
+    // a_old of this walk is a_p: the mirror of the state's a is stale after it
+    if ((s = do_calc(ctx, px, py, pz, st->ax, st->ay, st->az)) != NBODY_OK) return s;
+    ctx->since_rebuild++;
+    ctx->steps++;
+    st->t += st->dt;
+    if ((s = hip_status()) != NBODY_OK) return s;
+  }
+  return NBODY_OK;
+}
+
 // Global kick-drift-kick steps (no individual levels).
 nbody_status step_global(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   nbody_status s;
@@ -847,6 +911,7 @@ nbody_status step_global(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     ctx->since_rebuild = 0;
   }
   const float hdt = (float)(0.5 * st->dt);
+  if (st->integrator == kIntRK2) return step_rk2(ctx, st, n_steps);
   for (int32_t k = 0; k < n_steps; ++k) {
     bool rebuild = st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
                                             : rebuild_due(ctx, 64);
@@ -886,6 +951,8 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       (!(st->eta > 0.0) || !isfinite(st->eta) || st->level_min < 0 ||
        st->level_min > st->level_max || st->level_max > kTickBits || st->tick < 0))
     return NBODY_EINVAL;
+  if (st->integrator != kIntKDK && st->integrator != kIntRK2) return NBODY_EINVAL;
+  if (st->integrator == kIntRK2 && st->level) return NBODY_EINVAL;  // global steps only
   if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
   ctx->asort_src = nullptr;  // the caller may have changed the state since the last call
   s = st->level ? step_block(ctx, st, n_steps) : step_global(ctx, st, n_steps);
@@ -899,6 +966,20 @@ nbody_status nbody_direct(nbody_ctx *ctx, int64_t n, const float *x, const float
   if (ctx->sticky != NBODY_OK) return ctx->sticky;
   if (n < 1 || !x || !y || !z || !m || !ax || !ay || !az) return NBODY_EINVAL;
   launch_direct(n, x, y, z, m, ctx->p.G, ctx->p.eps, ax, ay, az, ctx->st);
+  return hip_status();
+}
+
+nbody_status nbody_direct64(nbody_ctx *ctx, int64_t n, const float *x, const float *y,
+                            const float *z, const float *m, int64_t n_target,
+                            const int64_t *targets, double *ax, double *ay, double *az,
+                            double *aabs, double *phi) {
+  if (!ctx) return NBODY_EINVAL;
+  if (ctx->sticky != NBODY_OK) return ctx->sticky;
+  if (n < 1 || n_target < 0 || !x || !y || !z || !m || !targets || !ax || !ay || !az)
+    return NBODY_EINVAL;
+  if (n_target == 0) return NBODY_OK;
+  launch_direct64(n, x, y, z, m, n_target, targets, (double)ctx->p.G, (double)ctx->p.eps, ax,
+                  ay, az, aabs, phi, ctx->st);
   return hip_status();
 }
 
@@ -1005,6 +1086,7 @@ nbody_status nbody_export(nbody_ctx *ctx, int32_t what, void *dst, int64_t capac
       src = P.groot;
       count = ctx->sys_r > 0 ? ng : 0;
       break;
+    case NBODY_X_APRED: src = P.atmp; count = 3 * n; break;
     default: return NBODY_EINVAL;
   }
   if (capacity < count) return NBODY_ENOMEM;
@@ -1214,7 +1296,8 @@ extern "C" {
 nbody_status nbody_step_graph(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   nbody_status s = pre(ctx);
   if (s != NBODY_OK) return s;
-  if (!st || st->level || st->rebuild_interval < 1) return NBODY_EINVAL;
+  if (!st || st->level || st->rebuild_interval < 1 || st->integrator != kIntKDK)
+    return NBODY_EINVAL;
   if (!ctx->cap_st) {
     if (hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->cap_ev[0], hipEventDisableTiming) != hipSuccess ||

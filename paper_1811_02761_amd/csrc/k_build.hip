@@ -538,13 +538,14 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                   int group_merge, int nsys, int r, const Ptrs &P, const Layout &L,
                   hipStream_t st) {
   const uint32_t nblk = (uint32_t)cdiv(n, kB);
-  // block rows [kLevels][nblk], then kLevels totals
-  uint32_t *totals = P.blkcnt + (int64_t)kLevels * nblk;
+  // block rows [kLevels][nblk], then kLevels totals; the scanned rows stay
+  // for the tree's life (calcNode derives ancestor indices from them)
+  uint32_t *totals = P.lvlblk + (int64_t)kLevels * nblk;
   hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, leaf_max, r,
-                     P.pinfo, P.blkcnt, nblk);
-  hipLaunchKernelGGL(k_scan_rows, dim3(kLevels), dim3(256), 0, st, P.blkcnt, nblk, totals);
+                     P.pinfo, P.lvlblk, nblk);
+  hipLaunchKernelGGL(k_scan_rows, dim3(kLevels), dim3(256), 0, st, P.lvlblk, nblk, totals);
   hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
-  hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, P.pinfo, (uint32_t)n, P.blkcnt,
+  hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, P.pinfo, (uint32_t)n, P.lvlblk,
                      nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount, P.cfchild,
                      P.cnchild, P.nodeB, P.leafof);
   hipLaunchKernelGGL(k_build_long, dim3(1024), dim3(256), 0, st, keys, (uint32_t)n, P.pinfo,
@@ -554,7 +555,7 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   if (ge > 4096) ge = 4096;
   hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.cfchild, P.cnchild,
                      P.cparent, P.nodeB);
-  // groups (the block rows are free again: reuse them for the group scan)
+  // groups (scanned in the block-count scratch)
   uint32_t *gblk = P.blkcnt, *gtot = P.blkcnt + nblk;
   hipLaunchKernelGGL(k_group_mark, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cpbegin,
                      P.cpcount, P.cfchild, P.cnchild, (uint32_t)group_max, group_merge, r,

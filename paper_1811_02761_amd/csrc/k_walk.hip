@@ -67,6 +67,7 @@ struct WalkArgs {
   unsigned long long *ghash;
   DevScalars *sc;
   float *ax, *ay, *az;
+  float *phi;              // potential output (the potential variant only)
   float *split;            // partial sums of split groups, per queue position
   float G, eps2;
   uint32_t n;
@@ -92,39 +93,45 @@ __device__ __forceinline__ uint64_t mix64(uint64_t v) {
   return v ^ (v >> 31);
 }
 
-template <bool kComp>
+// One lane's running sums of the acceleration components and, in the
+// potential variant (kPot), of the potential: sum of -m_j / r_j.
+template <bool kComp, bool kPot>
 struct Acc3 {
-  float x = 0.f, y = 0.f, z = 0.f;
-  __device__ __forceinline__ void add(float dx, float dy, float dz, float f) {
+  float x = 0.f, y = 0.f, z = 0.f, w = 0.f;
+  __device__ __forceinline__ void add(float dx, float dy, float dz, float f, float mr) {
     x = __builtin_fmaf(f, dx, x);
     y = __builtin_fmaf(f, dy, y);
     z = __builtin_fmaf(f, dz, z);
+    if constexpr (kPot) w = w - mr;
   }
-  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz, float &ow) const {
     ox = x;
     oy = y;
     oz = z;
+    ow = w;
   }
 };
 
 // Neumaier's compensated summation (Neumaier 1974) per component.
-template <>
-struct Acc3<true> {
-  float x = 0.f, y = 0.f, z = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+template <bool kPot>
+struct Acc3<true, kPot> {
+  float x = 0.f, y = 0.f, z = 0.f, w = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, cw = 0.f;
   __device__ __forceinline__ static void nadd(float &s, float &c, float v) {
     const float t = s + v;
     c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
     s = t;
   }
-  __device__ __forceinline__ void add(float dx, float dy, float dz, float f) {
+  __device__ __forceinline__ void add(float dx, float dy, float dz, float f, float mr) {
     nadd(x, cx, f * dx);
     nadd(y, cy, f * dy);
     nadd(z, cz, f * dz);
+    if constexpr (kPot) nadd(w, cw, -mr);
   }
-  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz, float &ow) const {
     ox = x + cx;
     oy = y + cy;
     oz = z + cz;
+    ow = w + cw;
   }
 };
 
@@ -136,38 +143,39 @@ struct Acc3<true> {
 // (rotating among those); after a whole number of rotation periods u_k holds
 // sum p + K k.
 constexpr uint32_t kBlk = 64;  // list entries per block
-template <bool kComp>
+template <bool kComp, bool kPot>
 struct RunSums;
-template <>
-struct RunSums<false> {
+template <bool kPot>
+struct RunSums<false, kPot> {
   static constexpr uint32_t kNum = 4;
-  Acc3<false> u0, u1, u2, u3;
+  Acc3<false, kPot> u0, u1, u2, u3;
   __device__ __forceinline__ void advance(uint32_t K) {
     if (K == 1u) {
-      const Acc3<false> t = u0;
+      const Acc3<false, kPot> t = u0;
       u0 = u1;
       u1 = u2;
       u2 = u3;
       u3 = t;
     } else if (K == 2u) {
-      const Acc3<false> t = u0;
+      const Acc3<false, kPot> t = u0;
       u0 = u1;
       u1 = t;
     }
   }
-  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz, float &ow) const {
     ox = ((u0.x + u1.x) + u2.x) + u3.x;
     oy = ((u0.y + u1.y) + u2.y) + u3.y;
     oz = ((u0.z + u1.z) + u2.z) + u3.z;
+    ow = ((u0.w + u1.w) + u2.w) + u3.w;
   }
 };
-template <>
-struct RunSums<true> {
+template <bool kPot>
+struct RunSums<true, kPot> {
   static constexpr uint32_t kNum = 1;
-  Acc3<true> u0;
+  Acc3<true, kPot> u0;
   __device__ __forceinline__ void advance(uint32_t) {}
-  __device__ __forceinline__ void total(float &ox, float &oy, float &oz) const {
-    u0.total(ox, oy, oz);
+  __device__ __forceinline__ void total(float &ox, float &oy, float &oz, float &ow) const {
+    u0.total(ox, oy, oz, ow);
   }
 };
 
@@ -179,13 +187,13 @@ constexpr uint32_t kFlushUnroll = 4;
 constexpr uint32_t kListPad = 8 * kFlushUnroll;  // largest S times the unroll
 
 __device__ __forceinline__ void eq1_term(const float4 e, float4 pi, float eps2, float &dx,
-                                         float &dy, float &dz, float &f) {
+                                         float &dy, float &dz, float &f, float &mr) {
   dx = e.x - pi.x;
   dy = e.y - pi.y;
   dz = e.z - pi.z;
   const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
   const float rinv = __builtin_amdgcn_rsqf(r2);
-  const float mr = e.w * rinv;
+  mr = e.w * rinv;
   const float rinv2 = rinv * rinv;
   f = mr * rinv2;
 }
@@ -193,10 +201,10 @@ __device__ __forceinline__ void eq1_term(const float4 e, float4 pi, float eps2, 
 // The stream count S is a template constant: the trip count and the LDS
 // offsets of one trip (u * S entries past the trip's base) are then uniform
 // and immediate.
-template <bool kComp, uint32_t S>
+template <bool kComp, bool kPot, uint32_t S>
 __device__ __forceinline__ void flush_run_s(const float4 *__restrict__ list, uint32_t padded,
                                             uint32_t stream, float4 pi, float eps2,
-                                            Acc3<kComp> &acc) {
+                                            Acc3<kComp, kPot> &acc) {
   constexpr uint32_t step = S * kFlushUnroll;
   const float4 *p = list + stream;
   for (uint32_t j0 = 0; j0 < padded; j0 += step) {
@@ -205,48 +213,48 @@ __device__ __forceinline__ void flush_run_s(const float4 *__restrict__ list, uin
     for (uint32_t u = 0; u < kFlushUnroll; ++u) e[u] = p[j0 + u * S];
 #pragma unroll
     for (uint32_t u = 0; u < kFlushUnroll; ++u) {
-      float dx, dy, dz, f;
-      eq1_term(e[u], pi, eps2, dx, dy, dz, f);
-      acc.add(dx, dy, dz, f);
+      float dx, dy, dz, f, mr;
+      eq1_term(e[u], pi, eps2, dx, dy, dz, f, mr);
+      acc.add(dx, dy, dz, f, mr);
     }
   }
 }
 
-template <bool kComp>
+template <bool kComp, bool kPot>
 __device__ __forceinline__ void flush_run(const float4 *__restrict__ list, uint32_t cnt,
                                           uint32_t stream, uint32_t S, float4 pi, float eps2,
-                                          Acc3<kComp> &acc) {
+                                          Acc3<kComp, kPot> &acc) {
   const uint32_t step = S * kFlushUnroll;
   const uint32_t padded = (cnt + step - 1) / step * step;
   // S is wave-uniform: these branches are not lane-predicated
   if (S == 1)
-    flush_run_s<kComp, 1>(list, padded, stream, pi, eps2, acc);
+    flush_run_s<kComp, kPot, 1>(list, padded, stream, pi, eps2, acc);
   else if (S == 2)
-    flush_run_s<kComp, 2>(list, padded, stream, pi, eps2, acc);
+    flush_run_s<kComp, kPot, 2>(list, padded, stream, pi, eps2, acc);
   else if (S == 4)
-    flush_run_s<kComp, 4>(list, padded, stream, pi, eps2, acc);
+    flush_run_s<kComp, kPot, 4>(list, padded, stream, pi, eps2, acc);
   else
-    flush_run_s<kComp, 8>(list, padded, stream, pi, eps2, acc);
+    flush_run_s<kComp, kPot, 8>(list, padded, stream, pi, eps2, acc);
 }
 
 // Flush the tile's cnt entries: whole blocks of 64 entries (the last one
 // possibly short), each into u0 followed by a rotation of the sums (the
 // compensated sum: all into its one sum). nblk counts the blocks added.
-template <bool kComp>
+template <bool kComp, bool kPot>
 __device__ __forceinline__ void flush_tile(float4 *__restrict__ list, uint32_t cnt, uint32_t K,
                                            uint32_t lane, uint32_t stream, uint32_t S,
-                                           float4 pi, float eps2, RunSums<kComp> &R,
+                                           float4 pi, float eps2, RunSums<kComp, kPot> &R,
                                            uint32_t &nblk) {
   // every lane stores (two lanes per slot, same value): no lane-predicated
   // region; slots [cnt, cnt + kListPad) are free
   list[cnt + (lane & (kListPad - 1))] = make_float4(0.f, 0.f, 0.f, 0.f);
   __builtin_amdgcn_wave_barrier();
   if constexpr (kComp) {
-    flush_run<kComp>(list, cnt, stream, S, pi, eps2, R.u0);
+    flush_run<kComp, kPot>(list, cnt, stream, S, pi, eps2, R.u0);
     return;
   }
   for (uint32_t off = 0; off < cnt; off += kBlk) {
-    flush_run<kComp>(list + off, min(kBlk, cnt - off), stream, S, pi, eps2, R.u0);
+    flush_run<kComp, kPot>(list + off, min(kBlk, cnt - off), stream, S, pi, eps2, R.u0);
     R.advance(K);
     ++nblk;
   }
@@ -266,6 +274,10 @@ __device__ __forceinline__ void stream_reduce(uint32_t Wd, float &sx, float &sy,
   }
 }
 
+__device__ __forceinline__ void stream_reduce1(uint32_t Wd, float &sw) {
+  for (uint32_t d = Wd; d < 64u; d <<= 1) sw += __shfl_xor(sw, (int)d, 64);
+}
+
 // The results of member `lane` (< gc) of group (gb, gc): G times the sum, in
 // caller order, and with |a| into the key-ordered mirror when there is one.
 __device__ __forceinline__ void store_group_result(const WalkArgs &a, uint32_t gb, uint32_t gc,
@@ -283,7 +295,7 @@ __device__ __forceinline__ void store_group_result(const WalkArgs &a, uint32_t g
   }
 }
 
-template <bool kComp, bool kHash>
+template <bool kComp, bool kHash, bool kPot>
 __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   const uint32_t wv = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
@@ -302,8 +314,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   const uint32_t npart = a.n;
   // K wavefronts per group (a power of two); task t is part t mod K of
   // queue position t / K
+  // (the compensated sum and the potential variant are never split)
   const uint32_t K = split_factor(ng, gridDim.x * kWalkWavesPerWG, a.split_slots, a.split_mode,
-                                  kComp);
+                                  kComp || kPot);
   const uint32_t kshift = K == 4u ? 2u : K == 2u ? 1u : 0u;
   // No lane-predicated region may sit in this loop: the compiler threads such
   // regions across the back-edge, and a wave that re-enters with lane 0 masked
@@ -326,7 +339,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
     const uint32_t stream = lane / Wd;
     const bool mem_ok = member < gc;
     const float4 pi = a.xyzm[gb + (mem_ok ? member : 0u)];
-    RunSums<kComp> R;
+    RunSums<kComp, kPot> R;
     uint64_t hsum = 0;
     stk[0] = a.groot ? a.groot[g] : 0u;  // the walk's root (same value in every lane)
     uint32_t top = 1, visited = 0, cnt = 0;
@@ -436,7 +449,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
         done += seg;
         if (cnt == a.tile) {
           __builtin_amdgcn_wave_barrier();
-          flush_tile<kComp>(list, cnt, K, lane, stream, S, pi, a.eps2, R, nblk);
+          flush_tile<kComp, kPot>(list, cnt, K, lane, stream, S, pi, a.eps2, R, nblk);
           __builtin_amdgcn_wave_barrier();
           cnt = 0;
         }
@@ -462,17 +475,26 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
     }
     if (overflow || corrupt) cnt = 0;
     __builtin_amdgcn_wave_barrier();
-    flush_tile<kComp>(list, cnt, K, lane, stream, S, pi, a.eps2, R, nblk);
+    flush_tile<kComp, kPot>(list, cnt, K, lane, stream, S, pi, a.eps2, R, nblk);
     __builtin_amdgcn_wave_barrier();
     // complete the rotation period (4 / K blocks): then u_k is sum part + K k
     if constexpr (!kComp)
-      for (; nblk & (RunSums<kComp>::kNum / K - 1u); ++nblk) R.advance(K);
+      for (; nblk & (RunSums<kComp, kPot>::kNum / K - 1u); ++nblk) R.advance(K);
     if (K == 1u) {
-      float sx, sy, sz;
-      R.total(sx, sy, sz);
+      float sx, sy, sz, sw;
+      R.total(sx, sy, sz, sw);
       stream_reduce(Wd, sx, sy, sz);
       store_group_result(a, gb, gc, lane, sx, sy, sz);
-    } else if constexpr (!kComp) {
+      if constexpr (kPot) {
+        // the member's own entry (r = eps exactly) is in its list: add its
+        // term back, phi_i = G (sum_j -m_j / r_j + m_i / eps)
+        stream_reduce1(Wd, sw);
+        if (lane < gc) {
+          const float self = pi.w * __builtin_amdgcn_rsqf(a.eps2);
+          a.phi[a.perm[gb + lane]] = a.G * (sw + self);
+        }
+      }
+    } else if constexpr (!kComp && !kPot) {
       // this part's running sums into the queue slot: [sum][component][lane]
       float *slot = a.split + (size_t)qi * (kSplitSlotBytes / 4);
       slot[((part + 0u) * 3 + 0) * 64 + lane] = R.u0.x;
@@ -598,13 +620,20 @@ __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
 template <bool kComp, bool kHash>
 __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk(WalkArgs a) {
   HIP_DYNAMIC_SHARED(float4, lds_list)
-  walk_body<kComp, kHash>(a, lds_list);
+  walk_body<kComp, kHash, false>(a, lds_list);
 }
 
 template <bool kComp, bool kHash>
 __global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk_retry(WalkArgs a) {
   HIP_DYNAMIC_SHARED(float4, lds_list)
-  walk_body<kComp, kHash>(a, lds_list);
+  walk_body<kComp, kHash, false>(a, lds_list);
+}
+
+// The potential variant (also writes phi; never split), main and retry pass.
+template <bool kComp, bool kHash>
+__global__ __launch_bounds__(64 * kWalkWavesPerWG) void k_walk_pot(WalkArgs a) {
+  HIP_DYNAMIC_SHARED(float4, lds_list)
+  walk_body<kComp, kHash, true>(a, lds_list);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
@@ -651,6 +680,7 @@ WalkArgs walk_args(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
   a.ax = ax;
   a.ay = ay;
   a.az = az;
+  a.phi = c.phi;
   a.G = c.G;
   a.eps2 = c.eps * c.eps;
   a.n = (uint32_t)n;
@@ -691,6 +721,10 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
   const WalkArgs a = walk_args(c, perm, n, ax, ay, az, P);
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
   launch_fill_u32(&P.sc->nretry, 0u, 1, st);
+  if (c.phi) {
+    NB_WALK_LAUNCH(k_walk_pot, c, dim3(blocks), walk_lds(c), st, a);
+    return;  // never split
+  }
   NB_WALK_LAUNCH(k_walk, c, dim3(blocks), walk_lds(c), st, a);
   // a split walk's results (the kernel returns at once when the walk was not split)
   if (!c.compensated)
@@ -711,7 +745,10 @@ void launch_walk_retry(const WalkCfg &c, const uint32_t *perm, int64_t n, float 
   r.fmask = (uint32_t)c.frontier2_cap - 1u;
   r.split_mode = -1;  // results written by the pass itself
   launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
-  NB_WALK_LAUNCH(k_walk_retry, c, dim3(c.retry_waves / kWalkWavesPerWG), walk_lds(c), st, r);
+  if (c.phi)
+    NB_WALK_LAUNCH(k_walk_pot, c, dim3(c.retry_waves / kWalkWavesPerWG), walk_lds(c), st, r);
+  else
+    NB_WALK_LAUNCH(k_walk_retry, c, dim3(c.retry_waves / kWalkWavesPerWG), walk_lds(c), st, r);
 }
 
 }  // namespace nb

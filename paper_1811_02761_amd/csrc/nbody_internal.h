@@ -59,6 +59,7 @@ struct DevScalars {
   uint32_t nretry;         // groups handed from the walk to its retry pass
   uint32_t pad[3];
   WalkStat wstat;
+  unsigned long long bar_epoch;  // launches of the grid-barrier calcNode so far
 };
 
 // Offsets of the workspace, all 256-byte aligned.
@@ -69,6 +70,8 @@ struct Layout {
   int64_t build_blocks = 0;
   int64_t walk_waves = 0;
   int64_t frontier_cap = 0;
+  int num_cu = 0;
+  size_t off_lvlblk, off_bar;
   size_t off_scalars, off_keysA, off_keysB, off_valsA, off_valsB, off_hist,
       off_xyzm, off_x32, off_pinfo, off_leafof, off_blkcnt, off_clevel,
       off_cpbegin, off_cpcount, off_cfchild, off_cnchild, off_cparent,
@@ -92,7 +95,10 @@ struct Ptrs {
   float *x32;           // FP32 (x, y, z, m) records of the state (caller order)
   uint32_t *pinfo;      // per sorted particle: s | D << 5 | group start << 15
   uint32_t *leafof;     // per sorted particle: its leaf cell
-  uint32_t *blkcnt;     // build block counts [kLevels][blocks] + totals
+  uint32_t *blkcnt;     // scratch of block counts (build, groups, block-step queue)
+  uint32_t *lvlblk;     // per level: cells starting in earlier build blocks [kLevels][blocks]
+                        // (+ totals), kept for the tree's life (ancestor indices)
+  unsigned long long *bar;  // grid barrier flags: [kBarSlots] arrivals, [kBarSlots] releases
   int32_t *clevel;
   uint32_t *cpbegin, *cpcount;
   int32_t *cfchild, *cnchild, *cparent;
@@ -159,7 +165,11 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
 void launch_sys_keys(const Coords &c, int64_t n, int nsys, int r, const Ptrs &P,
                      hipStream_t st);
 constexpr int kMaxSystems = 4096;
-void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L,
+// calcNode synchronisation (nbody_params.calcnode_sync)
+constexpr int kCalcNodeLevels = 1;  // one launch per tree level
+constexpr int kCalcNodeGrid = 2;    // one persistent launch with a grid barrier
+constexpr int kBarSlots = 1024;     // workgroups of the persistent launch, at most
+void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L, int mode,
                     hipStream_t st);
 // asort (may be null): key-ordered a_old with |a|, read instead of a gather
 // asort in a new key order from itself in the old one (inv_old: the old tree's
@@ -189,6 +199,7 @@ struct WalkCfg {
   bool asort_out;  // also write the outputs, with |a|, to P.asort in key order
   int split;       // wavefronts per group: 0 by queue length, else 1, 2 or 4
   int64_t split_slots;
+  float *phi = nullptr;  // potential output (caller order): the potential variant
 };
 // enqueue the walk kernel (the queue head must already be zero), then its
 // retry pass for groups whose stack overflowed
@@ -199,6 +210,10 @@ void launch_walk_retry(const WalkCfg &c, const uint32_t *perm, int64_t n, float 
 void launch_direct(int64_t n, const float *x, const float *y, const float *z,
                    const float *m, float G, float eps, float *ax, float *ay,
                    float *az, hipStream_t st);
+void launch_direct64(int64_t n, const float *x, const float *y, const float *z,
+                     const float *m, int64_t nt, const int64_t *tgt, double G, double eps,
+                     double *ax, double *ay, double *az, double *aabs, double *phi,
+                     hipStream_t st);
 void launch_kick(int64_t n, float *vx, float *vy, float *vz, const float *ax,
                  const float *ay, const float *az, float hdt, hipStream_t st);
 // Where a drift puts the FP32 image of the new positions: with xyzm set,
@@ -222,6 +237,15 @@ __device__ __forceinline__ void store_position(int64_t i, int64_t n, float fx, f
 void launch_drift(int64_t n, double *x, double *y, double *z, const float *vx,
                   const float *vy, const float *vz, double dt, float *x32, SortedOut so,
                   hipStream_t st);
+// second-order Runge-Kutta (Heun): predict writes only the FP32 image of
+// x + v dt; correct updates x, v from a and the predicted-position a_p
+void launch_rk2_predict(int64_t n, const double *x, const double *y, const double *z,
+                        const float *vx, const float *vy, const float *vz, double dt,
+                        float *x32, SortedOut so, hipStream_t st);
+void launch_rk2_correct(int64_t n, double *x, double *y, double *z, float *vx, float *vy,
+                        float *vz, const float *ax, const float *ay, const float *az,
+                        const float *apx, const float *apy, const float *apz, double dt,
+                        float *x32, SortedOut so, hipStream_t st);
 // inv[perm[s]] = s
 void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
@@ -264,6 +288,10 @@ void launch_cost_after(int64_t n, bool queued, const uint32_t *perm, const Ptrs 
 // length, mode 2: the model); queued: sort the current queue, else all groups
 void launch_cost_order(int64_t n, bool queued, int mode, int H, const Ptrs &P,
                        hipStream_t st);
+
+// integrators (nbody_state.integrator)
+constexpr int kIntKDK = 0;  // kick-drift-kick leapfrog
+constexpr int kIntRK2 = 1;  // second-order Runge-Kutta, predict / correct
 
 // individual block time steps
 constexpr int kTickBits = 10;  // finest level: dt_max 2^-10

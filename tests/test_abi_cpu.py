@@ -25,7 +25,7 @@ def nb():
 def _header_functions():
     txt = open(os.path.join(ROOT, "include", "nbody.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(nbody_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(nbody_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_symbols_exported(nb):
@@ -38,7 +38,7 @@ def test_header_symbols_exported(nb):
 
 def test_abi_version_and_strings(nb):
     L = nb.lib()
-    assert L.nbody_abi_version() == 2
+    assert L.nbody_abi_version() == nb.ABI_VERSION == 3
     for code in range(0, -8, -1):
         assert len(L.nbody_strerror(code)) > 0
 
@@ -57,7 +57,8 @@ def test_create_rejects_bad_params_without_gpu(nb):
                 dict(leaf_max=0), dict(leaf_max=65, group_max=64), dict(compensated=2),
                 dict(order=3), dict(frontier_cap=100), dict(list_tile=60), dict(list_tile=136),
                 dict(walk_split=3),
-                dict(waves_per_cu=33), dict(checks=2), dict(group_merge=2)):
+                dict(waves_per_cu=33), dict(checks=2), dict(group_merge=2),
+                dict(calcnode_sync=3), dict(calcnode_sync=-1)):
         p = nb.Params(**bad).c()
         h = ctypes.c_void_p()
         assert nb.lib().nbody_create(ctypes.byref(p), None, ctypes.byref(h)) == nb.NBODY_EINVAL

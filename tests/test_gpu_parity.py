@@ -141,12 +141,14 @@ CASES = [
 @pytest.mark.parametrize("merge", [0, 1])
 @pytest.mark.parametrize("model,n,seed,leaf,gmax", CASES)
 def test_tree_and_walk_parity(nb, torch, orc, model, n, seed, leaf, gmax, merge):
+    # calcNode with one launch per level (merge 0) and with the persistent
+    # grid-barrier launch (merge 1)
     _say("case", model, n, seed, leaf, gmax, merge)
     p = I.plummer(n, seed) if model == "plummer" else I.galaxy(n, seed)
     x, y, z, _, _, _, m = p.f32()
     eps = 2.0 ** -7
     params = nb.Params(eps=eps, delta_acc=2.0 ** -9, leaf_max=leaf, group_max=gmax,
-                       group_merge=merge)
+                       group_merge=merge, calcnode_sync=1 + merge)
     # bootstrap pass (no a_old)
     ctx, acc0 = _run(nb, torch, x, y, z, m, params)
     ref0 = _ref(orc, x, y, z, m, params)
@@ -163,12 +165,13 @@ def test_tree_and_walk_parity(nb, torch, orc, model, n, seed, leaf, gmax, merge)
     _assert_rule(e, et)
 
 
+@pytest.mark.parametrize("sync", [1, 2])
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 65, 257])
-def test_tiny_and_ragged(nb, torch, orc, n):
-    _say("tiny", n)
+def test_tiny_and_ragged(nb, torch, orc, n, sync):
+    _say("tiny", n, "calcnode_sync", sync)
     p = I.plummer(n, 100 + n)
     x, y, z, _, _, _, m = p.f32()
-    params = nb.Params(leaf_max=4, group_max=16)
+    params = nb.Params(leaf_max=4, group_max=16, calcnode_sync=sync)
     a_old = np.ones((n, 3), np.float32)
     ctx, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
     ref = _ref(orc, x, y, z, m, params, a_old)
@@ -189,8 +192,8 @@ def test_coincident_particles(nb, torch, orc):
     z = np.concatenate([np.full(300, 0.125), rng.uniform(-1, 1, 700)]).astype(np.float32)
     m = np.full(1000, 1e-3, np.float32)
     a_old = np.ones((1000, 3), np.float32)
-    for merge in (0, 1):
-        params = nb.Params(leaf_max=8, group_max=32, group_merge=merge)
+    for merge, sync in ((0, 1), (1, 2), (1, 1)):
+        params = nb.Params(leaf_max=8, group_max=32, group_merge=merge, calcnode_sync=sync)
         ctx, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
         ref = _ref(orc, x, y, z, m, params, a_old)
         _compare_tree(nb, ctx, ref, torch)
@@ -234,18 +237,29 @@ def test_results_independent_of_tile_waves_frontier_and_split(nb, torch, orc):
         np.testing.assert_array_equal(o, outs[0])
 
 
-def test_compensated_sum_not_worse(nb, torch, orc):
+def test_compensated_sum_parity_and_not_worse(nb, torch, orc):
+    """Both summations, plain and compensated (Neumaier), under the
+    element-wise tree-parity rule against the oracle's tree; the compensated
+    sum is also no worse in RMS relative error."""
     g = I.galaxy(20000, 13)
     x, y, z, _, _, _, m = g.f32()
     pos = np.stack([x, y, z], 1)
     a_old = _ref(orc, x, y, z, m, nb.Params()).acc.astype(np.float32)
     ref = _ref(orc, x, y, z, m, nb.Params(delta_acc=2.0 ** -16), a_old)
+    _, A = orc.direct(pos.astype(np.float64), m, eps=nb.Params().eps, want_aabs=True)
     errs = []
     for comp in (0, 1):
-        _, acc = _run(nb, torch, x, y, z, m, nb.Params(delta_acc=2.0 ** -16, compensated=comp),
-                      a_old=a_old)
-        d = np.linalg.norm(acc - ref.acc, axis=1) / np.linalg.norm(ref.acc, axis=1)
-        errs.append(d)
+        ctx, acc = _run(nb, torch, x, y, z, m,
+                        nb.Params(delta_acc=2.0 ** -16, compensated=comp), a_old=a_old)
+        np.testing.assert_array_equal(_np(ctx.export(nb.X.GENTRIES)).astype(np.int64),
+                                      ref.gentries)
+        d = np.linalg.norm(acc.astype(np.float64) - ref.acc, axis=1)
+        e = d / np.linalg.norm(ref.acc, axis=1)
+        _say("compensated %d: max e~ %.3g, p99.9 e %.3g, max e %.3g"
+             % (comp, (d / A).max(), np.percentile(e, 99.9), e.max()))
+        assert (d / A).max() <= TOL
+        assert np.percentile(e, 99.9) <= TOL
+        errs.append(e)
     _say("plain rms %.3g comp rms %.3g" % (np.sqrt((errs[0] ** 2).mean()),
                                           np.sqrt((errs[1] ** 2).mean())))
     assert np.sqrt((errs[1] ** 2).mean()) <= np.sqrt((errs[0] ** 2).mean())
@@ -331,3 +345,53 @@ def test_kdk_step_matches_oracle(nb, torch, orc):
     assert np.abs(xg - x).max() < 1e-6 * np.abs(x).max()
     assert np.abs(vg - v).max() < 1e-4 * np.abs(v).max()
     assert st.t == 2 * dt
+
+
+def test_direct64_matches_oracle(nb, torch, orc):
+    """The FP64 direct sum on the GPU (the accuracy reference of the tree
+    walk) against the oracle's FP64 direct sum: only the summation order
+    differs, so they agree to about 1e-13 relative."""
+    g = I.galaxy(20000, 41)
+    x, y, z, _, _, _, m = g.f32()
+    rng = np.random.default_rng(8)
+    tgt = np.concatenate([[0, 19999], rng.choice(20000, 700, replace=False)]).astype(np.int64)
+    eps = 2.0 ** -6
+    ctx = nb.Context(nb.Params(eps=eps), n_max=16)
+    acc, aabs, phi = ctx.direct64(*(_dev(torch, a) for a in (x, y, z, m)), _dev(torch, tgt))
+    ctx.sync()
+    pos = np.stack([x, y, z], 1).astype(np.float64)
+    ra, rA, rphi = orc.direct(pos, m, eps=eps, targets=tgt, want_aabs=True, want_phi=True)
+    for got, ref in ((_np(acc), ra), (_np(aabs), rA), (_np(phi), rphi)):
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # an index outside [0, n) gives zeros
+    bad = _dev(torch, np.array([3, 20000], np.int64))
+    acc2, aabs2, phi2 = ctx.direct64(*(_dev(torch, a) for a in (x, y, z, m)), bad)
+    ctx.sync()
+    assert (_np(acc2)[1] == 0).all() and _np(aabs2)[1] == 0 and _np(phi2)[1] == 0
+    r3 = orc.direct(pos, m, eps=eps, targets=np.array([3]))
+    assert np.abs(_np(acc2)[0] - r3[0]).max() <= 1e-12 * np.abs(r3).max()
+
+
+def test_potential_matches_oracle(nb, torch, orc):
+    """nbody_calc_acc_pot: the potential from the same interaction lists
+    against the oracle tree's FP64 potential (all terms share one sign, so
+    the rule is a plain relative error per particle), accelerations
+    bit-identical to nbody_calc_acc, lists exact."""
+    g = I.galaxy(20000, 43)
+    x, y, z, _, _, _, m = g.f32()
+    eps = 2.0 ** -6
+    params = nb.Params(eps=eps, checks=1)
+    a_old = _ref(orc, x, y, z, m, params).acc.astype(np.float32)
+    ref = _ref(orc, x, y, z, m, params, a_old)
+    ctx, acc = _run(nb, torch, x, y, z, m, params, a_old=a_old)
+    (ax, ay, az), phi = ctx.calc_acc_pot(tuple(_dev(torch, a_old[:, k]) for k in range(3)))
+    ctx.sync()
+    acc2 = np.stack([_np(ax), _np(ay), _np(az)], 1)
+    np.testing.assert_array_equal(acc2, acc)
+    np.testing.assert_array_equal(_np(ctx.export(nb.X.GENTRIES)).astype(np.int64),
+                                  ref.gentries)
+    rel = np.abs(_np(phi).astype(np.float64) - ref.phi) / np.abs(ref.phi)
+    _say("potential: max rel %.3g" % rel.max())
+    assert rel.max() <= TOL
+    W = 0.5 * float((m * _np(phi)).sum())
+    assert abs(W / (0.5 * float((m * ref.phi).sum())) - 1) < 1e-6

@@ -317,10 +317,27 @@ def test_walk_zero_delta_is_direct(orc):
     # delta_acc = 0 accepts only zero-size cells, so the list is every particle
     g = I.galaxy(3000, 9)
     x, y, z, _, _, _, m = g.f32()
-    ad = orc.direct(np.stack([x, y, z], 1), m)
+    ad, phid = orc.direct(np.stack([x, y, z], 1), m, want_phi=True)
     tr = orc.tree_forces(x, y, z, m, a_old=ad, delta_acc=0.0)
     np.testing.assert_allclose(tr.acc, ad, rtol=1e-11, atol=1e-13)
+    # the potential over the same lists leaves out each particle's own entry
+    np.testing.assert_allclose(tr.phi, phid, rtol=1e-12)
     assert tr.interactions() == 3000 * 3000
+
+
+def test_walk_potential_plummer_energy(orc):
+    # the tree potential at delta_acc = 2^-9: W = sum m phi / 2 against the
+    # Plummer model's -3 pi / 32 (G = M = a = 1; softening 2^-7 and the
+    # truncation at u <= 0.999 move it by well under 1 %), and per particle
+    # within the walk's error of the direct potential
+    p = I.plummer(1 << 14, 21)
+    x, y, z, _, _, _, m = p.f32()
+    ad, phid = orc.direct(np.stack([x, y, z], 1), m, want_phi=True)
+    tr = orc.tree_forces(x, y, z, m, a_old=ad.astype(np.float32), delta_acc=2.0 ** -9)
+    W = 0.5 * float((m * tr.phi).sum())
+    assert abs(W / (-3 * np.pi / 32) - 1) < 0.02, W
+    assert np.abs(tr.phi / phid - 1).max() < 2e-3
+    assert (tr.phi < 0).all()
 
 
 def test_walk_monotone_and_converging(orc):
