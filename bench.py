@@ -220,6 +220,9 @@ def main():
     ap.add_argument("--group-max", type=int, default=64)
     ap.add_argument("--group-merge", type=int, default=1, choices=(0, 1))
     ap.add_argument("--leaf-max", type=int, default=16)
+    ap.add_argument("--calcnode", type=int, default=0, choices=(0, 1, 2),
+                    help="calcNode synchronisation: 0 library default, 1 one launch per "
+                         "level, 2 one persistent launch with a grid barrier")
     ap.add_argument("--order", type=int, default=0, choices=(0, 1, 2),
                     help="queue order of the headline run: 0 plain (Morton), 1 size-based, "
                          "2 learned (needs --learn-steps > 0)")
@@ -244,7 +247,7 @@ def main():
     params = nb.Params(eps=args.eps, delta_acc=args.delta, waves_per_cu=args.waves,
                        list_tile=args.tile, frontier_cap=args.frontier,
                        group_max=args.group_max, leaf_max=args.leaf_max,
-                       group_merge=args.group_merge)
+                       group_merge=args.group_merge, calcnode_sync=args.calcnode)
     block = not args.global_steps
     st = nb.State.from_numpy(gal.pos, gal.vel, gal.mass, dt=args.dt,
                              rebuild_interval=args.rebuild, block_steps=block, eta=args.eta)

@@ -350,14 +350,28 @@ nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable);
  * with the acceleration criterion) both took, I is their interactions now and
  * I_ref then (the whole walk is taken to have grown by the same factor; with
  * block steps the groups walked every step are the heavy ones that dominate
- * the walk time). Returns 1 (rebuild) iff
- * steps_since >= max_interval or excess_ms >= t_build_ms; 0 if steps_since
- * <= 0. For an excess growing linearly per step this rebuilds at the interval
- * that minimises the mean cost per step (the cumulative excess then equals
- * the build time). nbody_step decides once every earlier walk is measured.
+ * the walk time). next_excess_ms is the extra time the coming step's walk is
+ * expected to add on the current tree (its walk time on a fresh tree, from
+ * the last walk of the same step kind, times the growth I / I_ref - 1 of the
+ * last walk). allowed is 0 where a rebuild should wait for the step after
+ * (see nbody_rebuild_allowed). Returns 1 (rebuild before the coming step)
+ * iff steps_since >= max_interval, or allowed and excess_ms + next_excess_ms
+ * >= t_build_ms; 0 if steps_since <= 0. For an excess growing linearly per
+ * step this rebuilds at the interval that minimises the mean cost per step.
+ * nbody_step decides once every earlier walk is measured.
  * Pure function, no device access. */
-int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms,
-                             int32_t steps_since, int32_t max_interval);
+int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms, double next_excess_ms,
+                             int32_t allowed, int32_t steps_since, int32_t max_interval);
+
+/* Host-only: with block time steps (ticks of dt_max 2^-10), may the tree be
+ * rebuilt before the step ending at tick `next_tick`? Only if that step is
+ * at least as heavy as the one after it (steps of length `step_ticks`): a
+ * step's particles are those of the levels ending at its tick, so its kind
+ * is the coarsest such level, 10 - min(ctz(tick), 10); rebuilding before the
+ * heavier of two consecutive steps gives the fresh tree to the bigger walk
+ * (with levels 0..3 occupied: before every second step). Returns 1 or 0.
+ * Pure function, no device access. */
+int32_t nbody_rebuild_allowed(int64_t next_tick, int64_t step_ticks);
 
 /* ---- Cost model of the walk queue (a small MLP: 4 inputs, two tanh layers
  * of `hidden` units, one output; hidden in {8, 16, 32, 64}). It predicts a

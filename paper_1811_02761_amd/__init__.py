@@ -13,7 +13,7 @@ import os
 from dataclasses import dataclass, field, fields
 
 __all__ = ["Params", "Context", "State", "lib", "LIB_PATH", "NbodyError", "X",
-           "rebuild_decide", "HEADER_FUNCTIONS"]
+           "rebuild_decide", "rebuild_allowed", "HEADER_FUNCTIONS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnbody_hip.so")
 
@@ -85,7 +85,8 @@ HEADER_FUNCTIONS = [
     "nbody_abi_version", "nbody_strerror", "nbody_params_default", "nbody_create",
     "nbody_destroy", "nbody_workspace_query", "nbody_bind_workspace", "nbody_build_tree",
     "nbody_refit", "nbody_calc_acc", "nbody_step", "nbody_direct", "nbody_export",
-    "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide", "nbody_timing",
+    "nbody_get_stats", "nbody_sync", "nbody_rebuild_decide", "nbody_rebuild_allowed",
+    "nbody_timing",
     "nbody_mlp_nparams", "nbody_mlp_forward", "nbody_mlp_grad", "nbody_mlp_adam",
     "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order", "nbody_set_systems",
     "nbody_step_graph", "nbody_direct64", "nbody_calc_acc_pot",
@@ -125,8 +126,10 @@ def lib():
         L.nbody_get_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.nbody_sync.argtypes = [vp]
         L.nbody_timing.argtypes = [vp, i32]
-        L.nbody_rebuild_decide.argtypes = [C.c_double, C.c_double, i32, i32]
+        L.nbody_rebuild_decide.argtypes = [C.c_double, C.c_double, C.c_double, i32, i32, i32]
         L.nbody_rebuild_decide.restype = i32
+        L.nbody_rebuild_allowed.argtypes = [C.c_int64, C.c_int64]
+        L.nbody_rebuild_allowed.restype = i32
         f32 = C.c_float
         L.nbody_mlp_nparams.argtypes = [i32]
         L.nbody_mlp_nparams.restype = i64
@@ -170,9 +173,16 @@ def mlp_fan_in(hidden: int):
                            np.full(H + 1, H)]).astype(np.float64)
 
 
-def rebuild_decide(t_build_ms, excess_ms, steps_since, max_interval=64):
+def rebuild_decide(t_build_ms, excess_ms, steps_since, max_interval=64, next_excess_ms=0.0,
+                   allowed=True):
     """The library's host-side rebuild rule (pure function)."""
-    return bool(lib().nbody_rebuild_decide(t_build_ms, excess_ms, steps_since, max_interval))
+    return bool(lib().nbody_rebuild_decide(t_build_ms, excess_ms, next_excess_ms, int(allowed),
+                                           steps_since, max_interval))
+
+
+def rebuild_allowed(next_tick, step_ticks):
+    """May the tree be rebuilt before the block step ending at next_tick?"""
+    return bool(lib().nbody_rebuild_allowed(next_tick, step_ticks))
 
 
 @dataclass

@@ -67,6 +67,14 @@ struct nbody_ctx {
   } gkey[2] = {};
   int64_t sys_n = 0;            // particles of the batch
   int mlp_hidden = 0;  // hidden width of the installed cost model (0: none)
+  // rebuild rule: per step kind the last walk time scaled to a fresh tree,
+  // the growth I / I_ref of the last walk on the current tree, and the tick
+  // and finest level of the last walk's step (block steps)
+  double w0_kind[kTickBits + 1] = {};
+  double growth = 1.0;
+  long long last_tick = 0;
+  int last_kmax = 0;
+  bool block_mode = false;
 };
 
 namespace {
@@ -125,6 +133,14 @@ int64_t eff_frontier(const nbody_params &p, int64_t cell_cap) {
   int64_t f = 64;
   while (f < cell_cap && f < 16384) f <<= 1;
   return f;
+}
+
+// Kind of the block step ending at tick T (ticks of dt_max 2^-kTickBits):
+// the coarsest level whose step ends there, so smaller is heavier.
+int step_kind(int64_t T) {
+  if (T <= 0) return 0;
+  const int tz = __builtin_ctzll((unsigned long long)T);
+  return kTickBits - (tz < kTickBits ? tz : kTickBits);
 }
 
 nbody_status hip_status() {
@@ -219,6 +235,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_split = take((size_t)kSplitSlotBytes * (size_t)L.split_slots);
   L.off_gid = take(4 * N);
   L.off_gflag = take(4 * N);
+  L.off_ilist = take(16 * C);
+  L.off_leaves = take(8 * N);
   L.total = o;
   return L;
 }
@@ -290,6 +308,8 @@ Ptrs carve(void *base, const Layout &L) {
   P.split = reinterpret_cast<float *>(b + L.off_split);
   P.gid = reinterpret_cast<uint32_t *>(b + L.off_gid);
   P.gflag = reinterpret_cast<uint32_t *>(b + L.off_gflag);
+  P.ilist = reinterpret_cast<uint4 *>(b + L.off_ilist);
+  P.leaves = reinterpret_cast<uint2 *>(b + L.off_leaves);
   return P;
 }
 
@@ -368,6 +388,8 @@ __global__ void k_scalars_init(DevScalars *sc) {
   sc->nqueue = 0;
   sc->nactive = 0;
   sc->bar_epoch = 0;
+  for (int l = 0; l < kLevels; ++l) sc->icnt[l] = 0;
+  sc->nleaf = 0;
 }
 
 // FP32 image of FP64 positions with the masses, (x, y, z, m) records in
@@ -478,8 +500,16 @@ void harvest(nbody_ctx *ctx, bool block) {
         // extra time of this walk over a walk on the fresh tree: the groups
         // that the reference walk also took have grown from inter_ref to
         // inter_a interactions; the whole walk is taken to have grown alike
-        if (ctx->span_epoch[i] == ctx->epoch && w.inter_ref > 0 && w.inter_ref < w.inter_a)
-          ctx->excess_ms += ms * (1.0 - (double)w.inter_ref / (double)w.inter_a);
+        const double g = (w.inter_ref > 0 && w.inter_ref < w.inter_a)
+                             ? (double)w.inter_a / (double)w.inter_ref
+                             : 1.0;
+        if (ctx->span_epoch[i] == ctx->epoch) {
+          ctx->excess_ms += ms * (1.0 - 1.0 / g);
+          ctx->growth = g;
+        }
+        ctx->w0_kind[ctx->block_mode ? step_kind(w.tick) : 0] = ms / g;
+        ctx->last_tick = w.tick;
+        ctx->last_kmax = (int)w.kmax;
       }
     }
     ctx->sp_head = (ctx->sp_head + 1) % nbody_ctx::kSpans;
@@ -498,6 +528,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
                      ctx->n == n;
   ctx->epoch++;
   ctx->excess_ms = 0.0;
+  ctx->growth = 1.0;
   ctx->mac_walks = 0;
   const int sp = span_begin(ctx, 0);
   if (ctx->sys_r > 0) {
@@ -642,14 +673,21 @@ nbody_status nbody_params_default(nbody_params *p) {
 }
 
 // Rebuild rule (the paper's auto-tuned rebuild interval, Sec. 1 and 4.1,
-// minimises tree-construction plus gravity time): with average cost per step
-// since the last rebuild A = (t_build + sum of walk times) / k, rebuild when
-// the latest walk time reaches A. Exported for host-side testing.
-int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms, int32_t steps_since,
-                             int32_t max_interval) {
+// minimises tree-construction plus gravity time): rebuild once the measured
+// extra walk time of the current tree, including the coming step's expected
+// extra, reaches the build time, at a step where a rebuild is allowed.
+// Exported for host-side testing.
+int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms, double next_excess_ms,
+                             int32_t allowed, int32_t steps_since, int32_t max_interval) {
   if (steps_since <= 0) return 0;
   if (steps_since >= max_interval) return 1;
-  return excess_ms >= t_build_ms ? 1 : 0;
+  if (!allowed) return 0;
+  return excess_ms + next_excess_ms >= t_build_ms ? 1 : 0;
+}
+
+int32_t nbody_rebuild_allowed(int64_t next_tick, int64_t step_ticks) {
+  if (next_tick <= 0 || step_ticks <= 0) return 1;
+  return step_kind(next_tick) <= step_kind(next_tick + step_ticks) ? 1 : 0;
 }
 
 }  // extern "C"
@@ -662,8 +700,18 @@ namespace {
 bool rebuild_due(nbody_ctx *ctx, int32_t max_interval) {
   harvest(ctx, false);
   while (pending_walks(ctx) > 0) harvest(ctx, true);
-  return nbody_rebuild_decide(ctx->t_build_ms, ctx->excess_ms, ctx->since_rebuild,
-                              max_interval) != 0;
+  int kind = 0, allowed = 1;
+  if (ctx->block_mode) {
+    // the coming step ends one step of the finest occupied level later
+    const int64_t dT = (int64_t)1 << (kTickBits - std::min(std::max(ctx->last_kmax, 0), kTickBits));
+    const int64_t T = ctx->last_tick + dT;
+    kind = step_kind(T);
+    allowed = nbody_rebuild_allowed(T, dT);
+  }
+  const double w0 = ctx->w0_kind[kind] > 0.0 ? ctx->w0_kind[kind] : ctx->t_walk_ms;
+  const double next = w0 * (ctx->growth - 1.0);
+  return nbody_rebuild_decide(ctx->t_build_ms, ctx->excess_ms, next, allowed,
+                              ctx->since_rebuild, max_interval) != 0;
 }
 }  // namespace
 
@@ -955,6 +1003,7 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   if (st->integrator == kIntRK2 && st->level) return NBODY_EINVAL;  // global steps only
   if (st->n > ctx->L.n_max) return NBODY_ENOMEM;
   ctx->asort_src = nullptr;  // the caller may have changed the state since the last call
+  ctx->block_mode = st->level != nullptr;
   s = st->level ? step_block(ctx, st, n_steps) : step_global(ctx, st, n_steps);
   ctx->asort_src = nullptr;  // and may change it before the next call
   return s;

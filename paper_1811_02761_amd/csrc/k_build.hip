@@ -15,7 +15,9 @@
 //    iff l <= M_i(W) = max over s in [i-W, i] of cpl(s, s+W);
 //  * cells containing i exist at levels 0..D_i with D_i = min(M_i(leaf_max)
 //    + 1, 21).
-// So particle i starts the cells (l, i) for s_i <= l <= D_i. The level-order
+// So particle i starts the cells (l, i) for s_i <= l <= D_i, and its leaf iff
+// s_i <= D_i; its cells at levels up to E_i = M_i(64) hold more than 64
+// particles (calcNode treats those and the smaller ones differently). The level-order
 // index of (l, i) is the number of cells of lower level plus the number of
 // level-l cells starting before i: per-level block counts, a scan over
 // blocks, and ballots inside the block give it. The window maxima use a
@@ -60,8 +62,11 @@ __device__ void lds_window_max(int *t, int len, int k) {
 
 __device__ __forceinline__ int ilog2_floor(int v) { return 31 - __clz(v); }
 
-// Pass A: per sorted particle s_i and D_i; per block and level the number of
-// cells starting in the block.
+// Pass A: per sorted particle s_i, D_i and E_i; per block and level the
+// number of cells starting in the block, and (row kLevels) of leaves.
+constexpr int kBigCell = 64;  // cells holding more particles are "big" (E_i)
+static_assert(kH >= kBigCell, "the halo covers the window of a big cell");
+
 __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
                                                 uint32_t n, int leaf_max, int min_level,
                                                 uint32_t *__restrict__ pinfo,
@@ -69,7 +74,8 @@ __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
                                                 uint32_t nblk) {
   __shared__ uint64_t sk[kB + 2 * kH];
   __shared__ int tL[kB + kH];
-  __shared__ uint32_t wc[kLevels][kB / 64];
+  __shared__ int tE[kB + kH];
+  __shared__ uint32_t wc[kLevels + 1][kB / 64];
   const int64_t b0 = (int64_t)blockIdx.x * kB;
   for (int t = threadIdx.x; t < kB + 2 * kH; t += kB) {
     const int64_t pos = b0 - kH + t;
@@ -79,10 +85,13 @@ __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
   for (int t = threadIdx.x; t < kB + kH; t += kB) {
     const int64_t s = b0 - kH + t;
     tL[t] = (s >= 0 && s + leaf_max < n) ? cpl_keys(sk[t], sk[t + leaf_max]) : -1;
+    tE[t] = (s >= 0 && s + kBigCell < n) ? cpl_keys(sk[t], sk[t + kBigCell]) : -1;
   }
   __syncthreads();
   const int kLw = ilog2_floor(leaf_max + 1);
   lds_window_max(tL, kB + kH, kLw);
+  constexpr int kEw = 6;  // floor(log2(kBigCell + 1))
+  lds_window_max(tE, kB + kH, kEw);
   const int64_t i = b0 + threadIdx.x;
   const bool valid = i < n;
   const int li = threadIdx.x + kH;
@@ -91,15 +100,21 @@ __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
     s = (i == 0) ? 0 : cpl_keys(sk[li - 1], sk[li]) + 1;
     const int M = max(tL[li - leaf_max], tL[li - (1 << kLw) + 1]);
     D = max(min(M + 1, kMaxLevel), min_level);  // cells above min_level always split
-    pinfo[i] = (uint32_t)s | ((uint32_t)D << 5);  // group mark (bit 15) clear
+    const int E = max(tE[li - kBigCell], tE[li - (1 << kEw) + 1]);  // -1: no big cell
+    // group mark (bit 15) clear
+    pinfo[i] = (uint32_t)s | ((uint32_t)D << 5) | ((uint32_t)(E + 1) << 10);
   }
   const int w = threadIdx.x >> 6;
   for (int l = 0; l < kLevels; ++l) {
     const uint64_t b = __ballot(valid && s <= l && l <= D);
     if (lane_id() == 0) wc[l][w] = (uint32_t)__popcll(b);
   }
+  {
+    const uint64_t b = __ballot(valid && s <= D);  // leaf starts
+    if (lane_id() == 0) wc[kLevels][w] = (uint32_t)__popcll(b);
+  }
   __syncthreads();
-  if (threadIdx.x < kLevels) {
+  if (threadIdx.x <= kLevels) {
     uint32_t t = 0;
     for (int q = 0; q < kB / 64; ++q) t += wc[threadIdx.x][q];
     blkcnt[threadIdx.x * nblk + blockIdx.x] = t;
@@ -139,12 +154,14 @@ __global__ __launch_bounds__(256) void k_scan_rows(uint32_t *__restrict__ rows,
 __global__ void k_build_c(const uint32_t *__restrict__ totals, DevScalars *sc,
                           int64_t cell_cap) {
   if (threadIdx.x != 0) return;
+  sc->nleaf = totals[kLevels];
   uint32_t o = 0;
   for (int l = 0; l < kLevels; ++l) {
     sc->lvl_off[l] = o;
     o += totals[l];
   }
   sc->lvl_off[kLevels] = o;
+  for (int l = 0; l < kLevels; ++l) sc->icnt[l] = 0;  // filled by pass E
   if ((int64_t)o > cell_cap) {
     atomicOr(&sc->status, kStCapacity);
     o = 0;
@@ -199,8 +216,8 @@ __global__ __launch_bounds__(kB) void k_build_d(
     int32_t *__restrict__ clevel, uint32_t *__restrict__ cpbegin,
     uint32_t *__restrict__ cpcount, int32_t *__restrict__ cfchild,
     int32_t *__restrict__ cnchild, float4 *__restrict__ nodeB,
-    uint32_t *__restrict__ leafof) {
-  __shared__ uint32_t wpre[kLevels][kB / 64];
+    uint32_t *__restrict__ leafof, uint2 *__restrict__ leaves) {
+  __shared__ uint32_t wpre[kLevels + 1][kB / 64];  // row kLevels: leaf starts
   __shared__ uint32_t lvl_off[kLevels + 1];
   __shared__ uint64_t bound[kLevels][kChunks];       // bit j: s_{b0+j} <= level (or past n)
   __shared__ uint64_t wbal[kB / 64][kLevels];        // per wave and level: lanes starting a cell
@@ -230,6 +247,8 @@ __global__ __launch_bounds__(kB) void k_build_d(
       wbal[w][l] = b;
     }
   }
+  const uint64_t lbal = __ballot(valid && s <= D);  // this wave's leaf starts
+  if (lane == 0) wpre[kLevels][w] = (uint32_t)__popcll(lbal);
   s_lo[threadIdx.x] = (uint8_t)s;
   // this lane's cells as tasks of its wave, in lane order
   const uint32_t nt = (valid && s <= D) ? (uint32_t)(D - s + 1) : 0u;
@@ -237,7 +256,7 @@ __global__ __launch_bounds__(kB) void k_build_d(
   const uint32_t ntask = __builtin_amdgcn_readlane(tinc, 63);
   for (uint32_t t = 0; t < nt; ++t) tasks[w][tinc - nt + t] = (uint16_t)((lane << 5) | (s + t));
   __syncthreads();
-  if (threadIdx.x < kLevels) {
+  if (threadIdx.x <= kLevels) {
     uint32_t o = 0;
     for (int q = 0; q < kB / 64; ++q) {
       const uint32_t t = wpre[threadIdx.x][q];
@@ -246,6 +265,15 @@ __global__ __launch_bounds__(kB) void k_build_d(
     }
   }
   __syncthreads();
+  // the leaf list, in particle order: (leaf cell, first particle); the
+  // particle's leaf is its cell at level D
+  if (valid && s <= D) {
+    const uint32_t rank = blkcnt[(int64_t)kLevels * nblk + blockIdx.x] + wpre[kLevels][w] +
+                          (uint32_t)__popcll(lbal & lanemask_lt());
+    const uint32_t lrank = blkcnt[(int64_t)D * nblk + blockIdx.x] + wpre[D][w] +
+                           (uint32_t)__popcll(wbal[w][D] & lanemask_lt());
+    leaves[rank] = make_uint2(lvl_off[D] + lrank, (uint32_t)i);
+  }
   for (uint32_t t = lane; t < ntask; t += 64) {
     const uint32_t code = tasks[w][t];
     const uint32_t k = code >> 5;  // the lane (particle) starting the cell
@@ -380,6 +408,7 @@ __global__ __launch_bounds__(256) void k_build_long(
 
 // Pass E: parents and the first-child word of internal walk nodes.
 __global__ __launch_bounds__(256) void k_build_e(DevScalars *__restrict__ sc,
+                                                 const int32_t *__restrict__ clevel,
                                                  const int32_t *__restrict__ cfchild,
                                                  const int32_t *__restrict__ cnchild,
                                                  int32_t *__restrict__ cparent,
@@ -391,12 +420,53 @@ __global__ __launch_bounds__(256) void k_build_e(DevScalars *__restrict__ sc,
     const int k = cnchild[c];
     if (k > 0) {
       const int32_t f = cfchild[c];
-      if (f <= (int32_t)c || k > 8 || (uint32_t)(f + k) > nc) {
+      const int32_t l = clevel[c];
+      if (f <= (int32_t)c || k > 8 || (uint32_t)(f + k) > nc || l < 0 || l >= kMaxLevel) {
         atomicOr(&sc->status, kStCorrupt);
         continue;
       }
       reinterpret_cast<uint32_t *>(&nodeB[c])[2] = (uint32_t)f;
       for (int q = 0; q < k; ++q) cparent[f + q] = (int32_t)c;
+    }
+  }
+}
+
+// The per-level lists of internal cells, (cell, first child, children,
+// particles), in slots claimed by one atomic per wavefront and level (the
+// cells of a wavefront are consecutive, so mostly of one level).
+__global__ __launch_bounds__(256) void k_build_ilist(DevScalars *__restrict__ sc,
+                                                     const int32_t *__restrict__ clevel,
+                                                     const uint32_t *__restrict__ cpcount,
+                                                     const int32_t *__restrict__ cfchild,
+                                                     const int32_t *__restrict__ cnchild,
+                                                     uint4 *__restrict__ ilist) {
+  const uint32_t nc = sc->ncell;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  const uint32_t wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  for (uint64_t c0 = (uint64_t)wv * 64u; c0 < nc; c0 += (uint64_t)nw * 64u) {
+    const uint32_t c = (uint32_t)c0 + lane;
+    int k = 0, l = -1;
+    if (c < nc) {
+      k = cnchild[c];
+      if (k > 0) l = clevel[c];
+    }
+    bool todo = k > 0 && l >= 0 && l < kMaxLevel;
+    uint64_t m = __ballot(todo);
+    while (m) {
+      const int L = __builtin_amdgcn_readlane(l, __builtin_ctzll(m));
+      const bool mine = todo && l == L;
+      const uint64_t mm = __ballot(mine);
+      uint32_t base = 0;
+      if (lane == (uint32_t)__builtin_ctzll(mm)) base = atomicAdd(&sc->icnt[L], (uint32_t)__popcll(mm));
+      base = (uint32_t)__builtin_amdgcn_readlane((int)base, __builtin_ctzll(mm));
+      if (mine) {
+        const uint32_t slot = base + (uint32_t)__popcll(mm & lanemask_lt());
+        ilist[sc->lvl_off[L] + slot] =
+            make_uint4(c, (uint32_t)cfchild[c], (uint32_t)k, cpcount[c]);
+        todo = false;
+      }
+      m &= ~mm;
     }
   }
 }
@@ -540,21 +610,24 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   const uint32_t nblk = (uint32_t)cdiv(n, kB);
   // block rows [kLevels][nblk], then kLevels totals; the scanned rows stay
   // for the tree's life (calcNode derives ancestor indices from them)
-  uint32_t *totals = P.lvlblk + (int64_t)kLevels * nblk;
+  // (row kLevels: leaf starts)
+  uint32_t *totals = P.lvlblk + (int64_t)(kLevels + 1) * nblk;
   hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, leaf_max, r,
                      P.pinfo, P.lvlblk, nblk);
-  hipLaunchKernelGGL(k_scan_rows, dim3(kLevels), dim3(256), 0, st, P.lvlblk, nblk, totals);
+  hipLaunchKernelGGL(k_scan_rows, dim3(kLevels + 1), dim3(256), 0, st, P.lvlblk, nblk, totals);
   hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
   hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, P.pinfo, (uint32_t)n, P.lvlblk,
                      nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount, P.cfchild,
-                     P.cnchild, P.nodeB, P.leafof);
+                     P.cnchild, P.nodeB, P.leafof, P.leaves);
   hipLaunchKernelGGL(k_build_long, dim3(1024), dim3(256), 0, st, keys, (uint32_t)n, P.pinfo,
                      P.sc, P.clevel, P.cpbegin, P.cpcount, P.cfchild, P.cnchild, P.nodeB,
                      P.leafof);
   int64_t ge = cdiv(n, 256);
   if (ge > 4096) ge = 4096;
-  hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.cfchild, P.cnchild,
-                     P.cparent, P.nodeB);
+  hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cfchild,
+                     P.cnchild, P.cparent, P.nodeB);
+  hipLaunchKernelGGL(k_build_ilist, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cpcount,
+                     P.cfchild, P.cnchild, P.ilist);
   // groups (scanned in the block-count scratch)
   uint32_t *gblk = P.blkcnt, *gtot = P.blkcnt + nblk;
   hipLaunchKernelGGL(k_group_mark, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cpbegin,

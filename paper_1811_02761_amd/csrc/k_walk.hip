@@ -559,6 +559,8 @@ __global__ void k_walk_stat_zero(DevScalars *sc) {
     sc->wstat.inter = 0;
     sc->wstat.inter_a = 0;
     sc->wstat.inter_ref = 0;
+    sc->wstat.tick = sc->tick;
+    sc->wstat.kmax = sc->kmax;
   }
 }
 

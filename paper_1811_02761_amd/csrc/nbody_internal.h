@@ -34,6 +34,8 @@ struct WalkStat {
   unsigned long long inter_a;    // interactions of those walked groups that the
                                  // tree's first (reference) walk also took
   unsigned long long inter_ref;  // the same groups' interactions in that walk
+  long long tick;                // block steps: the walk's step ends at this tick
+  uint32_t kmax, pad;            // block steps: finest occupied level of that step
 };
 
 // Device scalars kept in the workspace.
@@ -60,6 +62,8 @@ struct DevScalars {
   uint32_t pad[3];
   WalkStat wstat;
   unsigned long long bar_epoch;  // launches of the grid-barrier calcNode so far
+  uint32_t icnt[kLevels];  // internal cells per level (the build's internal-cell lists)
+  uint32_t nleaf;          // leaves of the current tree
 };
 
 // Offsets of the workspace, all 256-byte aligned.
@@ -79,7 +83,7 @@ struct Layout {
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
-      off_inv, off_asort, off_split, off_gid, off_gflag;
+      off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
@@ -93,11 +97,13 @@ struct Ptrs {
   uint32_t *hist;       // sort histograms [radix][blocks] + totals[radix]
   float4 *xyzm;         // sorted x, y, z, m
   float *x32;           // FP32 (x, y, z, m) records of the state (caller order)
-  uint32_t *pinfo;      // per sorted particle: s | D << 5 | group start << 15
+  uint32_t *pinfo;      // per sorted particle: s | D << 5 | (E + 1) << 10 | group start << 15
+                        // (cells from level s to D start at it; its cells up to level E
+                        // hold more than 64 particles)
   uint32_t *leafof;     // per sorted particle: its leaf cell
   uint32_t *blkcnt;     // scratch of block counts (build, groups, block-step queue)
-  uint32_t *lvlblk;     // per level: cells starting in earlier build blocks [kLevels][blocks]
-                        // (+ totals), kept for the tree's life (ancestor indices)
+  uint32_t *lvlblk;     // per level: cells starting in earlier build blocks [kLevels][blocks],
+                        // then leaves [blocks] (+ totals), kept for the tree's life
   unsigned long long *bar;  // grid barrier flags: [kBarSlots] arrivals, [kBarSlots] releases
   int32_t *clevel;
   uint32_t *cpbegin, *cpcount;
@@ -134,6 +140,9 @@ struct Ptrs {
   float *split;         // split walk: per queue position 4 x 3 x 64 partial sums
   uint32_t *gid;        // group of each sorted particle
   uint32_t *gflag;      // block steps: group holds a particle whose step ends (zero between steps)
+  uint4 *ilist;         // internal cells of level l at [lvl_off[l], lvl_off[l] + icnt[l]):
+                        // (cell, first child, children, particles), in no particular order
+  uint2 *leaves;        // leaves in particle order: (cell, first particle)
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);

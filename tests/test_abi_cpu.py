@@ -78,19 +78,42 @@ def test_rebuild_rule_synthetic_sequences(nb):
     # no steps since rebuild: never; the cap on the interval
     assert not d(5.0, 100.0, 0)
     assert d(5.0, 0.0, 64, 64)
+    assert d(5.0, 0.0, 64, 64, allowed=False)
+    # a step where a rebuild must wait never rebuilds below the cap
+    assert not d(5.0, 100.0, 3, 64, allowed=False)
     # walks of a fresh tree take 1 ms and every step on the same tree adds
     # 0.1 ms: walk k (k = 0, 1, ...) has excess 0.1 k, so the cumulative excess
-    # after K steps is 0.05 K (K - 1); with a 10 ms build the rule fires at the
-    # smallest K with 0.05 K (K - 1) >= 10, K = 15 (the mean cost per step,
-    # 10 / K + 1 + 0.05 (K - 1), is smallest near K = sqrt(200) = 14.1)
-    def interval(t_build, slope):
+    # after K steps is 0.05 K (K - 1). Without a look ahead the rule fires at
+    # the smallest K with 0.05 K (K - 1) >= 10, K = 15; counting the coming
+    # walk's excess 0.1 K too, at the smallest K with 0.05 K (K + 1) >= 10,
+    # K = 14. The mean cost per step, 10 / K + 1 + 0.05 (K - 1), is smallest
+    # near K = sqrt(200) = 14.1.
+    def interval(t_build, slope, ahead=False):
         ex = 0.0
         for k in range(1, 200):
             ex += slope * (k - 1)
-            if d(t_build, ex, k, 1000):
+            if d(t_build, ex, k, 1000, next_excess_ms=slope * k if ahead else 0.0):
                 return k
     assert interval(10.0, 0.1) == 15
+    assert interval(10.0, 0.1, ahead=True) == 14
     mean = lambda K: 10.0 / K + 1 + 0.05 * (K - 1)  # noqa: E731
-    assert abs(mean(15) - min(mean(K) for K in range(1, 100))) < 0.01
+    best = min(range(1, 100), key=mean)
+    assert best == 14
     # a cheap build rebuilds early, an expensive one late
     assert interval(0.5, 0.1) < 6 < 15 < interval(100.0, 0.1)
+
+
+def test_rebuild_allowed_before_the_heavier_block_step(nb):
+    a = nb.rebuild_allowed
+    # levels 0..3 occupied (steps of 2^7 ticks): the steps of a dt_max cycle
+    # end at ticks 128 k; their kinds (coarsest level ending there) are
+    # 3, 2, 3, 1, 3, 2, 3, 0: a rebuild may precede the steps of kind <= the
+    # next one's, i.e. every second step, the ones walking more levels
+    got = [a(128 * k, 128) for k in range(1, 17)]
+    assert got == [False, True] * 8
+    # one level occupied: every step is alike
+    assert all(a(1024 * k, 1024) for k in range(1, 9))
+    # global steps (tick 0) always
+    assert a(0, 1024)
+    # levels 0..1 (steps of 512 ticks): kinds 1, 0, 1, 0: before kind 0
+    assert [a(512 * k, 512) for k in range(1, 5)] == [False, True, False, True]
