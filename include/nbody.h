@@ -373,6 +373,30 @@ int32_t nbody_rebuild_decide(double t_build_ms, double excess_ms, double next_ex
  * Pure function, no device access. */
 int32_t nbody_rebuild_allowed(int64_t next_tick, int64_t step_ticks);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the tree build
+ * and force evaluation of nbody_build_tree followed by nbody_calc_acc in one
+ * stateless call, on a workspace the library holds in a static device array
+ * of 128 MiB per device (enough for n up to about 2^18 at leaf_max 16; the
+ * call returns NBODY_ENOMEM when the layout for (p, n) does not fit). It
+ * calls no allocator: no context, no events, no host copies; everything is
+ * enqueued on hip_stream and the call returns at once. p as for
+ * nbody_create; frontier_cap above 256 (or 0) is taken as 256, walk_split,
+ * order and calcnode_sync are fixed (none of them changes a result: the
+ * accelerations equal those of the context path bit for bit). x, y, z, m:
+ * device FP32, caller order, length n; ax_old..az_old: a_old of Eq. 2, or all
+ * NULL for the bootstrap criterion; ax..az: device outputs, caller order.
+ * status_dev (device int32, may be NULL) receives the device-side status
+ * bits of the call (0, or a nonzero word where nbody_sync would report
+ * NBODY_EOVERFLOW / NBODY_ENONFINITE / NBODY_ECORRUPT); argument errors are
+ * returned directly. All calls on one device share the one array: calls
+ * that overlap in time on a device race (serialise them on one stream). */
+nbody_status nbody_tree_forces_noalloc(const nbody_params *p, void *hip_stream, int64_t n,
+                                       const float *x, const float *y, const float *z,
+                                       const float *m, const float *ax_old,
+                                       const float *ay_old, const float *az_old, float *ax,
+                                       float *ay, float *az, int32_t *status_dev);
+
 /* ---- Cost model of the walk queue (a small MLP: 4 inputs, two tanh layers
  * of `hidden` units, one output; hidden in {8, 16, 32, 64}). It predicts a
  * group's log2 interaction count from NBODY_X_FEAT-style features: log2 of

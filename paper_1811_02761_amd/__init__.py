@@ -13,7 +13,7 @@ import os
 from dataclasses import dataclass, field, fields
 
 __all__ = ["Params", "Context", "State", "lib", "LIB_PATH", "NbodyError", "X",
-           "rebuild_decide", "rebuild_allowed", "HEADER_FUNCTIONS"]
+           "rebuild_decide", "rebuild_allowed", "tree_forces_noalloc", "HEADER_FUNCTIONS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnbody_hip.so")
 
@@ -89,7 +89,7 @@ HEADER_FUNCTIONS = [
     "nbody_timing",
     "nbody_mlp_nparams", "nbody_mlp_forward", "nbody_mlp_grad", "nbody_mlp_adam",
     "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order", "nbody_set_systems",
-    "nbody_step_graph", "nbody_direct64", "nbody_calc_acc_pot",
+    "nbody_step_graph", "nbody_direct64", "nbody_calc_acc_pot", "nbody_tree_forces_noalloc",
 ]
 
 _lib = None
@@ -143,6 +143,8 @@ def lib():
         L.nbody_step_graph.argtypes = [vp, C.POINTER(_State), i32]
         L.nbody_calc_acc_pot.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.nbody_direct64.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.nbody_tree_forces_noalloc.argtypes = [C.POINTER(_Params), vp, i64, vp, vp, vp, vp,
+                                                vp, vp, vp, vp, vp, vp, vp]
         for f in HEADER_FUNCTIONS:
             fn = getattr(L, f)
             if fn.restype is C.c_int or fn.restype is None and f != "nbody_destroy":
@@ -224,6 +226,32 @@ def _need(t, dtype, n, name):
         raise ValueError("%s must be a contiguous %s CUDA tensor with >= %d elements"
                          % (name, dtype, n))
     return t
+
+
+def tree_forces_noalloc(params, x, y, z, m, a_old, out, status=None, stream=None):
+    """nbody_tree_forces_noalloc: tree build + force evaluation on the library's
+    static scratch. x, y, z, m: float32 CUDA tensors (length n); a_old: None
+    (bootstrap criterion) or (ax, ay, az); out: (ax, ay, az) float32 tensors
+    of length >= n, written in place; status: optional int32 CUDA tensor that
+    receives the device-side status bits."""
+    import torch
+    n = x.numel()
+    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (m, "m")):
+        _need(t, torch.float32, n, nm)
+    for t, nm in zip(out, ("ax", "ay", "az")):
+        _need(t, torch.float32, n, nm)
+    ao = (None, None, None) if a_old is None else a_old
+    if a_old is not None:
+        for t, nm in zip(ao, ("ax_old", "ay_old", "az_old")):
+            _need(t, torch.float32, n, nm)
+    if status is not None:
+        _need(status, torch.int32, 1, "status")
+    cp = (params or Params()).c()
+    _check(lib().nbody_tree_forces_noalloc(C.byref(cp), _stream_handle(stream), n, _ptr(x),
+                                           _ptr(y), _ptr(z), _ptr(m), *[_ptr(t) for t in ao],
+                                           *[_ptr(t) for t in out], _ptr(status)),
+           "nbody_tree_forces_noalloc")
+    return out
 
 
 class Context:

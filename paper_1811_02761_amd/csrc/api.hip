@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -55,6 +56,7 @@ struct nbody_ctx {
   int nsys = 1, sys_r = 0;      // batch of independent systems (nbody_set_systems)
   // graph-captured steps (nbody_step_graph): one graph per step kind
   bool capturing = false;
+  bool no_spans = false;  // a context on the static scratch: no events, no host copies
   hipStream_t cap_st = nullptr;  // capture and replay stream (default priority)
   hipEvent_t cap_ev[2] = {};
   hipGraphExec_t gexec[2] = {};  // [0] refit step, [1] rebuild step
@@ -437,7 +439,7 @@ void harvest(nbody_ctx *ctx, bool block);
 // While a step is being captured into a graph there are no spans (no events,
 // no copies to the host): span_begin returns -1 and the rest do nothing.
 int span_begin(nbody_ctx *ctx, int kind) {
-  if (ctx->capturing) return -1;
+  if (ctx->capturing || ctx->no_spans) return -1;
   if (ctx->sp_count == nbody_ctx::kSpans) harvest(ctx, true);
   const int i = (ctx->sp_head + ctx->sp_count) % nbody_ctx::kSpans;
   ctx->span_kind[i] = kind;
@@ -1377,6 +1379,86 @@ nbody_status nbody_step_graph(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) 
   if (hipEventRecord(ctx->cap_ev[1], ctx->cap_st) != hipSuccess ||
       hipStreamWaitEvent(ctx->st, ctx->cap_ev[1], 0) != hipSuccess)
     return NBODY_EHIP;
+  return hip_status();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Tree forces on the library's own static scratch (no allocation by the call).
+//
+// The workspace of this entry point is the file-scope device array `scratch`.
+// Host code never passes the array's name to a kernel (in host code it only
+// stands in for the symbol); the device address comes from
+// hipGetSymbolAddress, once per device, and is kept per device.
+static constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kStaticMaxDevices] = {};
+
+// The device address of `scratch` on device dev (the current device).
+nbody_status static_scratch(int dev, void **out) {
+  if (dev < 0 || dev >= kStaticMaxDevices) return NBODY_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NBODY_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NBODY_OK;
+}
+
+__global__ void k_status_out(const DevScalars *sc, int32_t *out) { *out = sc->status; }
+}  // namespace
+
+extern "C" {
+
+nbody_status nbody_tree_forces_noalloc(const nbody_params *p, void *hip_stream, int64_t n,
+                                       const float *x, const float *y, const float *z,
+                                       const float *m, const float *axo, const float *ayo,
+                                       const float *azo, float *ax, float *ay, float *az,
+                                       int32_t *status_dev) {
+  nbody_status s = check_params(p);
+  if (s != NBODY_OK) return s;
+  if (n < 1 || !x || !y || !z || !m || !ax || !ay || !az) return NBODY_EINVAL;
+  const int nnull = (axo == nullptr) + (ayo == nullptr) + (azo == nullptr);
+  if (nnull != 0 && nnull != 3) return NBODY_EINVAL;
+  int dev = 0;
+  const int cu = device_cu_count(&dev);
+  if (cu <= 0) return NBODY_EHIP;
+  void *ws = nullptr;
+  if ((s = static_scratch(dev, &ws)) != NBODY_OK) return s;
+  // a small depth-first stack (groups that outgrow it go to the retry pass)
+  // and no split walk keep the layout small; neither changes any result
+  nbody_params q = *p;
+  if (q.frontier_cap == 0 || q.frontier_cap > 256) q.frontier_cap = 256;
+  q.walk_split = 1;
+  q.order = 0;
+  q.calcnode_sync = kCalcNodeLevels;
+  const Layout L = make_layout(q, n, cu);
+  if (L.total > kStaticScratchBytes) return NBODY_ENOMEM;
+  nbody_ctx c;  // on the stack: no events, no pinned memory
+  c.p = q;
+  c.order = 0;
+  c.st = static_cast<hipStream_t>(hip_stream);
+  c.device = dev;
+  c.num_cu = cu;
+  c.ws = ws;
+  c.ws_bytes = kStaticScratchBytes;
+  c.L = L;
+  c.P = carve(ws, L);
+  c.bound = true;
+  c.no_spans = true;
+  if (!carve_complete(c.P, ws)) return NBODY_ECORRUPT;
+  // the scratch keeps the previous call's contents: reset what starts at zero
+  hipLaunchKernelGGL(k_scalars_init, dim3(1), dim3(1), 0, c.st, c.P.sc);
+  if ((s = do_build(&c, n, Coords{x, y, z, m, 1})) != NBODY_OK) return s;
+  if ((s = do_calc(&c, axo, ayo, azo, ax, ay, az)) != NBODY_OK) return s;
+  if (status_dev) hipLaunchKernelGGL(k_status_out, dim3(1), dim3(1), 0, c.st, c.P.sc, status_dev);
   return hip_status();
 }
 
