@@ -77,6 +77,12 @@ struct nbody_ctx {
   long long last_tick = 0;
   int last_kmax = 0;
   bool block_mode = false;
+  // internal cells per level of the latest tree whose counts reached the host
+  // (shape of the calcNode launches): pinned copy, its event, pending flag
+  uint32_t *h_istart = nullptr;
+  hipEvent_t ev_istart = nullptr;
+  bool istart_pending = false, have_cells = false;
+  uint32_t level_cells[kMaxLevel] = {};
 };
 
 namespace {
@@ -390,7 +396,7 @@ __global__ void k_scalars_init(DevScalars *sc) {
   sc->nqueue = 0;
   sc->nactive = 0;
   sc->bar_epoch = 0;
-  for (int l = 0; l < kLevels; ++l) sc->icnt[l] = 0;
+  for (int l = 0; l <= kLevels; ++l) sc->istart[l] = 0;
   sc->nleaf = 0;
 }
 
@@ -519,6 +525,18 @@ void harvest(nbody_ctx *ctx, bool block) {
   }
 }
 
+// Internal cells per level of the latest tree whose counts have reached the
+// host, or null (calcNode then launches every level).
+const uint32_t *moment_plan(nbody_ctx *ctx) {
+  if (ctx->istart_pending && hipEventQuery(ctx->ev_istart) == hipSuccess) {
+    for (int l = 0; l < kMaxLevel; ++l)
+      ctx->level_cells[l] = ctx->h_istart[l + 1] - ctx->h_istart[l];
+    ctx->istart_pending = false;
+    ctx->have_cells = true;
+  }
+  return ctx->have_cells ? ctx->level_cells : nullptr;
+}
+
 // The (x, y, z, m) records of x32 as coordinates.
 Coords records(const float *x32) { return Coords{x32, x32 + 1, x32 + 2, x32 + 3, 4}; }
 
@@ -551,7 +569,15 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   launch_invert(pm, n, P.inv, ctx->st);
   launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, ctx->nsys,
                ctx->sys_r, P, ctx->L, ctx->st);
-  launch_moments(n, ctx->p.G, P, ctx->L, eff_calcnode(ctx->p), ctx->st);
+  const uint32_t *plan = moment_plan(ctx);
+  if (ctx->h_istart && !ctx->capturing && !ctx->istart_pending) {
+    // this tree's counts for the later refits (read once the copy has landed)
+    (void)hipMemcpyAsync(ctx->h_istart, &P.sc->istart, sizeof(uint32_t) * (kLevels + 1),
+                         hipMemcpyDeviceToHost, ctx->st);
+    (void)hipEventRecord(ctx->ev_istart, ctx->st);
+    ctx->istart_pending = true;
+  }
+  launch_moments(n, ctx->p.G, P, ctx->L, eff_calcnode(ctx->p), plan, ctx->st);
   span_end(ctx, sp);
   span_done(ctx, sp);
   launch_fill_u32(P.gref, 0u, n, ctx->st);
@@ -566,13 +592,15 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
 
 nbody_status do_refit(nbody_ctx *ctx, const Coords &c) {
   launch_gather(c, ctx->perm, ctx->n, ctx->P.xyzm, ctx->st);
-  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, eff_calcnode(ctx->p), ctx->st);
+  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, eff_calcnode(ctx->p), moment_plan(ctx),
+                 ctx->st);
   return hip_status();
 }
 
 // Refit after a drift that wrote the key-ordered positions itself.
 nbody_status do_refit_sorted(nbody_ctx *ctx) {
-  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, eff_calcnode(ctx->p), ctx->st);
+  launch_moments(ctx->n, ctx->p.G, ctx->P, ctx->L, eff_calcnode(ctx->p), moment_plan(ctx),
+                 ctx->st);
   return hip_status();
 }
 
@@ -747,6 +775,14 @@ nbody_status nbody_create(const nbody_params *p, void *hip_stream, nbody_ctx **o
     nbody_destroy(c);
     return NBODY_EHIP;
   }
+  if (hipHostMalloc((void **)&c->h_istart, sizeof(uint32_t) * (kLevels + 1),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_istart, hipEventDisableTiming) != hipSuccess) {
+    if (c->h_istart) (void)hipHostFree(c->h_istart);
+    c->h_istart = nullptr;
+    nbody_destroy(c);
+    return NBODY_EHIP;
+  }
   *out = c;
   return NBODY_OK;
 }
@@ -758,10 +794,10 @@ void nbody_destroy(nbody_ctx *ctx) {
     if (ctx->ev_b[i]) (void)hipEventDestroy(ctx->ev_b[i]);
     if (ctx->ev_c[i]) (void)hipEventDestroy(ctx->ev_c[i]);
   }
-  if (ctx->aux) {
-    (void)hipStreamSynchronize(ctx->st);
-    (void)hipHostFree(ctx->aux);
-  }
+  if (ctx->aux || ctx->h_istart) (void)hipStreamSynchronize(ctx->st);
+  if (ctx->aux) (void)hipHostFree(ctx->aux);
+  if (ctx->h_istart) (void)hipHostFree(ctx->h_istart);
+  if (ctx->ev_istart) (void)hipEventDestroy(ctx->ev_istart);
   if (ctx->cap_st) {
     (void)hipStreamSynchronize(ctx->cap_st);
     for (int k = 0; k < 2; ++k) {

@@ -161,7 +161,6 @@ __global__ void k_build_c(const uint32_t *__restrict__ totals, DevScalars *sc,
     o += totals[l];
   }
   sc->lvl_off[kLevels] = o;
-  for (int l = 0; l < kLevels; ++l) sc->icnt[l] = 0;  // filled by pass E
   if ((int64_t)o > cell_cap) {
     atomicOr(&sc->status, kStCapacity);
     o = 0;
@@ -431,44 +430,53 @@ __global__ __launch_bounds__(256) void k_build_e(DevScalars *__restrict__ sc,
   }
 }
 
-// The per-level lists of internal cells, (cell, first child, children,
-// particles), in slots claimed by one atomic per wavefront and level (the
-// cells of a wavefront are consecutive, so mostly of one level).
-__global__ __launch_bounds__(256) void k_build_ilist(DevScalars *__restrict__ sc,
-                                                     const int32_t *__restrict__ clevel,
-                                                     const uint32_t *__restrict__ cpcount,
-                                                     const int32_t *__restrict__ cfchild,
+// The list of internal cells in cell order (so level by level), entries
+// (cell, first child, children, particles): internal cells per block of 256
+// cells, a scan of the block counts, then each cell's rank. istart[l] is the
+// rank of cell lvl_off[l] (the internal cells before level l).
+__global__ __launch_bounds__(256) void k_ilist_count(const DevScalars *__restrict__ sc,
                                                      const int32_t *__restrict__ cnchild,
-                                                     uint4 *__restrict__ ilist) {
+                                                     uint32_t *__restrict__ cblk) {
+  __shared__ uint32_t wc[4];
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  const bool in = c < sc->ncell && cnchild[c] > 0;
+  const uint64_t b = __ballot(in);
+  if (lane_id() == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) cblk[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+__global__ __launch_bounds__(256) void k_ilist_emit(DevScalars *__restrict__ sc,
+                                                    const uint32_t *__restrict__ cpcount,
+                                                    const int32_t *__restrict__ cfchild,
+                                                    const int32_t *__restrict__ cnchild,
+                                                    const uint32_t *__restrict__ cblk,
+                                                    uint4 *__restrict__ ilist) {
+  __shared__ uint32_t wc[4];
   const uint32_t nc = sc->ncell;
-  const uint32_t lane = lane_id();
-  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  const uint32_t wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  for (uint64_t c0 = (uint64_t)wv * 64u; c0 < nc; c0 += (uint64_t)nw * 64u) {
-    const uint32_t c = (uint32_t)c0 + lane;
-    int k = 0, l = -1;
-    if (c < nc) {
-      k = cnchild[c];
-      if (k > 0) l = clevel[c];
-    }
-    bool todo = k > 0 && l >= 0 && l < kMaxLevel;
-    uint64_t m = __ballot(todo);
-    while (m) {
-      const int L = __builtin_amdgcn_readlane(l, __builtin_ctzll(m));
-      const bool mine = todo && l == L;
-      const uint64_t mm = __ballot(mine);
-      uint32_t base = 0;
-      if (lane == (uint32_t)__builtin_ctzll(mm)) base = atomicAdd(&sc->icnt[L], (uint32_t)__popcll(mm));
-      base = (uint32_t)__builtin_amdgcn_readlane((int)base, __builtin_ctzll(mm));
-      if (mine) {
-        const uint32_t slot = base + (uint32_t)__popcll(mm & lanemask_lt());
-        ilist[sc->lvl_off[L] + slot] =
-            make_uint4(c, (uint32_t)cfchild[c], (uint32_t)k, cpcount[c]);
-        todo = false;
-      }
-      m &= ~mm;
-    }
-  }
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  const int k = c < nc ? cnchild[c] : 0;
+  const bool in = k > 0;
+  const uint64_t b = __ballot(in);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) wc[w] = (uint32_t)__popcll(b);
+  __syncthreads();
+  uint32_t rank = cblk[blockIdx.x];
+  for (int q = 0; q < w; ++q) rank += wc[q];
+  rank += (uint32_t)__popcll(b & lanemask_lt());  // internal cells before c
+  if (in) ilist[rank] = make_uint4(c, (uint32_t)cfchild[c], (uint32_t)k, cpcount[c]);
+  if (c < nc)
+    for (int l = 0; l < kLevels; ++l)
+      if (sc->lvl_off[l] == c) sc->istart[l] = rank;
+}
+
+// Levels starting at or past the last cell (empty) and the total.
+__global__ void k_ilist_total(const uint32_t *__restrict__ total, DevScalars *sc) {
+  if (threadIdx.x != 0) return;
+  const uint32_t t = total[0], nc = sc->ncell;
+  for (int l = 0; l < kLevels; ++l)
+    if (sc->lvl_off[l] >= nc) sc->istart[l] = t;
+  sc->istart[kLevels] = t;
 }
 
 __device__ __forceinline__ void mark_chunks(uint32_t *__restrict__ pinfo, uint32_t b,
@@ -626,8 +634,14 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   if (ge > 4096) ge = 4096;
   hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cfchild,
                      P.cnchild, P.cparent, P.nodeB);
-  hipLaunchKernelGGL(k_build_ilist, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cpcount,
-                     P.cfchild, P.cnchild, P.ilist);
+  // internal-cell list (block counts in the group scratch, before the groups use it)
+  const uint32_t cblk = (uint32_t)cdiv(L.cell_cap, 256);
+  uint32_t *ib = P.blkcnt, *itot = P.blkcnt + cblk;
+  hipLaunchKernelGGL(k_ilist_count, dim3(cblk), dim3(256), 0, st, P.sc, P.cnchild, ib);
+  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, st, ib, cblk, itot);
+  hipLaunchKernelGGL(k_ilist_emit, dim3(cblk), dim3(256), 0, st, P.sc, P.cpcount, P.cfchild,
+                     P.cnchild, ib, P.ilist);
+  hipLaunchKernelGGL(k_ilist_total, dim3(1), dim3(64), 0, st, itot, P.sc);
   // groups (scanned in the block-count scratch)
   uint32_t *gblk = P.blkcnt, *gtot = P.blkcnt + nblk;
   hipLaunchKernelGGL(k_group_mark, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cpbegin,

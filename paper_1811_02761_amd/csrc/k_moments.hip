@@ -180,9 +180,29 @@ __global__ __launch_bounds__(256) void k_mom_level(DevScalars *__restrict__ sc, 
                                                    float4 *__restrict__ nodeA,
                                                    float4 *__restrict__ nodeB) {
   const uint32_t ncell = sc->ncell;
-  const uint32_t c0 = sc->lvl_off[level], cnt = sc->icnt[level];
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x)
-    internal_cell(ilist[c0 + t], ncell, n, sc, cpbegin, xyzm, mom64, nodeA, nodeB);
+  const uint32_t t0 = sc->istart[level], t1 = sc->istart[level + 1];
+  for (uint32_t t = t0 + blockIdx.x * blockDim.x + threadIdx.x; t < t1;
+       t += gridDim.x * blockDim.x)
+    internal_cell(ilist[t], ncell, n, sc, cpbegin, xyzm, mom64, nodeA, nodeB);
+}
+
+// Several consecutive levels with few internal cells (lo <= l <= hi,
+// deepest first) in one workgroup: a workgroup barrier between levels.
+__global__ __launch_bounds__(1024) void k_mom_levels_narrow(DevScalars *__restrict__ sc, int lo,
+                                                            int hi, uint32_t n,
+                                                            const uint4 *__restrict__ ilist,
+                                                            const uint32_t *__restrict__ cpbegin,
+                                                            const float4 *__restrict__ xyzm,
+                                                            double4 *__restrict__ mom64,
+                                                            float4 *__restrict__ nodeA,
+                                                            float4 *__restrict__ nodeB) {
+  const uint32_t ncell = sc->ncell;
+  for (int l = hi; l >= lo; --l) {
+    const uint32_t t0 = sc->istart[l], t1 = sc->istart[l + 1];
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x)
+      internal_cell(ilist[t], ncell, n, sc, cpbegin, xyzm, mom64, nodeA, nodeB);
+    __syncthreads();  // (makes the level's global writes visible to the workgroup)
+  }
 }
 
 // Lock-free grid barrier (Xiao and Feng 2010): each workgroup publishes its
@@ -260,65 +280,56 @@ __global__ __launch_bounds__(256) void k_mom_levels_grid(DevScalars *__restrict_
   const uint32_t ncell = sc->ncell;
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
   for (int l = kMaxLevel - 1; l >= 0; --l) {
-    const uint32_t cnt = sc->icnt[l];
-    if (cnt == 0u) continue;  // uniform over the grid: no barrier needed
-    const uint32_t c0 = sc->lvl_off[l];
-    for (uint32_t t = tid; t < cnt; t += nth)
-      internal_cell(ilist[c0 + t], ncell, n, sc, cpbegin, xyzm, mom64, nodeA, nodeB);
+    const uint32_t t0 = sc->istart[l], t1 = sc->istart[l + 1];
+    if (t1 <= t0) continue;  // uniform over the grid: no barrier needed
+    for (uint32_t t = t0 + tid; t < t1; t += nth)
+      internal_cell(ilist[t], ncell, n, sc, cpbegin, xyzm, mom64, nodeA, nodeB);
     if (!grid_sync(bar_in, bar_out, ++goal, &fail, sc)) return;
   }
 }
 
 // ---------------------------------------------------------------- phase 3
-// b2 of the internal cells of at most kSmallCell particles: one lane each,
-// over the internal cells of all levels (t counts them level by level: pre
-// holds the per-level prefix of the counts).
+// b2 of the internal cells of at most kSmallCell particles: 32 lanes per
+// cell (two particles per lane at most), coalesced loads, then a maximum
+// over the half wavefront.
 __global__ __launch_bounds__(256) void k_mom_b2small(DevScalars *__restrict__ sc, uint32_t n,
                                                      const uint4 *__restrict__ ilist,
                                                      const uint32_t *__restrict__ cpbegin,
                                                      const float4 *__restrict__ xyzm,
                                                      float4 *__restrict__ nodeA) {
-  __shared__ uint32_t pre[kMaxLevel + 1], off[kMaxLevel];
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int l = 0; l < kMaxLevel; ++l) {
-      pre[l] = t;
-      t += sc->icnt[l];
-      off[l] = sc->lvl_off[l];
-    }
-    pre[kMaxLevel] = t;
-  }
-  __syncthreads();
-  const uint32_t ncell = sc->ncell, total = pre[kMaxLevel];
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += gridDim.x * blockDim.x) {
-    int lo = 0, hi = kMaxLevel;  // the level l with pre[l] <= t < pre[l + 1]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pre[mid] <= t) lo = mid;
-      else hi = mid;
-    }
-    const uint4 e = ilist[off[lo] + (t - pre[lo])];
-    if (e.w > kSmallCell) continue;
-    const uint32_t c = e.x;
-    const uint32_t pb = c < ncell ? cpbegin[c] : n;
-    if (pb >= n || e.w == 0u || e.w > n - pb) {
-      atomicOr(&sc->status, kStCorrupt);
-      continue;
-    }
-    const float4 cm = nodeA[c];
-    float bb = 0.0f;
-    for (uint32_t j0 = 0; j0 < e.w; j0 += 8) {
-      float4 q[8];
-#pragma unroll
-      for (uint32_t u = 0; u < 8; ++u) q[u] = xyzm[pb + min(j0 + u, e.w - 1u)];
-#pragma unroll
-      for (uint32_t u = 0; u < 8; ++u) {
-        const float d2 = dist2(q[u], cm.x, cm.y, cm.z);
-        bb = d2 > bb ? d2 : bb;  // (a repeated last particle changes nothing)
+  const uint32_t ncell = sc->ncell, total = sc->istart[kLevels];
+  const uint32_t lane = lane_id(), h = lane & 31u;
+  const uint32_t nhalf = gridDim.x * (blockDim.x >> 5);
+  for (uint32_t t0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2u; t0 < total;
+       t0 += nhalf) {
+    const uint32_t t = t0 + (lane >> 5);  // this half's cell
+    uint4 e = make_uint4(0u, 0u, 0u, 0u);
+    if (t < total) e = ilist[t];
+    const bool mine = t < total && e.w <= kSmallCell;
+    uint32_t pb = 0u;
+    float4 cm = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (mine) {
+      pb = e.x < ncell ? cpbegin[e.x] : n;
+      if (pb >= n || e.w == 0u || e.w > n - pb) {
+        if (h == 0) atomicOr(&sc->status, kStCorrupt);
+        pb = n;
+      } else {
+        cm = nodeA[e.x];
       }
     }
-    reinterpret_cast<float *>(&nodeA[c])[3] = bb;
+    const bool ok = mine && pb < n;
+    uint32_t v = 0u;
+    if (ok && h < e.w) v = __float_as_uint(dist2(xyzm[pb + h], cm.x, cm.y, cm.z));
+    if (ok && h + 32u < e.w) {
+      const uint32_t v2 = __float_as_uint(dist2(xyzm[pb + h + 32u], cm.x, cm.y, cm.z));
+      v = v2 > v ? v2 : v;
+    }
+    // maximum over each half (b2 >= 0: the bit patterns order like the values)
+    for (int d = 1; d < 32; d <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)v, d, 64);
+      v = o > v ? o : v;
+    }
+    if (ok && h == 0) reinterpret_cast<float *>(&nodeA[e.x])[3] = __uint_as_float(v);
   }
 }
 
@@ -470,16 +481,13 @@ __global__ __launch_bounds__(256) void k_mom_q(const DevScalars *__restrict__ sc
                                                const uint4 *__restrict__ ilist,
                                                const float4 *__restrict__ nodeA,
                                                float4 *__restrict__ nodeB) {
-  const uint32_t ncell = sc->ncell;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
-  for (int l = 0; l < kMaxLevel; ++l) {
-    const uint32_t c0 = sc->lvl_off[l], cnt = sc->icnt[l];
-    for (uint32_t t = tid; t < cnt; t += nth) {
-      const uint32_t c = ilist[c0 + t].x;
-      if (c >= ncell) continue;
-      const float gm = G * nodeB[c].x;
-      nodeB[c].y = gm * nodeA[c].w;
-    }
+  const uint32_t ncell = sc->ncell, total = sc->istart[kLevels];
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += gridDim.x * blockDim.x) {
+    const uint32_t c = ilist[t].x;
+    if (c >= ncell) continue;
+    const float gm = G * nodeB[c].x;
+    nodeB[c].y = gm * nodeA[c].w;
   }
 }
 
@@ -502,7 +510,7 @@ int grid_blocks(int num_cu) {
 }  // namespace
 
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L, int mode,
-                    hipStream_t st) {
+                    const uint32_t *level_cells, hipStream_t st) {
   const uint32_t nblk = (uint32_t)cdiv(n, kBuildThreads);
   // leaves <= n: one wavefront per 64 leaves, four per workgroup
   hipLaunchKernelGGL(k_mom_leaf, dim3((uint32_t)cdiv(n, 256)), dim3(256), 0, st, P.sc,
@@ -515,9 +523,27 @@ void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L, int mode
   } else {
     int64_t gl = cdiv(n, 256 * 8);
     gl = std::min<int64_t>(std::max<int64_t>(gl, 1), 2048);
-    for (int l = kMaxLevel - 1; l >= 0; --l)
-      hipLaunchKernelGGL(k_mom_level, dim3(gl), dim3(256), 0, st, P.sc, l, (uint32_t)n,
-                         P.ilist, P.cpbegin, P.xyzm, P.mom64, P.nodeA, P.nodeB);
+    // with level_cells (internal cells per level of a recent tree) runs of
+    // levels with at most kNarrowCells cells go to one single-workgroup
+    // launch each (correct for any counts; only the speed depends on them)
+    int hi = -1;  // top of the open run of narrow levels
+    for (int l = kMaxLevel - 1; l >= 0; --l) {
+      const bool narrow = level_cells && level_cells[l] <= kNarrowCells;
+      if (narrow) {
+        if (hi < 0) hi = l;
+        if (l > 0) continue;
+      }
+      if (hi >= 0) {
+        const int lo = narrow ? l : l + 1;
+        hipLaunchKernelGGL(k_mom_levels_narrow, dim3(1), dim3(1024), 0, st, P.sc, lo, hi,
+                           (uint32_t)n, P.ilist, P.cpbegin, P.xyzm, P.mom64, P.nodeA,
+                           P.nodeB);
+        hi = -1;
+      }
+      if (!narrow)
+        hipLaunchKernelGGL(k_mom_level, dim3(gl), dim3(256), 0, st, P.sc, l, (uint32_t)n,
+                           P.ilist, P.cpbegin, P.xyzm, P.mom64, P.nodeA, P.nodeB);
+    }
   }
   int64_t gi = cdiv(n, 256 * 4);
   gi = std::min<int64_t>(std::max<int64_t>(gi, 1), 4096);

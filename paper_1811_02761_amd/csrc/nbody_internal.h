@@ -62,7 +62,7 @@ struct DevScalars {
   uint32_t pad[3];
   WalkStat wstat;
   unsigned long long bar_epoch;  // launches of the grid-barrier calcNode so far
-  uint32_t icnt[kLevels];  // internal cells per level (the build's internal-cell lists)
+  uint32_t istart[kLevels + 1];  // internal cells of level l: ilist[istart[l] .. istart[l + 1])
   uint32_t nleaf;          // leaves of the current tree
 };
 
@@ -140,8 +140,8 @@ struct Ptrs {
   float *split;         // split walk: per queue position 4 x 3 x 64 partial sums
   uint32_t *gid;        // group of each sorted particle
   uint32_t *gflag;      // block steps: group holds a particle whose step ends (zero between steps)
-  uint4 *ilist;         // internal cells of level l at [lvl_off[l], lvl_off[l] + icnt[l]):
-                        // (cell, first child, children, particles), in no particular order
+  uint4 *ilist;         // internal cells in cell order, so level by level (istart):
+                        // (cell, first child, children, particles)
   uint2 *leaves;        // leaves in particle order: (cell, first particle)
 };
 
@@ -178,8 +178,12 @@ constexpr int kMaxSystems = 4096;
 constexpr int kCalcNodeLevels = 1;  // one launch per tree level
 constexpr int kCalcNodeGrid = 2;    // one persistent launch with a grid barrier
 constexpr int kBarSlots = 1024;     // workgroups of the persistent launch, at most
+// level_cells: internal cells per level of a recent tree (host array of
+// kMaxLevel), or null; it only shapes the launches (levels with at most
+// kNarrowCells cells are run by one workgroup), never the result
+constexpr uint32_t kNarrowCells = 1024;
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L, int mode,
-                    hipStream_t st);
+                    const uint32_t *level_cells, hipStream_t st);
 // asort (may be null): key-ordered a_old with |a|, read instead of a gather
 // asort in a new key order from itself in the old one (inv_old: the old tree's
 // caller index -> position; tmp: n float4 of scratch)
