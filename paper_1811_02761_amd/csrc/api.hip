@@ -44,7 +44,8 @@ struct nbody_ctx {
   int sp_head = 0, sp_count = 0;
   double walk_ms_sum = 0.0, build_ms_sum = 0.0;
   int64_t walk_calls = 0, build_calls = 0;
-  bool counting = false;  // accumulate interactions of every walk on the device
+  bool counting = false;  // accumulate the entries and interactions of every walk
+  unsigned long long entries_host = 0, inter_host = 0;  // (from each walk's statistics)
   WalkStat *aux = nullptr;   // pinned, one per span (walk spans)
   bool last_queued = false;  // the last walk used the queue (block steps)
   int64_t queued_sum = 0, ngroup_sum = 0;  // groups walked / present, summed over walks
@@ -245,6 +246,9 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   L.off_gflag = take(4 * N);
   L.off_ilist = take(16 * C);
   L.off_leaves = take(8 * N);
+  // the largest row scan: the build's level rows, or the internal-cell blocks
+  L.off_scan = take(4 * (size_t)std::max(scan_scratch_words(L.build_blocks, kLevels + 1),
+                                         scan_scratch_words(cdiv(L.cell_cap, 256), 1)));
   L.total = o;
   return L;
 }
@@ -318,6 +322,7 @@ Ptrs carve(void *base, const Layout &L) {
   P.gflag = reinterpret_cast<uint32_t *>(b + L.off_gflag);
   P.ilist = reinterpret_cast<uint4 *>(b + L.off_ilist);
   P.leaves = reinterpret_cast<uint2 *>(b + L.off_leaves);
+  P.scan = reinterpret_cast<uint32_t *>(b + L.off_scan);
   return P;
 }
 
@@ -505,6 +510,10 @@ void harvest(nbody_ctx *ctx, bool block) {
         ctx->walk_calls++;
         ctx->queued_sum += w.queued;
         ctx->ngroup_sum += w.ngroup;
+        if (ctx->counting) {
+          ctx->entries_host += w.entries;
+          ctx->inter_host += w.inter;
+        }
         // extra time of this walk over a walk on the fresh tree: the groups
         // that the reference walk also took have grown from inter_ref to
         // inter_a interactions; the whole walk is taken to have grown alike
@@ -656,7 +665,8 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   span_done(ctx, sp);
   ctx->last_queued = use_queue;
   if (mode != 0) launch_cost_after(ctx->n, true, ctx->perm, P, ctx->st);
-  if (ctx->counting)
+  // counted from the walk statistics on the host; a captured step has none
+  if (ctx->counting && ctx->capturing)
     hipLaunchKernelGGL(k_stats_accum, dim3(256), dim3(256), 0, ctx->st, P.sc, P.gent,
                        P.gcount, use_queue ? P.order : nullptr);
   return hip_status();
@@ -1092,6 +1102,7 @@ nbody_status nbody_timing(nbody_ctx *ctx, int32_t enable) {
   ctx->walk_calls = ctx->build_calls = 0;
   ctx->queued_sum = ctx->ngroup_sum = 0;
   ctx->counting = enable != 0;
+  ctx->entries_host = ctx->inter_host = 0;
   hipLaunchKernelGGL(k_acc_zero, dim3(1), dim3(1), 0, ctx->st, ctx->P.sc);
   return hip_status();
 }
@@ -1120,8 +1131,8 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out) {
   out->ngroup = h.ngroup;
   out->list_entries = (int64_t)h.entries_total;
   out->interactions = (int64_t)h.inter_total;
-  out->entries_sum = (int64_t)h.entries_acc;
-  out->interactions_sum = (int64_t)h.inter_acc;
+  out->entries_sum = (int64_t)(h.entries_acc + ctx->entries_host);
+  out->interactions_sum = (int64_t)(h.inter_acc + ctx->inter_host);
   out->queued = ctx->last_queued ? (int64_t)h.nqueue : (int64_t)h.ngroup;
   out->active = (int64_t)h.nactive;
   out->queued_sum = ctx->queued_sum;

@@ -372,7 +372,7 @@ void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, cons
   const uint32_t nblk = (uint32_t)cdiv(n, kQGroups);
   uint32_t *blk = P.blkcnt, *total = P.blkcnt + nblk;
   hipLaunchKernelGGL(k_blk_qcount, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gflag, blk);
-  launch_scan_rows(blk, nblk, 1, total, st);
+  launch_scan_rows(blk, nblk, 1, total, P.scan, st);
   hipLaunchKernelGGL(k_blk_qemit, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gflag, blk,
                      P.order);
   hipLaunchKernelGGL(k_blk_qtotal, dim3(1), dim3(64), 0, st, total, P.sc);

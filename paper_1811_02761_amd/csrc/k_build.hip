@@ -31,6 +31,8 @@
 // Each cell holding more than group_max particles marks the group starts
 // among its children; a scan over the marked particles lists the groups in
 // particle order.
+#include <algorithm>
+
 #include "nbody_internal.h"
 
 namespace nb {
@@ -121,33 +123,95 @@ __global__ __launch_bounds__(kB) void k_build_a(const uint64_t *__restrict__ K,
   }
 }
 
-// Exclusive scan of each row (one workgroup per row) of rows[row][0..nblk);
-// the row total goes to totals[row].
-__global__ __launch_bounds__(256) void k_scan_rows(uint32_t *__restrict__ rows,
-                                                   uint32_t nblk,
-                                                   uint32_t *__restrict__ totals) {
-  __shared__ uint32_t wsum[4];
-  uint32_t *row = rows + (int64_t)blockIdx.x * nblk;
-  const uint32_t per = (nblk + 255) / 256;
-  const uint32_t k0 = threadIdx.x * per;
-  uint32_t s = 0;
-  for (uint32_t k = k0; k < k0 + per && k < nblk; ++k) s += row[k];
-  const uint32_t inc = wave_incl_scan(s);
+// Exclusive scan of each row of rows[row][0 .. len) in place, the row total
+// to totals[row], in three coalesced passes over tiles of kScanTile entries:
+// tile sums, a scan of each row's tile sums (into tsum), then every tile
+// rescanned with its offset.
+constexpr uint32_t kScanTile = 4096;  // 256 threads x 16
+
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *wsum,
+                                                       uint32_t *total) {
+  const uint32_t inc = wave_incl_scan_dpp(v);
   const int w = threadIdx.x >> 6;
   if (lane_id() == 63) wsum[w] = inc;
   __syncthreads();
   uint32_t off = 0, tot = 0;
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (q < w) off += wsum[q];
+    off += q < w ? wsum[q] : 0u;
     tot += wsum[q];
   }
-  uint32_t run = off + inc - s;
-  for (uint32_t k = k0; k < k0 + per && k < nblk; ++k) {
-    const uint32_t v = row[k];
-    row[k] = run;
-    run += v;
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const uint32_t *__restrict__ rows,
+                                                    uint32_t len, uint32_t ntile,
+                                                    uint32_t *__restrict__ tsum) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t *row = rows + (size_t)blockIdx.y * len;
+  const uint32_t b = blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kScanTile / 256; ++k) {
+    const uint32_t j = b + k * 256u + threadIdx.x;
+    s += j < len ? row[j] : 0u;
   }
-  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+  uint32_t tot;
+  (void)block_excl_scan256(s, wsum, &tot);
+  if (threadIdx.x == 0) tsum[(size_t)blockIdx.y * ntile + blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tilesums(uint32_t *__restrict__ tsum,
+                                                       uint32_t ntile,
+                                                       uint32_t *__restrict__ totals) {
+  __shared__ uint32_t wsum[4];
+  uint32_t *t = tsum + (size_t)blockIdx.x * ntile;
+  uint32_t carry = 0;
+  for (uint32_t k0 = 0; k0 < ntile; k0 += 256) {
+    const uint32_t k = k0 + threadIdx.x;
+    const uint32_t v = k < ntile ? t[k] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(v, wsum, &tot);
+    if (k < ntile) t[k] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(uint32_t *__restrict__ rows, uint32_t len,
+                                                    uint32_t ntile,
+                                                    const uint32_t *__restrict__ tsum) {
+  __shared__ uint32_t wsum[4];
+  uint32_t *row = rows + (size_t)blockIdx.y * len;
+  const uint32_t b = blockIdx.x * kScanTile + threadIdx.x * (kScanTile / 256);
+  uint32_t v[kScanTile / 256];
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kScanTile / 256; ++k) {
+    v[k] = b + k < len ? row[b + k] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = tsum[(size_t)blockIdx.y * ntile + blockIdx.x] + block_excl_scan256(s, wsum, &tot);
+#pragma unroll
+  for (uint32_t k = 0; k < kScanTile / 256; ++k) {
+    if (b + k < len) row[b + k] = run;
+    run += v[k];
+  }
+}
+
+void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
+                      uint32_t *tsum, hipStream_t st) {
+  const uint32_t ntile = (uint32_t)std::max<int64_t>(cdiv(len, kScanTile), 1);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntile, nrows), dim3(256), 0, st, rows, len, ntile, tsum);
+  hipLaunchKernelGGL(k_scan_tilesums, dim3(nrows), dim3(256), 0, st, tsum, ntile, totals);
+  hipLaunchKernelGGL(k_scan_apply, dim3(ntile, nrows), dim3(256), 0, st, rows, len, ntile, tsum);
+}
+
+int64_t scan_scratch_words(int64_t len, int nrows) {
+  return std::max<int64_t>(cdiv(len, kScanTile), 1) * nrows;
 }
 
 // Pass C: level offsets and the cell count.
@@ -622,7 +686,7 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   uint32_t *totals = P.lvlblk + (int64_t)(kLevels + 1) * nblk;
   hipLaunchKernelGGL(k_build_a, dim3(nblk), dim3(kB), 0, st, keys, (uint32_t)n, leaf_max, r,
                      P.pinfo, P.lvlblk, nblk);
-  hipLaunchKernelGGL(k_scan_rows, dim3(kLevels + 1), dim3(256), 0, st, P.lvlblk, nblk, totals);
+  launch_scan_rows(P.lvlblk, nblk, kLevels + 1, totals, P.scan, st);
   hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
   hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, P.pinfo, (uint32_t)n, P.lvlblk,
                      nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount, P.cfchild,
@@ -638,7 +702,7 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   const uint32_t cblk = (uint32_t)cdiv(L.cell_cap, 256);
   uint32_t *ib = P.blkcnt, *itot = P.blkcnt + cblk;
   hipLaunchKernelGGL(k_ilist_count, dim3(cblk), dim3(256), 0, st, P.sc, P.cnchild, ib);
-  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, st, ib, cblk, itot);
+  launch_scan_rows(ib, cblk, 1, itot, P.scan, st);
   hipLaunchKernelGGL(k_ilist_emit, dim3(cblk), dim3(256), 0, st, P.sc, P.cpcount, P.cfchild,
                      P.cnchild, ib, P.ilist);
   hipLaunchKernelGGL(k_ilist_total, dim3(1), dim3(64), 0, st, itot, P.sc);
@@ -648,7 +712,7 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                      P.cpcount, P.cfchild, P.cnchild, (uint32_t)group_max, group_merge, r,
                      P.pinfo);
   hipLaunchKernelGGL(k_group_count, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk);
-  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, st, gblk, nblk, gtot);
+  launch_scan_rows(gblk, nblk, 1, gtot, P.scan, st);
   hipLaunchKernelGGL(k_group_emit, dim3(nblk), dim3(kB), 0, st, (uint32_t)n, P.pinfo, gblk,
                      P.gbegin, P.gid);
   hipLaunchKernelGGL(k_group_total, dim3(1), dim3(64), 0, st, gtot, (uint32_t)n, P.sc,
@@ -659,9 +723,5 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                        r, P.groot);
 }
 
-void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_scan_rows, dim3(nrows), dim3(256), 0, st, rows, len, totals);
-}
 
 }  // namespace nb

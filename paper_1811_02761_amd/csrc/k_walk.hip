@@ -559,6 +559,7 @@ __global__ void k_walk_stat_zero(DevScalars *sc) {
     sc->wstat.inter = 0;
     sc->wstat.inter_a = 0;
     sc->wstat.inter_ref = 0;
+    sc->wstat.entries = 0;
     sc->wstat.tick = sc->tick;
     sc->wstat.kmax = sc->kmax;
   }
@@ -572,9 +573,9 @@ __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
                                                    const uint32_t *__restrict__ gcount,
                                                    const uint32_t *__restrict__ gent,
                                                    uint32_t *__restrict__ gref, int record) {
-  __shared__ unsigned long long s_cur[4], s_a[4], s_ref[4];
+  __shared__ unsigned long long s_cur[4], s_a[4], s_ref[4], s_e[4];
   const uint32_t nq = order ? sc->nqueue : sc->ngroup;
-  unsigned long long cur = 0, cur_a = 0, ref = 0;
+  unsigned long long cur = 0, cur_a = 0, ref = 0, ent = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq;
        q += gridDim.x * blockDim.x) {
     const uint32_t g = order ? order[q] : q;
@@ -582,6 +583,7 @@ __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
     if (e == 0xffffffffu) continue;
     const unsigned long long ec = (unsigned long long)e * c;
     cur += ec;
+    ent += e;
     uint32_t r = gref[g];
     if (record && r == 0) {
       r = e;
@@ -596,23 +598,27 @@ __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
     cur += __shfl_xor(cur, d, 64);
     cur_a += __shfl_xor(cur_a, d, 64);
     ref += __shfl_xor(ref, d, 64);
+    ent += __shfl_xor(ent, d, 64);
   }
   if (lane_id() == 0) {
     s_cur[threadIdx.x >> 6] = cur;
     s_a[threadIdx.x >> 6] = cur_a;
     s_ref[threadIdx.x >> 6] = ref;
+    s_e[threadIdx.x >> 6] = ent;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long a = 0, b = 0, r = 0;
+    unsigned long long a = 0, b = 0, r = 0, e = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
       a += s_cur[w];
       b += s_a[w];
       r += s_ref[w];
+      e += s_e[w];
     }
     atomicAdd(&sc->wstat.inter, a);
     atomicAdd(&sc->wstat.inter_a, b);
     atomicAdd(&sc->wstat.inter_ref, r);
+    atomicAdd(&sc->wstat.entries, e);
     if (blockIdx.x == 0) sc->wstat.queued = nq;
   }
 }

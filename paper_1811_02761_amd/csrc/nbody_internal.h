@@ -34,6 +34,7 @@ struct WalkStat {
   unsigned long long inter_a;    // interactions of those walked groups that the
                                  // tree's first (reference) walk also took
   unsigned long long inter_ref;  // the same groups' interactions in that walk
+  unsigned long long entries;    // list entries of the walked groups
   long long tick;                // block steps: the walk's step ends at this tick
   uint32_t kmax, pad;            // block steps: finest occupied level of that step
 };
@@ -83,7 +84,7 @@ struct Layout {
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
-      off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves;
+      off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
@@ -143,6 +144,7 @@ struct Ptrs {
   uint4 *ilist;         // internal cells in cell order, so level by level (istart):
                         // (cell, first child, children, particles)
   uint2 *leaves;        // leaves in particle order: (cell, first particle)
+  uint32_t *scan;       // tile sums of the row scans
 };
 
 Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
@@ -262,9 +264,11 @@ void launch_rk2_correct(int64_t n, double *x, double *y, double *z, float *vx, f
 // inv[perm[s]] = s
 void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
-// exclusive scan of rows[r][0 .. len) for r < nrows, row totals to totals[r]
+// exclusive scan of rows[r][0 .. len) for r < nrows, row totals to totals[r];
+// tsum: scan_scratch_words(len, nrows) words of scratch
 void launch_scan_rows(uint32_t *rows, uint32_t len, int nrows, uint32_t *totals,
-                      hipStream_t st);
+                      uint32_t *tsum, hipStream_t st);
+int64_t scan_scratch_words(int64_t len, int nrows);
 
 // sc->wstat of the walk just finished (queued: order[0 .. nqueue), else all)
 // record: this walk is the tree's reference walk (its first with the
