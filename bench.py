@@ -199,6 +199,78 @@ def restore(snap, nb):
     return nb.State(**d)
 
 
+def run_batch(args):
+    """The batched workload: 64 independent clusters (Plummer or King W0 = 6,
+    N_k = 2^(10 + 8 u_k), G = M = scale = 1), eps = dt = 2^-7, global KDK steps
+    with the tree rebuilt every `rebuild` steps (2 unless given), one HIP
+    graph per step kind replayed per step, one sort, tree and persistent walk
+    for all systems per step; list tile, wavefronts per compute unit and
+    group size from the autotuner (JSON cache keyed by device, size and
+    workload)."""
+    import torch
+
+    import nbody_inputs as I
+    import paper_1811_02761_amd as nb
+    from paper_1811_02761_amd import autotune
+
+    log("generating 64 clusters seed %d" % args.seed)
+    ps = I.cluster_batch(64, args.seed)
+    off = np.concatenate([[0], np.cumsum([p.n for p in ps])]).astype(np.int64)
+    pos = np.concatenate([p.pos for p in ps])
+    vel = np.concatenate([p.vel for p in ps])
+    mass = np.concatenate([p.mass for p in ps])
+    n = int(mass.shape[0])
+    eps = dt = 2.0 ** -7
+    base = nb.Params(eps=eps, delta_acc=args.delta)
+    p32 = pos.astype(np.float32)
+    t0 = time.perf_counter()
+    params, table, hit = autotune.autotune_cached(
+        p32[:, 0], p32[:, 1], p32[:, 2], mass.astype(np.float32), base, "batch64-plummer-king",
+        systems=off, reps=2)
+    t_tune = time.perf_counter() - t0
+    log("autotuner (%s, %.1f s): list_tile %d, waves_per_cu %d, group_max %d"
+        % ("cache hit" if hit else "measured", t_tune, params.list_tile, params.waves_per_cu,
+           params.group_max))
+    rebuild = args.rebuild or 2
+    ctx = nb.Context(params, n_max=n)
+    ctx.set_systems(off)
+    st = nb.State.from_numpy(pos, vel, mass, dt=dt, rebuild_interval=rebuild)
+    ctx.timing(True)  # (the captured steps then count their interactions)
+    ctx.step_graph(st, max(args.warmup, 1))
+    ctx.sync()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    log("timing %d graph-replayed steps, n=%d in 64 systems, rebuild every %d"
+        % (args.steps, n, rebuild))
+    t0 = time.perf_counter()
+    ctx.step_graph(st, args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s = ctx.stats()
+    sec = (t1 - t0) / args.steps
+    inter = s["interactions_sum"] / args.steps
+    log("s/step %.4g, %.3g interactions/step, %.3g interactions/s"
+        % (sec, inter, inter / sec))
+    rec = {
+        "metric": "s/step of a batch of 64 independent clusters (graph-replayed KDK steps)",
+        "value": sec, "unit": "s/step", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 clusters (Plummer or King W0=6, N_k = 2^(10+8u), seed %d), "
+                               "n=%d, eps=2^-7, dt=2^-7, delta_acc=2^%d, global KDK, rebuild "
+                               "every %d, one graph per step kind"
+                               % (args.seed, n, round(np.log2(args.delta)), rebuild),
+                   "n": n, "systems": 64, "list_tile": params.list_tile,
+                   "waves_per_cu": params.waves_per_cu, "group_max": params.group_max},
+        "interactions_per_step": inter,
+        "interactions_per_s": inter / sec,
+        "autotune": {"cache_hit": hit, "seconds": t_tune,
+                     "table": table if table is not None else None},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +299,9 @@ def main():
                     help="queue order of the headline run: 0 plain (Morton), 1 size-based, "
                          "2 learned (needs --learn-steps > 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="the batched workload instead: 64 clusters, graph-replayed steps "
+                         "(use --seed 4)")
     ap.add_argument("--learn-steps", type=int, default=300,
                     help="Adam steps of the cost model for the plain-vs-learned walks (0: skip)")
     args = ap.parse_args()
@@ -241,6 +316,9 @@ def main():
     import paper_1811_02761_amd as nb
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.batch:
+        run_batch(args)
+        return
     log("generating galaxy n=%d seed=%d" % (args.n, args.seed))
     gal = I.galaxy(args.n, args.seed)
     m32 = gal.mass.astype(np.float32)

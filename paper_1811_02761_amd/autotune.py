@@ -10,8 +10,20 @@ from __future__ import annotations
 
 import dataclasses
 import hashlib
+import json
+import math
+import os
 
 from . import Context, Params
+
+CACHE_ENV = "NBODY_AUTOTUNE_CACHE"
+
+
+def cache_path() -> str:
+    """The autotuner's JSON cache: $NBODY_AUTOTUNE_CACHE, else
+    ~/.cache/paper_1811_02761_amd/autotune.json."""
+    return os.environ.get(CACHE_ENV) or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_1811_02761_amd", "autotune.json")
 
 
 def _acc_digest(out) -> str:
@@ -70,3 +82,45 @@ def autotune(x, y, z, m, params: Params, *, systems=None, a_old=None, reps: int 
                                group_max=r["group_max"],
                                leaf_max=min(params.leaf_max, r["group_max"]))
     return best, table
+
+
+def cache_key(n: int, config: str) -> str:
+    """Device name, size bucket (nearest power of two of n) and workload."""
+    import torch
+    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    return "%s|n=2^%d|%s" % (dev, int(round(math.log2(max(int(n), 1)))), config)
+
+
+def autotune_cached(x, y, z, m, params: Params, config: str, *, systems=None, a_old=None,
+                    path: str | None = None, **kw):
+    """autotune() through the JSON cache: returns (Params, table or None,
+    hit). A hit takes the stored list tile, wavefronts per compute unit and
+    group size; a miss measures and stores them."""
+    path = path or cache_path()
+    n = len(x) if not hasattr(x, "numel") else x.numel()
+    key = cache_key(n, config)
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except (OSError, ValueError):
+        db = {}
+    if key in db:
+        r = db[key]
+        best = dataclasses.replace(params, list_tile=int(r["list_tile"]),
+                                   waves_per_cu=int(r["waves_per_cu"]),
+                                   group_max=int(r["group_max"]),
+                                   leaf_max=min(params.leaf_max, int(r["group_max"])))
+        return best, None, True
+    best, table = autotune(x, y, z, m, params, systems=systems, a_old=a_old, **kw)
+    db[key] = {"list_tile": best.list_tile, "waves_per_cu": best.waves_per_cu,
+               "group_max": best.group_max,
+               "walk_ms": min(r["walk_ms"] for r in table)}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return best, table, False

@@ -171,3 +171,77 @@ def test_autotuner_picks_a_measured_configuration(nb, torch):
         if r["group_max"] == best.group_max:
             outs[(r["list_tile"], r["waves_per_cu"])] = r["acc_digest"]
     assert len(set(outs.values())) == 1
+
+
+def test_batch_graph_steps_match_oracle_per_system(nb, torch, orc):
+    """Graph-replayed KDK steps of a batch, one step per call on one context,
+    each checked against the oracle's step from the same state with the force
+    of the oracle's batch tree kept since the last rebuild (rebuild every 2
+    steps): positions bit for bit, the kept tree's keys, lists and hashes
+    exactly, and per system the accelerations under the tree-parity rule
+    (A_i within the system)."""
+    ps, off, _, _, _, _ = _batch(6, 14, 8.0, 11.5)
+    pos = np.concatenate([p.pos for p in ps])
+    vel = np.concatenate([p.vel for p in ps])
+    mass = np.concatenate([p.mass for p in ps])
+    m = mass.astype(np.float32)
+    n, dt, eps, dacc, interval = mass.shape[0], 2.0 ** -7, 2.0 ** -7, 2.0 ** -9, 2
+    params = nb.Params(eps=eps, delta_acc=dacc, checks=1)
+    ctx = nb.Context(params, n_max=n)
+    ctx.set_systems(off)
+    st = nb.State.from_numpy(pos, vel, mass, dt=dt, rebuild_interval=interval)
+    ctx.step_graph(st, 0)  # the first force evaluation, eagerly
+    ctx.sync()
+    topo = pos.astype(np.float32)
+    get = lambda *ts: np.stack([t.cpu().numpy() for t in ts], 1)  # noqa: E731
+    rebuilds = ctx.stats()["rebuilds"]
+    for s in range(5):
+        X, V, A = get(st.x, st.y, st.z), get(st.vx, st.vy, st.vz), get(st.ax, st.ay, st.az)
+        ctx.step_graph(st, 1)
+        ctx.sync()
+        stats = ctx.stats()
+        rebuilt = stats["rebuilds"] > rebuilds
+        rebuilds = stats["rebuilds"]
+        last = {}
+
+        def force(p32):
+            nonlocal topo
+            if rebuilt:
+                topo = p32.copy()
+            last["r"] = orc.tree_forces(*p32.T, m, a_old=A, eps=eps, delta_acc=dacc,
+                                        leaf_max=params.leaf_max, group_max=params.group_max,
+                                        group_merge=params.group_merge,
+                                        topo=tuple(topo.T), systems=off)
+            return last["r"].acc.astype(np.float32)
+
+        Xo, Vo, Ao = orc.kdk_step(X, V, A, m, dt, force)
+        r = last["r"]
+        gx, ga = get(st.x, st.y, st.z), get(st.ax, st.ay, st.az)
+        _say("batch graph step %d rebuilt %s" % (s, rebuilt))
+        np.testing.assert_array_equal(gx, Xo)
+        np.testing.assert_array_equal(ctx.export(nb.X.KEYS).cpu().numpy(), r.keys_sorted)
+        np.testing.assert_array_equal(ctx.export(nb.X.GENTRIES).cpu().numpy().astype(np.int64),
+                                      r.gentries)
+        np.testing.assert_array_equal(ctx.export(nb.X.GHASH).cpu().numpy(), r.ghash)
+        for k in range(len(ps)):
+            a, b = off[k], off[k + 1]
+            _, Aabs = orc.direct(Xo[a:b].astype(np.float32).astype(np.float64), m[a:b], eps=eps,
+                                 want_aabs=True)
+            d = np.linalg.norm(ga[a:b].astype(np.float64) - r.acc[a:b], axis=1)
+            assert (d / Aabs).max() <= 1e-5, (k, (d / Aabs).max())
+            e = d / np.linalg.norm(r.acc[a:b], axis=1)
+            assert np.percentile(e, 99.9) <= 1e-5, (k, np.percentile(e, 99.9))
+    assert rebuilds >= 2
+
+
+def test_autotuner_cache_round_trip(nb, torch, tmp_path):
+    from paper_1811_02761_amd import autotune
+
+    ps, off, x, y, z, m = _batch(8, 15, 9.0, 11.0)
+    path = str(tmp_path / "tune.json")
+    kw = dict(systems=off, reps=1, tiles=(128, 256), waves=(32,), group_max=(64,))
+    b1, t1, hit1 = autotune.autotune_cached(x, y, z, m, nb.Params(), "test", path=path, **kw)
+    b2, t2, hit2 = autotune.autotune_cached(x, y, z, m, nb.Params(), "test", path=path, **kw)
+    assert not hit1 and hit2 and t1 is not None and t2 is None
+    assert (b1.list_tile, b1.waves_per_cu, b1.group_max) == \
+        (b2.list_tile, b2.waves_per_cu, b2.group_max)
