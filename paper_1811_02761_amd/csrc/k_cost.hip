@@ -6,8 +6,10 @@
 // 2^-40) with h half the diagonal of the members' box; log2 of its mass minus
 // three times the previous feature (a density); log2(1 + the members' mean
 // list length from their last walk). The last one is kept per particle in
-// caller order, so it survives tree rebuilds. The target is log2 of the
-// group's interactions (members x list entries).
+// caller order and cleared at every rebuild (0 = not walked on the current
+// tree): a length measured on an aged tree overstates the work on a fresh
+// one. The target is log2 of the group's interactions (members x list
+// entries).
 //
 // The order never changes the results: a group's list and its summation
 // order depend on the group alone.

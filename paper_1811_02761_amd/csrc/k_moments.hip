@@ -13,12 +13,17 @@
 //     order; a wavefront's 64 leaves are contiguous, so their particles are
 //     staged in LDS with coalesced loads): sums, com, b2, q.
 //  2. internal sums, deepest level first, over the build's per-level lists of
-//     internal cells (the children's sums must be final): one launch per
-//     level (the same count of grid-wide synchronisations as the paper's
-//     calcNode, App. A), or one persistent launch with a lock-free grid
+//     internal cells (the children's sums must be final). Planned from the
+//     per-level counts of the latest tree the host has seen: a level with
+//     more than kNarrowCells internal cells gets a launch of its own (the
+//     grid-wide synchronisation of the paper's calcNode, App. A); a run of
+//     consecutive levels with fewer runs in one workgroup, with workgroup
+//     barriers between its levels. Without counts: one launch per level. Or
+//     (a selectable variant) one persistent launch with a lock-free grid
 //     barrier between levels (Xiao and Feng 2010, the method GOTHIC uses).
-//  3. b2 of internal cells. A cell of at most 64 particles: one lane loops
-//     over them. A bigger cell: a pass over the sorted particles, every
+//  3. b2 of internal cells. A cell of at most 64 particles: a half
+//     wavefront, two particles per lane at most. A bigger cell: a pass over
+//     the sorted particles, every
 //     particle meeting each of its big cells. The level-l cell of sorted
 //     particle i is found without parent links: cells are numbered by level,
 //     then by first particle, so its index is the level's offset plus the
@@ -492,21 +497,10 @@ __global__ __launch_bounds__(256) void k_mom_q(const DevScalars *__restrict__ sc
 }
 
 namespace {
-// Workgroups of the persistent phase-2 launch: as many as can be resident
-// at once (every workgroup must run concurrently for the barrier), at most
-// kBarSlots.
-int grid_blocks(int num_cu) {
-  static int per_cu = -1;
-  if (per_cu < 0) {
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_mom_levels_grid, 256, 0) !=
-            hipSuccess ||
-        b < 1)
-      b = 1;
-    per_cu = b;
-  }
-  return std::min(std::max(num_cu, 1) * per_cu, kBarSlots);
-}
+// Workgroups of the persistent phase-2 launch: one per compute unit (all
+// resident at once, as the barrier needs; fewer arrivals for workgroup 0 to
+// poll than a fully occupied grid), at most kBarSlots.
+int grid_blocks(int num_cu) { return std::min(std::max(num_cu, 1), kBarSlots); }
 }  // namespace
 
 void launch_moments(int64_t n, float G, const Ptrs &P, const Layout &L, int mode,
