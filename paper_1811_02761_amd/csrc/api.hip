@@ -84,11 +84,33 @@ struct nbody_ctx {
   hipEvent_t ev_istart = nullptr;
   bool istart_pending = false, have_cells = false;
   uint32_t level_cells[kMaxLevel] = {};
+  // block steps inside one nbody_step call keep the state in key order in
+  // set ko of the key-ordered arrays (-1: not in such a call)
+  int ko = -1;
 };
 
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Set c of the key-ordered block-step state for n particles.
+KoSet ko_set(const Ptrs &P, int c, int64_t n) {
+  KoSet k;
+  k.x = P.kpos[c];
+  k.y = k.x + n;
+  k.z = k.y + n;
+  k.vx = P.kvel[c];
+  k.vy = k.vx + n;
+  k.vz = k.vy + n;
+  k.ax = P.kacc[c];
+  k.ay = k.ax + n;
+  k.az = k.ay + n;
+  k.m = P.kmass[c];
+  k.pt = P.kpt[c];
+  k.lv = P.klv[c];
+  k.asort = c == 0 ? P.asort : P.kasort;
+  return k;
+}
 
 int device_cu_count(int *dev_out) {
   int dev = 0;
@@ -169,7 +191,7 @@ nbody_status status_from_bits(int32_t b) {
 
 namespace nb {
 
-Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
+Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) {
   Layout L{};  // offsets not taken below stay 0 (caught by carve_complete)
   L.n_max = n;
   L.cell_cap = n + cdiv(21 * n, p.leaf_max + 1) + 2;
@@ -249,6 +271,18 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu) {
   // the largest row scan: the build's level rows, or the internal-cell blocks
   L.off_scan = take(4 * (size_t)std::max(scan_scratch_words(L.build_blocks, kLevels + 1),
                                          scan_scratch_words(cdiv(L.cell_cap, 256), 1)));
+  // key-ordered block-step state, two sets (none without stepping: the
+  // pointers then share one empty offset and are never used)
+  const size_t K = stepping ? N : 0;
+  for (int c = 0; c < 2; ++c) {
+    L.off_kpos[c] = take(24 * K);
+    L.off_kvel[c] = take(12 * K);
+    L.off_kacc[c] = take(12 * K);
+    L.off_kmass[c] = take(4 * K);
+    L.off_kpt[c] = take(4 * K);
+    L.off_klv[c] = take(K);
+  }
+  L.off_kasort = take(16 * K);
   L.total = o;
   return L;
 }
@@ -323,6 +357,15 @@ Ptrs carve(void *base, const Layout &L) {
   P.ilist = reinterpret_cast<uint4 *>(b + L.off_ilist);
   P.leaves = reinterpret_cast<uint2 *>(b + L.off_leaves);
   P.scan = reinterpret_cast<uint32_t *>(b + L.off_scan);
+  for (int c = 0; c < 2; ++c) {
+    P.kpos[c] = reinterpret_cast<double *>(b + L.off_kpos[c]);
+    P.kvel[c] = reinterpret_cast<float *>(b + L.off_kvel[c]);
+    P.kacc[c] = reinterpret_cast<float *>(b + L.off_kacc[c]);
+    P.kmass[c] = reinterpret_cast<float *>(b + L.off_kmass[c]);
+    P.kpt[c] = reinterpret_cast<uint32_t *>(b + L.off_kpt[c]);
+    P.klv[c] = reinterpret_cast<int8_t *>(b + L.off_klv[c]);
+  }
+  P.kasort = reinterpret_cast<float4 *>(b + L.off_kasort);
   return P;
 }
 
@@ -552,9 +595,12 @@ Coords records(const float *x32) { return Coords{x32, x32 + 1, x32 + 2, x32 + 3,
 nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   const Ptrs &P = ctx->P;
   if (ctx->sys_r > 0 && n != ctx->sys_n) return NBODY_EINVAL;  // not the configured batch
+  // key-ordered block steps: c holds the drifted positions in the old key
+  // order, so the sort's values are old slots; the state is permuted below
+  const bool ko = ctx->ko >= 0;
   // a mirror of the old tree's key order is carried over to the new one
-  const bool remap = ctx->asort_src && ctx->asort_epoch == ctx->epoch && ctx->have_tree &&
-                     ctx->n == n;
+  const bool remap = !ko && ctx->asort_src && ctx->asort_epoch == ctx->epoch &&
+                     ctx->have_tree && ctx->n == n;
   ctx->epoch++;
   ctx->excess_ms = 0.0;
   ctx->growth = 1.0;
@@ -570,12 +616,19 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   uint32_t *pm;
   launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
               &ks, &pm);
+  if (ko) launch_ko_ties(n, ks, pm, P.kpt[ctx->ko], ctx->st);  // equal keys: caller order
   launch_gather(c, pm, n, P.xyzm, ctx->st);
   if (remap) {  // (before inv is rewritten; okeys is free outside a walk)
     launch_asort_remap(pm, P.inv, n, P.asort, reinterpret_cast<float4 *>(P.okeys), ctx->st);
     ctx->asort_epoch = ctx->epoch;
   }
-  launch_invert(pm, n, P.inv, ctx->st);
+  if (ko) {
+    const int c1 = 1 - ctx->ko;
+    launch_ko_permute(n, pm, ko_set(P, ctx->ko, n), ko_set(P, c1, n), ctx->st);
+    ctx->ko = c1;
+  } else {
+    launch_invert(pm, n, P.inv, ctx->st);
+  }
   launch_build(ks, n, ctx->p.leaf_max, ctx->p.group_max, ctx->p.group_merge, ctx->nsys,
                ctx->sys_r, P, ctx->L, ctx->st);
   const uint32_t *plan = moment_plan(ctx);
@@ -593,7 +646,8 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   // previous list lengths are those of walks on the current tree (0: none yet)
   launch_fill_u32(P.plast, 0u, n, ctx->st);
   ctx->keys = ks;
-  ctx->perm = pm;
+  // the tree's permutation (sorted position -> caller index)
+  ctx->perm = ko ? P.kpt[ctx->ko] : pm;
   ctx->n = n;
   ctx->have_tree = true;
   return hip_status();
@@ -637,11 +691,17 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
                      float *phi = nullptr) {
   const bool boot = axo == nullptr;
   const Ptrs &P = ctx->P;
-  const bool mirrored = axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
-  launch_group_bounds(axo, ayo, azo, mirrored ? P.asort : nullptr, ctx->perm, ctx->n,
+  // key-ordered block steps: inputs and outputs are in key order, and the
+  // state's own asort is the mirror
+  const bool ko = ctx->ko >= 0;
+  const bool mirrored =
+      ko ? axo != nullptr : axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
+  const float4 *mirror = ko ? ko_set(P, ctx->ko, ctx->n).asort : P.asort;
+  const uint32_t *out_perm = ko ? nullptr : ctx->perm;
+  launch_group_bounds(axo, ayo, azo, mirrored ? mirror : nullptr, ctx->perm, ctx->n,
                       ctx->p.delta_acc, queued, P, ctx->st);
   // outputs over the mirrored array keep the mirror; other writes to it end it
-  const bool keep_mirror = mirrored && ax == axo;
+  const bool keep_mirror = !ko && mirrored && ax == axo;
   if (!keep_mirror && ax && ax == ctx->asort_src) ctx->asort_src = nullptr;
   // the learned order needs an installed model; until then the queue is plain
   const int mode = (ctx->order == 2 && ctx->mlp_hidden == 0) ? 0 : ctx->order;
@@ -655,9 +715,9 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
   wc.asort_out = keep_mirror;
   wc.phi = phi;
   const int sp = span_begin(ctx, 1);
-  launch_walk(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
+  launch_walk(wc, out_perm, ctx->n, ax, ay, az, P, ctx->st);
   span_end(ctx, sp);
-  launch_walk_retry(wc, ctx->perm, ctx->n, ax, ay, az, P, ctx->st);
+  launch_walk_retry(wc, out_perm, ctx->n, ax, ay, az, P, ctx->st);
   // the tree's first walk with the acceleration criterion is its reference
   const bool record = !boot && ctx->mac_walks == 0;
   if (!boot) ctx->mac_walks++;
@@ -898,15 +958,17 @@ namespace {
 nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   nbody_status s;
   const int64_t n = st->n;
-  float *x32 = ctx->P.x32;
-  float *tx = ctx->P.atmp, *ty = tx + n, *tz = tx + 2 * n;
+  const Ptrs &P = ctx->P;
+  float *x32 = P.x32;
+  float *tx = P.atmp, *ty = tx + n, *tz = tx + 2 * n;
   const BlockCfg bc{st->dt, st->eta, ctx->p.eps, st->level_min, st->level_max};
-  DevScalars *sc = ctx->P.sc;
+  DevScalars *sc = P.sc;
+  const unsigned to_f32_grid = (unsigned)std::min<int64_t>(cdiv(n, 1024), 8192);
   launch_blk_setup((long long)st->tick, sc, ctx->st);
+  bool force_rebuild = false;
   if (!st->have_acc) {
-    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>(cdiv(n, 1024), 8192)),
-                       dim3(256), 0, ctx->st, n, st->x, st->y, st->z, st->m,
-                       reinterpret_cast<float4 *>(x32));
+    hipLaunchKernelGGL(k_to_f32, dim3(to_f32_grid), dim3(256), 0, ctx->st, n, st->x, st->y,
+                       st->z, st->m, reinterpret_cast<float4 *>(x32));
     if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
     if ((s = do_calc(ctx, nullptr, nullptr, nullptr, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
@@ -917,31 +979,63 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     ctx->since_rebuild = 0;
   } else {
     launch_blk_scan(n, st->level, bc, sc, ctx->st);
-  }
-  for (int32_t k = 0; k < n_steps; ++k) {
-    bool rebuild = st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
-                                            : rebuild_due(ctx, 64);
-    if (ctx->n != n) rebuild = true;
-    launch_blk_begin(sc, ctx->st);
-    launch_blk_open_drift(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay,
-                          st->az, st->level, st->dt, sc, x32, drift_out(ctx, st, rebuild),
-                          ctx->st);
-    if (rebuild) {
+    if (!ctx->have_tree || ctx->n != n) {
+      // a tree of these particles gives the key order; the first step
+      // rebuilds it from the drifted positions
+      hipLaunchKernelGGL(k_to_f32, dim3(to_f32_grid), dim3(256), 0, ctx->st, n, st->x, st->y,
+                         st->z, st->m, reinterpret_cast<float4 *>(x32));
       if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
+      force_rebuild = true;
+    }
+  }
+  // the rest of the call works on the state in the tree's key order
+  {
+    const KoSet k0 = ko_set(P, 0, n);
+    if (ctx->perm != k0.pt &&
+        hipMemcpyAsync(k0.pt, ctx->perm, 4 * (size_t)n, hipMemcpyDeviceToDevice, ctx->st) !=
+            hipSuccess)
+      return NBODY_EHIP;
+    launch_ko_gather(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
+                     st->m, st->level, k0, ctx->st);
+    ctx->ko = 0;
+    ctx->perm = k0.pt;
+  }
+  s = NBODY_OK;
+  for (int32_t k = 0; k < n_steps && s == NBODY_OK; ++k) {
+    const bool rebuild = force_rebuild ||
+                         (st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
+                                                   : rebuild_due(ctx, 64));
+    force_rebuild = false;
+    KoSet K = ko_set(P, ctx->ko, n);
+    launch_blk_begin(sc, ctx->st);
+    // a rebuild reads the drifted positions as (x, y, z, m) records in the
+    // old key order; a refit reads them as the tree's sorted positions
+    const SortedOut so = rebuild ? SortedOut{nullptr, nullptr, K.m}
+                                 : SortedOut{P.xyzm, nullptr, K.m};
+    launch_blk_open_drift(n, K.x, K.y, K.z, K.vx, K.vy, K.vz, K.ax, K.ay, K.az, K.lv, st->dt,
+                          sc, x32, so, ctx->st);
+    if (rebuild) {
+      if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) break;
+      K = ko_set(P, ctx->ko, n);  // the state now lies in the other set
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
     } else {
-      if ((s = do_refit_sorted(ctx)) != NBODY_OK) return s;
+      if ((s = do_refit_sorted(ctx)) != NBODY_OK) break;
     }
-    launch_blk_queue(n, st->level, ctx->perm, ctx->P, ctx->st);
-    ensure_asort(ctx, st);
-    if ((s = do_calc(ctx, st->ax, st->ay, st->az, tx, ty, tz, true)) != NBODY_OK) return s;
-    launch_blk_close(n, st->ax, st->ay, st->az, tx, ty, tz, st->vx, st->vy, st->vz,
-                     st->level, bc, ctx->P.asort, ctx->P.inv, sc, ctx->st);
+    launch_blk_queue(n, K.lv, nullptr, P, ctx->st);
+    if ((s = do_calc(ctx, K.ax, K.ay, K.az, tx, ty, tz, true)) != NBODY_OK) break;
+    launch_blk_close(n, K.ax, K.ay, K.az, tx, ty, tz, K.vx, K.vy, K.vz, K.lv, bc, K.asort,
+                     nullptr, sc, ctx->st);
     ctx->since_rebuild++;
     ctx->steps++;
-    if ((s = hip_status()) != NBODY_OK) return s;
+    s = hip_status();
   }
+  // back to caller order; the tree keeps its permutation and gets its inverse
+  launch_ko_scatter(n, ko_set(P, ctx->ko, n), st->x, st->y, st->z, st->vx, st->vy, st->vz,
+                    st->ax, st->ay, st->az, st->level, ctx->st);
+  launch_invert(ctx->perm, n, P.inv, ctx->st);
+  ctx->ko = -1;
+  if (s != NBODY_OK) return s;
   long long tick = 0;
   if (hipMemcpyAsync(&tick, &sc->tick, sizeof(tick), hipMemcpyDeviceToHost, ctx->st) !=
           hipSuccess ||
@@ -1486,7 +1580,7 @@ nbody_status nbody_tree_forces_noalloc(const nbody_params *p, void *hip_stream, 
   q.walk_split = 1;
   q.order = 0;
   q.calcnode_sync = kCalcNodeLevels;
-  const Layout L = make_layout(q, n, cu);
+  const Layout L = make_layout(q, n, cu, false);
   if (L.total > kStaticScratchBytes) return NBODY_ENOMEM;
   nbody_ctx c;  // on the stack: no events, no pinned memory
   c.p = q;

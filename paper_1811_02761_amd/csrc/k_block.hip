@@ -192,7 +192,9 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_mark(int64_t n,
   for (int64_t s0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s0 < n; s0 += 4 * stride) {
     uint32_t p[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) p[u] = s0 + u * stride < n ? perm[s0 + u * stride] : 0u;
+    for (int u = 0; u < 4; ++u)  // no perm: levels in key order
+      p[u] = s0 + u * stride < n ? (perm ? perm[s0 + u * stride] : (uint32_t)(s0 + u * stride))
+                                 : 0u;
     int8_t lv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) lv[u] = s0 + u * stride < n ? level[p[u]] : (int8_t)0;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
         vx[i] = vx[i] + kx;
         vy[i] = vy[i] + ky;
         vz[i] = vz[i] + kz;
-        asort[inv[i]] =
+        asort[inv ? inv[i] : (uint32_t)i] =  // no inv: the state is in key order
             make_float4(a0, a1, a2, sqrt_rn(__builtin_fmaf(a2, a2, __builtin_fmaf(a1, a1, a0 * a0))));
         k = level_of(a0, a1, a2, t, lo);
         level[i] = (int8_t)k;

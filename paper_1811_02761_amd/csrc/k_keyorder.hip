@@ -1,0 +1,149 @@
+// k_keyorder.hip -- the block-step state in key order within one nbody_step
+// call.
+//
+// The state arrays the caller passes are in caller order, while every
+// per-particle pass of a block step (drift, the queue flags, the walk's
+// results, the closing kick, the group bounds) works on the tree's sorted
+// order. Inside one call the state is therefore kept in key order: gathered
+// once on entry, permuted at every rebuild from the old key order into the
+// new one (particles move little between rebuilds, so these reads are nearly
+// in order), and scattered back to caller order on exit. The arithmetic of a
+// step does not depend on where a particle's values are stored, so results
+// are bit-identical to a caller-order step.
+#include "nbody_internal.h"
+
+namespace nb {
+
+namespace {
+int ko_grid(int64_t n) {
+  int64_t g = cdiv(n, 256 * 4);
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+}  // namespace
+
+__device__ __forceinline__ float4 with_norm(float x, float y, float z) {
+  return make_float4(x, y, z, sqrt_rn(__builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x))));
+}
+
+__global__ __launch_bounds__(256) void k_ko_gather(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const float *__restrict__ vx, const float *__restrict__ vy,
+    const float *__restrict__ vz, const float *__restrict__ ax, const float *__restrict__ ay,
+    const float *__restrict__ az, const float *__restrict__ m,
+    const int8_t *__restrict__ level, KoSet k) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = k.pt[s];
+    k.x[s] = x[o];
+    k.y[s] = y[o];
+    k.z[s] = z[o];
+    k.vx[s] = vx[o];
+    k.vy[s] = vy[o];
+    k.vz[s] = vz[o];
+    const float a0 = ax[o], a1 = ay[o], a2 = az[o];
+    k.ax[s] = a0;
+    k.ay[s] = a1;
+    k.az[s] = a2;
+    k.asort[s] = with_norm(a0, a1, a2);
+    k.m[s] = m[o];
+    k.lv[s] = level[o];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ko_scatter(int64_t n, KoSet k, double *__restrict__ x,
+                                                    double *__restrict__ y, double *__restrict__ z,
+                                                    float *__restrict__ vx, float *__restrict__ vy,
+                                                    float *__restrict__ vz, float *__restrict__ ax,
+                                                    float *__restrict__ ay, float *__restrict__ az,
+                                                    int8_t *__restrict__ level) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = k.pt[s];
+    x[o] = k.x[s];
+    y[o] = k.y[s];
+    z[o] = k.z[s];
+    vx[o] = k.vx[s];
+    vy[o] = k.vy[s];
+    vz[o] = k.vz[s];
+    ax[o] = k.ax[s];
+    ay[o] = k.ay[s];
+    az[o] = k.az[s];
+    level[o] = k.lv[s];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ko_permute(int64_t n, const uint32_t *__restrict__ perm,
+                                                    KoSet f, KoSet t) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = perm[s];
+    t.x[s] = f.x[o];
+    t.y[s] = f.y[o];
+    t.z[s] = f.z[o];
+    t.vx[s] = f.vx[o];
+    t.vy[s] = f.vy[o];
+    t.vz[s] = f.vz[o];
+    t.ax[s] = f.ax[o];
+    t.ay[s] = f.ay[o];
+    t.az[s] = f.az[o];
+    t.asort[s] = f.asort[o];
+    t.m[s] = f.m[o];
+    t.pt[s] = f.pt[o];
+    t.lv[s] = f.lv[o];
+  }
+}
+
+// One thread per sorted position; the first position of a run of equal keys
+// sorts the run's values by caller index (insertion sort: runs are the
+// particles that share one 63-bit key, usually none or a few; a run of L
+// costs its thread O(L^2)).
+__global__ __launch_bounds__(256) void k_ko_ties(int64_t n, const uint64_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ vals,
+                                                 const uint32_t *__restrict__ pt_old) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j + 1 < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[j];
+    if (keys[j + 1] != k || (j > 0 && keys[j - 1] == k)) continue;
+    int64_t e = j + 2;
+    while (e < n && keys[e] == k) ++e;
+    for (int64_t a = j + 1; a < e; ++a) {
+      const uint32_t v = vals[a];
+      const uint32_t c = pt_old[v];
+      int64_t b = a;
+      while (b > j && pt_old[vals[b - 1]] > c) {
+        vals[b] = vals[b - 1];
+        --b;
+      }
+      vals[b] = v;
+    }
+  }
+}
+
+void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
+                      const float *vx, const float *vy, const float *vz, const float *ax,
+                      const float *ay, const float *az, const float *m, const int8_t *level,
+                      const KoSet &k, hipStream_t st) {
+  hipLaunchKernelGGL(k_ko_gather, dim3(ko_grid(n)), dim3(256), 0, st, n, x, y, z, vx, vy, vz, ax,
+                     ay, az, m, level, k);
+}
+
+void launch_ko_scatter(int64_t n, const KoSet &k, double *x, double *y, double *z, float *vx,
+                       float *vy, float *vz, float *ax, float *ay, float *az, int8_t *level,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_ko_scatter, dim3(ko_grid(n)), dim3(256), 0, st, n, k, x, y, z, vx, vy,
+                     vz, ax, ay, az, level);
+}
+
+void launch_ko_permute(int64_t n, const uint32_t *perm, const KoSet &from, const KoSet &to,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_ko_permute, dim3(ko_grid(n)), dim3(256), 0, st, n, perm, from, to);
+}
+
+void launch_ko_ties(int64_t n, const uint64_t *keys, uint32_t *vals, const uint32_t *pt_old,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_ko_ties, dim3(ko_grid(n)), dim3(256), 0, st, n, keys, vals, pt_old);
+}
+
+}  // namespace nb

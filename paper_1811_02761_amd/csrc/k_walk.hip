@@ -279,12 +279,13 @@ __device__ __forceinline__ void stream_reduce1(uint32_t Wd, float &sw) {
 }
 
 // The results of member `lane` (< gc) of group (gb, gc): G times the sum, in
-// caller order, and with |a| into the key-ordered mirror when there is one.
+// caller order (in key order without perm), and with |a| into the
+// key-ordered mirror when there is one.
 __device__ __forceinline__ void store_group_result(const WalkArgs &a, uint32_t gb, uint32_t gc,
                                                    uint32_t lane, float sx, float sy,
                                                    float sz) {
   if (lane < gc) {  // lane == member here (stream 0)
-    const uint32_t o = a.perm[gb + lane];
+    const uint32_t o = a.perm ? a.perm[gb + lane] : gb + lane;
     const float gx = a.G * sx, gy = a.G * sy, gz = a.G * sz;
     a.ax[o] = gx;
     a.ay[o] = gy;
@@ -491,7 +492,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
         stream_reduce1(Wd, sw);
         if (lane < gc) {
           const float self = pi.w * __builtin_amdgcn_rsqf(a.eps2);
-          a.phi[a.perm[gb + lane]] = a.G * (sw + self);
+          a.phi[a.perm ? a.perm[gb + lane] : gb + lane] = a.G * (sw + self);
         }
       }
     } else if constexpr (!kComp && !kPot) {

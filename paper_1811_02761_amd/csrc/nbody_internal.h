@@ -85,6 +85,8 @@ struct Layout {
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
       off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan;
+  size_t off_kpos[2], off_kvel[2], off_kacc[2], off_kmass[2], off_kpt[2], off_klv[2],
+      off_kasort;
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
@@ -145,9 +147,19 @@ struct Ptrs {
                         // (cell, first child, children, particles)
   uint2 *leaves;        // leaves in particle order: (cell, first particle)
   uint32_t *scan;       // tile sums of the row scans
+  // block steps inside one nbody_step call: the state in key order, two sets
+  // (a rebuild permutes set c into set 1 - c); asort of set 1 is kasort
+  double *kpos[2];      // [3][n] x, y, z (FP64)
+  float *kvel[2];       // [3][n] vx, vy, vz
+  float *kacc[2];       // [3][n] ax, ay, az of the last step
+  float *kmass[2];      // [n]
+  uint32_t *kpt[2];     // [n] caller index of each sorted slot
+  int8_t *klv[2];       // [n] block-step levels
+  float4 *kasort;       // second buffer of asort
 };
 
-Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu);
+// stepping = false: no room for the key-ordered step state (tree forces only)
+Layout make_layout(const nbody_params &p, int64_t n_max, int num_cu, bool stepping = true);
 Ptrs carve(void *base, const Layout &L);
 
 // FP32 coordinates and masses of particle i at x[i * stride], y[i * stride],
@@ -245,7 +257,7 @@ __device__ __forceinline__ void store_position(int64_t i, int64_t n, float fx, f
   (void)n;
   const float4 r = make_float4(fx, fy, fz, so.m[i]);
   if (so.xyzm)
-    so.xyzm[so.inv[i]] = r;
+    so.xyzm[so.inv ? so.inv[i] : (uint32_t)i] = r;  // no inv: the state is in key order
   else
     reinterpret_cast<float4 *>(x32)[i] = r;  // (x, y, z, m) records in caller order
 }
@@ -263,6 +275,33 @@ void launch_rk2_correct(int64_t n, double *x, double *y, double *z, float *vx, f
                         float *x32, SortedOut so, hipStream_t st);
 // inv[perm[s]] = s
 void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t st);
+
+// One set of the key-ordered block-step state (slot s = sorted position).
+struct KoSet {
+  double *x, *y, *z;
+  float *vx, *vy, *vz, *ax, *ay, *az, *m;
+  uint32_t *pt;   // caller index of slot s
+  int8_t *lv;
+  float4 *asort;  // (a, |a|) of slot s
+};
+// Caller order -> key order: slot s takes caller index pt[s] (pt filled by
+// the caller); asort from the accelerations.
+void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
+                      const float *vx, const float *vy, const float *vz, const float *ax,
+                      const float *ay, const float *az, const float *m, const int8_t *level,
+                      const KoSet &k, hipStream_t st);
+// Key order -> caller order (positions, velocities, accelerations, levels).
+void launch_ko_scatter(int64_t n, const KoSet &k, double *x, double *y, double *z, float *vx,
+                       float *vy, float *vz, float *ax, float *ay, float *az, int8_t *level,
+                       hipStream_t st);
+// After a rebuild: slot s of the new order is slot perm[s] of the old one.
+void launch_ko_permute(int64_t n, const uint32_t *perm, const KoSet &from, const KoSet &to,
+                       hipStream_t st);
+// Equal keys in caller order: the sort of a key-ordered state keeps equal
+// keys in their old slot order; each run of equal keys is reordered by the
+// caller index pt_old[vals[j]].
+void launch_ko_ties(int64_t n, const uint64_t *keys, uint32_t *vals, const uint32_t *pt_old,
+                    hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 // exclusive scan of rows[r][0 .. len) for r < nrows, row totals to totals[r];
 // tsum: scan_scratch_words(len, nrows) words of scratch
