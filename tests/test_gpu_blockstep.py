@@ -163,3 +163,34 @@ def test_bad_levels_are_reported(nb, torch):
         ctx.step(st, 1)
         ctx.sync()
     assert ei.value.code == nb.NBODY_ECORRUPT
+
+
+def test_equal_keys_keep_caller_order_across_calls(nb, torch, orc):
+    # Particles in identical pairs share one 63-bit key. Within one call the
+    # block steps sort the state from the tree's previous key order (slot s
+    # holds the caller index the tree's permutation names). After the caller
+    # permutes its arrays between two calls, about half of the pairs reach
+    # that sort in the opposite of caller order. The tree must still break
+    # every tie by caller index, exactly as the oracle's stable sort does.
+    n0 = 1500
+    p = I.plummer(n0, 9)
+    pos, vel, mass = (np.concatenate([a, a]) for a in (p.pos, p.vel, p.mass))
+    n = 2 * n0
+    params = nb.Params(eps=2.0 ** -7, delta_acc=2.0 ** -9)
+    st = nb.State.from_numpy(pos, vel, mass, dt=2.0 ** -4, rebuild_interval=1,
+                             block_steps=True, eta=0.025)
+    ctx = nb.Context(params, n_max=n)
+    ctx.step(st, 2)
+    ctx.sync()
+    idx = torch.as_tensor(np.random.default_rng(4).permutation(n), device=st.x.device)
+    for t in (st.x, st.y, st.z, st.vx, st.vy, st.vz, st.m, st.ax, st.ay, st.az, st.level):
+        t.copy_(t[idx])
+    ctx.step(st, 2)
+    ctx.sync()
+    x, y, z = (t.cpu().numpy().astype(np.float32) for t in (st.x, st.y, st.z))
+    k, _ = orc.keys(x, y, z)
+    perm, ks = orc.sort(k)
+    # the twins stayed identical: every pair is still a tie
+    assert int((ks[1:] == ks[:-1]).sum()) >= n0
+    np.testing.assert_array_equal(ctx.export(nb.X.KEYS).cpu().numpy(), ks)
+    np.testing.assert_array_equal(ctx.export(nb.X.PERM).cpu().numpy().astype(np.int64), perm)
