@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define NBODY_ABI_VERSION 3
+#define NBODY_ABI_VERSION 4
 
 typedef int32_t nbody_status;
 enum {
@@ -446,6 +446,16 @@ nbody_status nbody_set_cost_model(nbody_ctx *ctx, int32_t hidden, const float *w
 
 /* Change the queue order (0, 1 or 2, as nbody_params.order). */
 nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order);
+
+/* Where nbody_step keeps the state during block steps (Sec. 1 and 4.1: every
+ * per-particle pass of a step runs over the tree's sorted order). layout 1:
+ * in the tree's key order, gathered from the caller's arrays on entry,
+ * permuted at each rebuild and scattered back on exit; 2: in the caller's
+ * arrays, reached through the tree's permutation; 0 (the default): 1 for
+ * calls of at least 8 steps, else 2 (the gather and scatter cost about what
+ * eight steps save). Results are bit-identical in every layout. EINVAL for
+ * other values. */
+nbody_status nbody_set_step_layout(nbody_ctx *ctx, int32_t layout);
 
 /* ---- Batches of independent systems in one tree (one sort, one build,
  * one persistent walk for all of them). offsets (host, n_sys + 1 entries,

@@ -90,10 +90,11 @@ HEADER_FUNCTIONS = [
     "nbody_mlp_nparams", "nbody_mlp_forward", "nbody_mlp_grad", "nbody_mlp_adam",
     "nbody_costmodel_train", "nbody_set_cost_model", "nbody_set_order", "nbody_set_systems",
     "nbody_step_graph", "nbody_direct64", "nbody_calc_acc_pot", "nbody_tree_forces_noalloc",
+    "nbody_set_step_layout",
 ]
 
 _lib = None
-ABI_VERSION = 3  # NBODY_ABI_VERSION of include/nbody.h
+ABI_VERSION = 4  # NBODY_ABI_VERSION of include/nbody.h
 
 
 def lib():
@@ -139,6 +140,7 @@ def lib():
         L.nbody_costmodel_train.argtypes = [vp, i32, vp, i64, vp, vp, i32, f32, vp]
         L.nbody_set_cost_model.argtypes = [vp, i32, vp]
         L.nbody_set_order.argtypes = [vp, i32]
+        L.nbody_set_step_layout.argtypes = [vp, i32]
         L.nbody_set_systems.argtypes = [vp, i32, vp]
         L.nbody_step_graph.argtypes = [vp, C.POINTER(_State), i32]
         L.nbody_calc_acc_pot.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -428,6 +430,10 @@ class Context:
 
     def set_order(self, order: int):
         _check(lib().nbody_set_order(self._h, int(order)), "nbody_set_order")
+
+    def set_step_layout(self, layout: int):
+        """Block-step state during nbody_step: 0 automatic, 1 key order, 2 caller order."""
+        _check(lib().nbody_set_step_layout(self._h, int(layout)), "nbody_set_step_layout")
 
     def set_systems(self, offsets):
         """Several independent systems in one tree: caller-order offsets (S + 1)."""

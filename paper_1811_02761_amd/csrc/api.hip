@@ -85,8 +85,10 @@ struct nbody_ctx {
   bool istart_pending = false, have_cells = false;
   uint32_t level_cells[kMaxLevel] = {};
   // block steps inside one nbody_step call keep the state in key order in
-  // set ko of the key-ordered arrays (-1: not in such a call)
+  // set ko of the key-ordered arrays (-1: not in such a call); step_layout:
+  // 0 key order for calls of kKeyedSteps steps or more, 1 always, 2 never
   int ko = -1;
+  int step_layout = 0;
 };
 
 namespace {
@@ -955,6 +957,12 @@ nbody_status nbody_calc_acc_pot(nbody_ctx *ctx, const float *axo, const float *a
 namespace {
 
 // Block steps (level != NULL): see nbody.h and k_block.hip.
+// Block steps. With the key-ordered layout (calls of many steps) the state
+// is gathered into the tree's key order on entry, permuted at every rebuild
+// and scattered back on exit: every per-particle pass of a step then reads
+// and writes in order. The gather and scatter cost about as much as eight
+// steps save, so shorter calls work on the caller-order arrays directly,
+// through the tree's permutation. Both give the same bits.
 nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   nbody_status s;
   const int64_t n = st->n;
@@ -963,6 +971,7 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   float *tx = P.atmp, *ty = tx + n, *tz = tx + 2 * n;
   const BlockCfg bc{st->dt, st->eta, ctx->p.eps, st->level_min, st->level_max};
   DevScalars *sc = P.sc;
+  const bool keyed = ctx->step_layout == 1 || (ctx->step_layout == 0 && n_steps >= kKeyedSteps);
   const unsigned to_f32_grid = (unsigned)std::min<int64_t>(cdiv(n, 1024), 8192);
   launch_blk_setup((long long)st->tick, sc, ctx->st);
   bool force_rebuild = false;
@@ -980,16 +989,18 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   } else {
     launch_blk_scan(n, st->level, bc, sc, ctx->st);
     if (!ctx->have_tree || ctx->n != n) {
-      // a tree of these particles gives the key order; the first step
-      // rebuilds it from the drifted positions
-      hipLaunchKernelGGL(k_to_f32, dim3(to_f32_grid), dim3(256), 0, ctx->st, n, st->x, st->y,
-                         st->z, st->m, reinterpret_cast<float4 *>(x32));
-      if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
+      // no tree of these particles: the first step builds one from the
+      // drifted positions (the key-ordered layout needs one for its order
+      // before that)
       force_rebuild = true;
+      if (keyed) {
+        hipLaunchKernelGGL(k_to_f32, dim3(to_f32_grid), dim3(256), 0, ctx->st, n, st->x, st->y,
+                           st->z, st->m, reinterpret_cast<float4 *>(x32));
+        if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) return s;
+      }
     }
   }
-  // the rest of the call works on the state in the tree's key order
-  {
+  if (keyed) {
     const KoSet k0 = ko_set(P, 0, n);
     if (ctx->perm != k0.pt &&
         hipMemcpyAsync(k0.pt, ctx->perm, 4 * (size_t)n, hipMemcpyDeviceToDevice, ctx->st) !=
@@ -1000,41 +1011,48 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     ctx->ko = 0;
     ctx->perm = k0.pt;
   }
+  // the state arrays of the current layout
+  KoSet S{st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, st->m,
+          nullptr, st->level, P.asort};
   s = NBODY_OK;
   for (int32_t k = 0; k < n_steps && s == NBODY_OK; ++k) {
     const bool rebuild = force_rebuild ||
                          (st->rebuild_interval > 0 ? ctx->since_rebuild >= st->rebuild_interval
                                                    : rebuild_due(ctx, 64));
     force_rebuild = false;
-    KoSet K = ko_set(P, ctx->ko, n);
+    if (keyed) S = ko_set(P, ctx->ko, n);
     launch_blk_begin(sc, ctx->st);
-    // a rebuild reads the drifted positions as (x, y, z, m) records in the
-    // old key order; a refit reads them as the tree's sorted positions
-    const SortedOut so = rebuild ? SortedOut{nullptr, nullptr, K.m}
-                                 : SortedOut{P.xyzm, nullptr, K.m};
-    launch_blk_open_drift(n, K.x, K.y, K.z, K.vx, K.vy, K.vz, K.ax, K.ay, K.az, K.lv, st->dt,
+    // key order: a rebuild reads the drifted positions as (x, y, z, m)
+    // records in the old key order, a refit as the tree's sorted positions
+    const SortedOut so = !keyed ? drift_out(ctx, st, rebuild)
+                         : rebuild ? SortedOut{nullptr, nullptr, S.m}
+                                   : SortedOut{P.xyzm, nullptr, S.m};
+    launch_blk_open_drift(n, S.x, S.y, S.z, S.vx, S.vy, S.vz, S.ax, S.ay, S.az, S.lv, st->dt,
                           sc, x32, so, ctx->st);
     if (rebuild) {
       if ((s = do_build(ctx, n, records(x32))) != NBODY_OK) break;
-      K = ko_set(P, ctx->ko, n);  // the state now lies in the other set
+      if (keyed) S = ko_set(P, ctx->ko, n);  // the state now lies in the other set
       ctx->rebuilds++;
       ctx->since_rebuild = 0;
     } else {
       if ((s = do_refit_sorted(ctx)) != NBODY_OK) break;
     }
-    launch_blk_queue(n, K.lv, nullptr, P, ctx->st);
-    if ((s = do_calc(ctx, K.ax, K.ay, K.az, tx, ty, tz, true)) != NBODY_OK) break;
-    launch_blk_close(n, K.ax, K.ay, K.az, tx, ty, tz, K.vx, K.vy, K.vz, K.lv, bc, K.asort,
-                     nullptr, sc, ctx->st);
+    launch_blk_queue(n, S.lv, keyed ? nullptr : ctx->perm, P, ctx->st);
+    if (!keyed) ensure_asort(ctx, st);
+    if ((s = do_calc(ctx, S.ax, S.ay, S.az, tx, ty, tz, true)) != NBODY_OK) break;
+    launch_blk_close(n, S.ax, S.ay, S.az, tx, ty, tz, S.vx, S.vy, S.vz, S.lv, bc, S.asort,
+                     keyed ? nullptr : P.inv, sc, ctx->st);
     ctx->since_rebuild++;
     ctx->steps++;
     s = hip_status();
   }
-  // back to caller order; the tree keeps its permutation and gets its inverse
-  launch_ko_scatter(n, ko_set(P, ctx->ko, n), st->x, st->y, st->z, st->vx, st->vy, st->vz,
-                    st->ax, st->ay, st->az, st->level, ctx->st);
-  launch_invert(ctx->perm, n, P.inv, ctx->st);
-  ctx->ko = -1;
+  if (keyed) {
+    // back to caller order; the tree keeps its permutation and gets its inverse
+    launch_ko_scatter(n, ko_set(P, ctx->ko, n), st->x, st->y, st->z, st->vx, st->vy, st->vz,
+                      st->ax, st->ay, st->az, st->level, ctx->st);
+    launch_invert(ctx->perm, n, P.inv, ctx->st);
+    ctx->ko = -1;
+  }
   if (s != NBODY_OK) return s;
   long long tick = 0;
   if (hipMemcpyAsync(&tick, &sc->tick, sizeof(tick), hipMemcpyDeviceToHost, ctx->st) !=
@@ -1383,6 +1401,13 @@ nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order) {
   if (!ctx) return NBODY_EINVAL;
   if (order < 0 || order > 2) return NBODY_EINVAL;
   ctx->order = order;
+  return NBODY_OK;
+}
+
+nbody_status nbody_set_step_layout(nbody_ctx *ctx, int32_t layout) {
+  if (!ctx) return NBODY_EINVAL;
+  if (layout < 0 || layout > 2) return NBODY_EINVAL;
+  ctx->step_layout = layout;
   return NBODY_OK;
 }
 

@@ -276,6 +276,11 @@ void launch_rk2_correct(int64_t n, double *x, double *y, double *z, float *vx, f
 // inv[perm[s]] = s
 void launch_invert(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t st);
 
+// Block-step calls of at least this many steps keep the state in key order
+// (the gather on entry and the scatter on exit cost about what eight steps
+// save).
+constexpr int32_t kKeyedSteps = 8;
+
 // One set of the key-ordered block-step state (slot s = sorted position).
 struct KoSet {
   double *x, *y, *z;

@@ -38,7 +38,7 @@ def test_header_symbols_exported(nb):
 
 def test_abi_version_and_strings(nb):
     L = nb.lib()
-    assert L.nbody_abi_version() == nb.ABI_VERSION == 3
+    assert L.nbody_abi_version() == nb.ABI_VERSION == 4
     for code in range(0, -8, -1):
         assert len(L.nbody_strerror(code)) > 0
 
@@ -70,6 +70,7 @@ def test_null_context_is_rejected(nb):
     assert L.nbody_sync(None) == nb.NBODY_EINVAL
     assert L.nbody_build_tree(None, 10, None, None, None, None) == nb.NBODY_EINVAL
     assert L.nbody_calc_acc(None, None, None, None, None, None, None) == nb.NBODY_EINVAL
+    assert L.nbody_set_step_layout(None, 1) == nb.NBODY_EINVAL
     L.nbody_destroy(None)
 
 

@@ -180,6 +180,7 @@ def test_equal_keys_keep_caller_order_across_calls(nb, torch, orc):
     st = nb.State.from_numpy(pos, vel, mass, dt=2.0 ** -4, rebuild_interval=1,
                              block_steps=True, eta=0.025)
     ctx = nb.Context(params, n_max=n)
+    ctx.set_step_layout(1)  # key order for these short calls too
     ctx.step(st, 2)
     ctx.sync()
     idx = torch.as_tensor(np.random.default_rng(4).permutation(n), device=st.x.device)
@@ -194,3 +195,28 @@ def test_equal_keys_keep_caller_order_across_calls(nb, torch, orc):
     assert int((ks[1:] == ks[:-1]).sum()) >= n0
     np.testing.assert_array_equal(ctx.export(nb.X.KEYS).cpu().numpy(), ks)
     np.testing.assert_array_equal(ctx.export(nb.X.PERM).cpu().numpy().astype(np.int64), perm)
+
+
+def test_layouts_bit_identical(nb, torch):
+    # the state kept in key order, or in the caller's arrays, during a call of
+    # block steps: the same arithmetic, so the same bits (rebuild every 3rd
+    # step: the automatic rule depends on timings)
+    p = I.galaxy(20000, 8)
+    params = nb.Params(eps=2.0 ** -7, delta_acc=2.0 ** -9)
+    out = []
+    for layout in (1, 2, 0):
+        st = nb.State.from_numpy(p.pos, p.vel, p.mass, dt=2.0 ** -3, rebuild_interval=3,
+                                 block_steps=True, eta=0.025)
+        ctx = nb.Context(params, n_max=len(p.mass))
+        ctx.set_step_layout(layout)
+        ctx.step(st, 9)
+        ctx.step(st, 3)
+        ctx.sync()
+        out.append(([t.cpu().numpy() for t in (st.x, st.y, st.z, st.vx, st.vy, st.vz, st.ax,
+                                                st.ay, st.az, st.level)],
+                    ctx.export(nb.X.PERM).cpu().numpy(), st.tick, ctx.stats()["rebuilds"]))
+    for o in out[1:]:
+        for a, b in zip(out[0][0], o[0]):
+            np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(out[0][1], o[1])
+        assert out[0][2:] == o[2:]

@@ -16,9 +16,11 @@ particles under the tree-parity rule (max |da|/A <= 1e-5 and the 99.9th
 percentile of |da|/|a| <= 1e-5); levels exactly except where |a| is within
 1e-5 of a level threshold.
 
-A second context runs the same steps in ONE nbody_step call (the form the
-benchmark times, where the key-ordered mirror is remapped across rebuilds
-inside the call) and must end bit-identical to the step-by-step run.
+Block steps alternate the state's layout during a call (the tree's key
+order, or the caller's arrays through the tree's permutation) from step to
+step. A second context runs the same steps in ONE nbody_step call in key
+order (the form the benchmark times) and must end bit-identical to the
+step-by-step run.
 """
 import sys
 
@@ -109,6 +111,8 @@ def test_multistep_matches_oracle(nb, torch, orc, case, interval):
     for s in range(nsteps):
         X, V, A, LV = _get(st)
         tick = st.tick
+        # block steps alternate the state's layout (key order, caller order)
+        ctx.set_step_layout(1 + s % 2)
         ctx.step(st, 1)
         ctx.sync()
         stats = ctx.stats()
@@ -167,6 +171,7 @@ def test_multistep_matches_oracle(nb, torch, orc, case, interval):
         assert seen_rebuild == (nsteps - 1) // interval
     # the same steps in one call on a fresh context: bit-identical end state
     ctx2 = nb.Context(params, n_max=n)
+    ctx2.set_step_layout(1)  # key order whatever the step count
     st2 = fresh_state()
     ctx2.step(st2, 0)
     ctx2.step(st2, nsteps)
