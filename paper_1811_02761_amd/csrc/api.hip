@@ -89,6 +89,10 @@ struct nbody_ctx {
   // 0 key order for calls of kKeyedSteps steps or more, 1 always, 2 never
   int ko = -1;
   int step_layout = 0;
+  // the set a key-ordered call left its state in, kept while the tree
+  // (epoch) stays and the caller's arrays hash as they did on exit
+  int ko_keep = -1;
+  int64_t ko_keep_epoch = -1;
 };
 
 namespace {
@@ -110,7 +114,7 @@ KoSet ko_set(const Ptrs &P, int c, int64_t n) {
   k.m = P.kmass[c];
   k.pt = P.kpt[c];
   k.lv = P.klv[c];
-  k.asort = c == 0 ? P.asort : P.kasort;
+  k.asort = P.kasort[c];
   return k;
 }
 
@@ -284,7 +288,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) 
     L.off_kpt[c] = take(4 * K);
     L.off_klv[c] = take(K);
   }
-  L.off_kasort = take(16 * K);
+  L.off_kasort[0] = take(16 * K);
+  L.off_kasort[1] = take(16 * K);
   L.total = o;
   return L;
 }
@@ -367,7 +372,7 @@ Ptrs carve(void *base, const Layout &L) {
     P.kpt[c] = reinterpret_cast<uint32_t *>(b + L.off_kpt[c]);
     P.klv[c] = reinterpret_cast<int8_t *>(b + L.off_klv[c]);
   }
-  P.kasort = reinterpret_cast<float4 *>(b + L.off_kasort);
+  for (int c = 0; c < 2; ++c) P.kasort[c] = reinterpret_cast<float4 *>(b + L.off_kasort[c]);
   return P;
 }
 
@@ -1001,16 +1006,25 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     }
   }
   if (keyed) {
-    const KoSet k0 = ko_set(P, 0, n);
+    // the set the last key-ordered call left is still this state's if the
+    // tree is the same and the caller's arrays hash as they did on its exit
+    const bool kept = ctx->ko_keep >= 0 && ctx->ko_keep_epoch == ctx->epoch && ctx->n == n &&
+                      ctx->perm == P.kpt[ctx->ko_keep];
+    const int c = kept ? ctx->ko_keep : 0;
+    const KoSet k0 = ko_set(P, c, n);
     if (ctx->perm != k0.pt &&
         hipMemcpyAsync(k0.pt, ctx->perm, 4 * (size_t)n, hipMemcpyDeviceToDevice, ctx->st) !=
             hipSuccess)
       return NBODY_EHIP;
+    if (kept)
+      launch_ko_hash(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
+                     st->m, st->level, &sc->ko_hash[1], ctx->st);
     launch_ko_gather(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
-                     st->m, st->level, k0, ctx->st);
-    ctx->ko = 0;
+                     st->m, st->level, k0, kept ? sc->ko_hash : nullptr, ctx->st);
+    ctx->ko = c;
     ctx->perm = k0.pt;
   }
+  ctx->ko_keep = -1;
   // the state arrays of the current layout
   KoSet S{st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, st->m,
           nullptr, st->level, P.asort};
@@ -1051,6 +1065,12 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     launch_ko_scatter(n, ko_set(P, ctx->ko, n), st->x, st->y, st->z, st->vx, st->vy, st->vz,
                       st->ax, st->ay, st->az, st->level, ctx->st);
     launch_invert(ctx->perm, n, P.inv, ctx->st);
+    if (s == NBODY_OK) {
+      launch_ko_hash(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
+                     st->m, st->level, &sc->ko_hash[0], ctx->st);
+      ctx->ko_keep = ctx->ko;
+      ctx->ko_keep_epoch = ctx->epoch;
+    }
     ctx->ko = -1;
   }
   if (s != NBODY_OK) return s;

@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void k_ko_gather(
     const double *__restrict__ z, const float *__restrict__ vx, const float *__restrict__ vy,
     const float *__restrict__ vz, const float *__restrict__ ax, const float *__restrict__ ay,
     const float *__restrict__ az, const float *__restrict__ m,
-    const int8_t *__restrict__ level, KoSet k) {
+    const int8_t *__restrict__ level, KoSet k, const unsigned long long *__restrict__ skip) {
+  if (skip && skip[0] == skip[1]) return;  // the set holds this state already
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t o = k.pt[s];
@@ -95,6 +96,51 @@ __global__ __launch_bounds__(256) void k_ko_permute(int64_t n, const uint32_t *_
   }
 }
 
+namespace {
+// splitmix64's finaliser (Steele, Lea and Flood 2014).
+__device__ __forceinline__ unsigned long long state_mix(unsigned long long x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ unsigned long long pack2(float a, float b) {
+  return (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
+}
+}  // namespace
+
+// Sum over particles of a chained mix of the particle's index and the bit
+// patterns of its values (order-free, so the result does not depend on the
+// launch); one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_ko_hash(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const float *__restrict__ vx, const float *__restrict__ vy,
+    const float *__restrict__ vz, const float *__restrict__ ax, const float *__restrict__ ay,
+    const float *__restrict__ az, const float *__restrict__ m,
+    const int8_t *__restrict__ level, unsigned long long *__restrict__ out) {
+  __shared__ unsigned long long part[4];
+  unsigned long long acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long h = state_mix((unsigned long long)i * 0x9e3779b97f4a7c15ull);
+    h = state_mix(h ^ (unsigned long long)__double_as_longlong(x[i]));
+    h = state_mix(h ^ (unsigned long long)__double_as_longlong(y[i]));
+    h = state_mix(h ^ (unsigned long long)__double_as_longlong(z[i]));
+    h = state_mix(h ^ pack2(vx[i], vy[i]));
+    h = state_mix(h ^ pack2(vz[i], ax[i]));
+    h = state_mix(h ^ pack2(ay[i], az[i]));
+    h = state_mix(h ^ ((unsigned long long)__float_as_uint(m[i]) |
+                   ((unsigned long long)(uint8_t)level[i] << 32)));
+    acc += h;
+  }
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
 // One thread per sorted position; the first position of a run of equal keys
 // sorts the run's values by caller index (insertion sort: runs are the
 // particles that share one 63-bit key, usually none or a few; a run of L
@@ -124,9 +170,20 @@ __global__ __launch_bounds__(256) void k_ko_ties(int64_t n, const uint64_t *__re
 void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
                       const float *vx, const float *vy, const float *vz, const float *ax,
                       const float *ay, const float *az, const float *m, const int8_t *level,
-                      const KoSet &k, hipStream_t st) {
+                      const KoSet &k, const unsigned long long *skip, hipStream_t st) {
   hipLaunchKernelGGL(k_ko_gather, dim3(ko_grid(n)), dim3(256), 0, st, n, x, y, z, vx, vy, vz, ax,
-                     ay, az, m, level, k);
+                     ay, az, m, level, k, skip);
+}
+
+void launch_ko_hash(int64_t n, const double *x, const double *y, const double *z,
+                    const float *vx, const float *vy, const float *vz, const float *ax,
+                    const float *ay, const float *az, const float *m, const int8_t *level,
+                    unsigned long long *out, hipStream_t st) {
+  launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 2, st);
+  int64_t g = cdiv(n, 256 * 8);
+  g = std::min<int64_t>(std::max<int64_t>(g, 1), 1024);
+  hipLaunchKernelGGL(k_ko_hash, dim3((unsigned)g), dim3(256), 0, st, n, x, y, z, vx, vy, vz, ax,
+                     ay, az, m, level, out);
 }
 
 void launch_ko_scatter(int64_t n, const KoSet &k, double *x, double *y, double *z, float *vx,

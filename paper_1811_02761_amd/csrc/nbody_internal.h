@@ -65,6 +65,10 @@ struct DevScalars {
   unsigned long long bar_epoch;  // launches of the grid-barrier calcNode so far
   uint32_t istart[kLevels + 1];  // internal cells of level l: ilist[istart[l] .. istart[l + 1])
   uint32_t nleaf;          // leaves of the current tree
+  uint32_t pad2;
+  // hashes of the caller's block-step state: [0] when a key-ordered call
+  // scattered it back, [1] on entry to the next such call
+  unsigned long long ko_hash[2];
 };
 
 // Offsets of the workspace, all 256-byte aligned.
@@ -86,7 +90,7 @@ struct Layout {
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
       off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan;
   size_t off_kpos[2], off_kvel[2], off_kacc[2], off_kmass[2], off_kpt[2], off_klv[2],
-      off_kasort;
+      off_kasort[2];
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
@@ -148,14 +152,14 @@ struct Ptrs {
   uint2 *leaves;        // leaves in particle order: (cell, first particle)
   uint32_t *scan;       // tile sums of the row scans
   // block steps inside one nbody_step call: the state in key order, two sets
-  // (a rebuild permutes set c into set 1 - c); asort of set 1 is kasort
+  // (a rebuild permutes set c into set 1 - c)
   double *kpos[2];      // [3][n] x, y, z (FP64)
   float *kvel[2];       // [3][n] vx, vy, vz
   float *kacc[2];       // [3][n] ax, ay, az of the last step
   float *kmass[2];      // [n]
   uint32_t *kpt[2];     // [n] caller index of each sorted slot
   int8_t *klv[2];       // [n] block-step levels
-  float4 *kasort;       // second buffer of asort
+  float4 *kasort[2];    // [n] (a, |a|) of each slot
 };
 
 // stepping = false: no room for the key-ordered step state (tree forces only)
@@ -290,11 +294,20 @@ struct KoSet {
   float4 *asort;  // (a, |a|) of slot s
 };
 // Caller order -> key order: slot s takes caller index pt[s] (pt filled by
-// the caller); asort from the accelerations.
+// the caller); asort from the accelerations. With skip (two hashes on the
+// device), nothing is done when skip[0] == skip[1].
 void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
                       const float *vx, const float *vy, const float *vz, const float *ax,
                       const float *ay, const float *az, const float *m, const int8_t *level,
-                      const KoSet &k, hipStream_t st);
+                      const KoSet &k, const unsigned long long *skip, hipStream_t st);
+// *out = a 64-bit hash of the caller-order block-step state (positions,
+// velocities, accelerations, masses, levels, by index; a sum of per-particle
+// mixes, so any change of a value changes it except with probability about
+// 2^-64). Clears *out first.
+void launch_ko_hash(int64_t n, const double *x, const double *y, const double *z,
+                    const float *vx, const float *vy, const float *vz, const float *ax,
+                    const float *ay, const float *az, const float *m, const int8_t *level,
+                    unsigned long long *out, hipStream_t st);
 // Key order -> caller order (positions, velocities, accelerations, levels).
 void launch_ko_scatter(int64_t n, const KoSet &k, double *x, double *y, double *z, float *vx,
                        float *vy, float *vz, float *ax, float *ay, float *az, int8_t *level,

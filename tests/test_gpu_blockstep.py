@@ -200,7 +200,9 @@ def test_equal_keys_keep_caller_order_across_calls(nb, torch, orc):
 def test_layouts_bit_identical(nb, torch):
     # the state kept in key order, or in the caller's arrays, during a call of
     # block steps: the same arithmetic, so the same bits (rebuild every 3rd
-    # step: the automatic rule depends on timings)
+    # step: the automatic rule depends on timings). Between calls the caller
+    # changes two values in place (a key-ordered context must notice and
+    # gather again), then leaves the state alone (it may reuse its own copy).
     p = I.galaxy(20000, 8)
     params = nb.Params(eps=2.0 ** -7, delta_acc=2.0 ** -9)
     out = []
@@ -210,7 +212,10 @@ def test_layouts_bit_identical(nb, torch):
         ctx = nb.Context(params, n_max=len(p.mass))
         ctx.set_step_layout(layout)
         ctx.step(st, 9)
+        st.vx[17] += 2.0 ** -10
+        st.ay[4321] *= 0.5
         ctx.step(st, 3)
+        ctx.step(st, 8)
         ctx.sync()
         out.append(([t.cpu().numpy() for t in (st.x, st.y, st.z, st.vx, st.vy, st.vz, st.ax,
                                                 st.ay, st.az, st.level)],
