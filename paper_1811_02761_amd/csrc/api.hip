@@ -114,7 +114,6 @@ KoSet ko_set(const Ptrs &P, int c, int64_t n) {
   k.m = P.kmass[c];
   k.pt = P.kpt[c];
   k.lv = P.klv[c];
-  k.asort = P.kasort[c];
   return k;
 }
 
@@ -288,8 +287,6 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) 
     L.off_kpt[c] = take(4 * K);
     L.off_klv[c] = take(K);
   }
-  L.off_kasort[0] = take(16 * K);
-  L.off_kasort[1] = take(16 * K);
   L.total = o;
   return L;
 }
@@ -372,7 +369,6 @@ Ptrs carve(void *base, const Layout &L) {
     P.kpt[c] = reinterpret_cast<uint32_t *>(b + L.off_kpt[c]);
     P.klv[c] = reinterpret_cast<int8_t *>(b + L.off_klv[c]);
   }
-  for (int c = 0; c < 2; ++c) P.kasort[c] = reinterpret_cast<float4 *>(b + L.off_kasort[c]);
   return P;
 }
 
@@ -698,14 +694,12 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
                      float *phi = nullptr) {
   const bool boot = axo == nullptr;
   const Ptrs &P = ctx->P;
-  // key-ordered block steps: inputs and outputs are in key order, and the
-  // state's own asort is the mirror
+  // key-ordered block steps: inputs and outputs are in key order (read and
+  // written directly, no mirror)
   const bool ko = ctx->ko >= 0;
-  const bool mirrored =
-      ko ? axo != nullptr : axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
-  const float4 *mirror = ko ? ko_set(P, ctx->ko, ctx->n).asort : P.asort;
+  const bool mirrored = !ko && axo && axo == ctx->asort_src && ctx->asort_epoch == ctx->epoch;
   const uint32_t *out_perm = ko ? nullptr : ctx->perm;
-  launch_group_bounds(axo, ayo, azo, mirrored ? mirror : nullptr, ctx->perm, ctx->n,
+  launch_group_bounds(axo, ayo, azo, mirrored ? P.asort : nullptr, out_perm, ctx->n,
                       ctx->p.delta_acc, queued, P, ctx->st);
   // outputs over the mirrored array keep the mirror; other writes to it end it
   const bool keep_mirror = !ko && mirrored && ax == axo;
@@ -1027,7 +1021,7 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   ctx->ko_keep = -1;
   // the state arrays of the current layout
   KoSet S{st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az, st->m,
-          nullptr, st->level, P.asort};
+          nullptr, st->level};
   s = NBODY_OK;
   for (int32_t k = 0; k < n_steps && s == NBODY_OK; ++k) {
     const bool rebuild = force_rebuild ||
@@ -1054,8 +1048,8 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     launch_blk_queue(n, S.lv, keyed ? nullptr : ctx->perm, P, ctx->st);
     if (!keyed) ensure_asort(ctx, st);
     if ((s = do_calc(ctx, S.ax, S.ay, S.az, tx, ty, tz, true)) != NBODY_OK) break;
-    launch_blk_close(n, S.ax, S.ay, S.az, tx, ty, tz, S.vx, S.vy, S.vz, S.lv, bc, S.asort,
-                     keyed ? nullptr : P.inv, sc, ctx->st);
+    launch_blk_close(n, S.ax, S.ay, S.az, tx, ty, tz, S.vx, S.vy, S.vz, S.lv, bc,
+                     keyed ? nullptr : P.asort, P.inv, sc, ctx->st);
     ctx->since_rebuild++;
     ctx->steps++;
     s = hip_status();

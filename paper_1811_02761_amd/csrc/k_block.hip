@@ -307,8 +307,9 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
         vx[i] = vx[i] + kx;
         vy[i] = vy[i] + ky;
         vz[i] = vz[i] + kz;
-        asort[inv ? inv[i] : (uint32_t)i] =  // no inv: the state is in key order
-            make_float4(a0, a1, a2, sqrt_rn(__builtin_fmaf(a2, a2, __builtin_fmaf(a1, a1, a0 * a0))));
+        if (asort)  // the key-ordered mirror of caller-order state
+          asort[inv[i]] = make_float4(
+              a0, a1, a2, sqrt_rn(__builtin_fmaf(a2, a2, __builtin_fmaf(a1, a1, a0 * a0))));
         k = level_of(a0, a1, a2, t, lo);
         level[i] = (int8_t)k;
         ++cnt;

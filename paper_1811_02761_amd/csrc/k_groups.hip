@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_group_bounds(
     if (asort && ok) {  // key-ordered copy of a_old with |a| in w
       amin = asort[b + k].w;
     } else if (axo && ok) {
-      const uint32_t o = perm[b + k];
+      const uint32_t o = perm ? perm[b + k] : b + k;  // no perm: a_old in key order
       const float ax = axo[o], ay = ayo[o], az = azo[o];
       amin = sqrt_rn(__builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
     }

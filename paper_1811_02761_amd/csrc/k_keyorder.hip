@@ -23,10 +23,6 @@ int ko_grid(int64_t n) {
 }
 }  // namespace
 
-__device__ __forceinline__ float4 with_norm(float x, float y, float z) {
-  return make_float4(x, y, z, sqrt_rn(__builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x))));
-}
-
 __global__ __launch_bounds__(256) void k_ko_gather(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const float *__restrict__ vx, const float *__restrict__ vy,
@@ -43,11 +39,9 @@ __global__ __launch_bounds__(256) void k_ko_gather(
     k.vx[s] = vx[o];
     k.vy[s] = vy[o];
     k.vz[s] = vz[o];
-    const float a0 = ax[o], a1 = ay[o], a2 = az[o];
-    k.ax[s] = a0;
-    k.ay[s] = a1;
-    k.az[s] = a2;
-    k.asort[s] = with_norm(a0, a1, a2);
+    k.ax[s] = ax[o];
+    k.ay[s] = ay[o];
+    k.az[s] = az[o];
     k.m[s] = m[o];
     k.lv[s] = level[o];
   }
@@ -89,7 +83,6 @@ __global__ __launch_bounds__(256) void k_ko_permute(int64_t n, const uint32_t *_
     t.ax[s] = f.ax[o];
     t.ay[s] = f.ay[o];
     t.az[s] = f.az[o];
-    t.asort[s] = f.asort[o];
     t.m[s] = f.m[o];
     t.pt[s] = f.pt[o];
     t.lv[s] = f.lv[o];

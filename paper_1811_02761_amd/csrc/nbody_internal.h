@@ -89,8 +89,7 @@ struct Layout {
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
       off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan;
-  size_t off_kpos[2], off_kvel[2], off_kacc[2], off_kmass[2], off_kpt[2], off_klv[2],
-      off_kasort[2];
+  size_t off_kpos[2], off_kvel[2], off_kacc[2], off_kmass[2], off_kpt[2], off_klv[2];
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
   int64_t split_slots = 0;  // queue positions with room for split-walk partial sums
@@ -159,7 +158,6 @@ struct Ptrs {
   float *kmass[2];      // [n]
   uint32_t *kpt[2];     // [n] caller index of each sorted slot
   int8_t *klv[2];       // [n] block-step levels
-  float4 *kasort[2];    // [n] (a, |a|) of each slot
 };
 
 // stepping = false: no room for the key-ordered step state (tree forces only)
@@ -291,10 +289,9 @@ struct KoSet {
   float *vx, *vy, *vz, *ax, *ay, *az, *m;
   uint32_t *pt;   // caller index of slot s
   int8_t *lv;
-  float4 *asort;  // (a, |a|) of slot s
 };
 // Caller order -> key order: slot s takes caller index pt[s] (pt filled by
-// the caller); asort from the accelerations. With skip (two hashes on the
+// the caller). With skip (two hashes on the
 // device), nothing is done when skip[0] == skip[1].
 void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
                       const float *vx, const float *vy, const float *vz, const float *ax,
