@@ -617,8 +617,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   }
   uint64_t *ks;
   uint32_t *pm;
-  launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->L.sort_blocks, ctx->st,
-              &ks, &pm);
+  launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->st, &ks, &pm);
   if (ko) launch_ko_ties(n, ks, pm, P.kpt[ctx->ko], ctx->st);  // equal keys: caller order
   launch_gather(c, pm, n, P.xyzm, ctx->st);
   if (remap) {  // (before inv is rewritten; okeys is free outside a walk)

@@ -177,8 +177,8 @@ void launch_keys(const Coords &c, int64_t n, DevScalars *sc, uint64_t *keys, uin
                  hipStream_t st);
 // returns pointer (A or B) holding the sorted result
 void launch_sort(int64_t n, uint64_t *keysA, uint32_t *valsA, uint64_t *keysB,
-                 uint32_t *valsB, uint32_t *hist, int64_t blocks, hipStream_t st,
-                 uint64_t **keys_out, uint32_t **vals_out);
+                 uint32_t *valsB, uint32_t *hist, hipStream_t st, uint64_t **keys_out,
+                 uint32_t **vals_out);
 void launch_gather(const Coords &c, const uint32_t *perm, int64_t n, float4 *xyzm,
                    hipStream_t st);
 // r > 0: a batch of nsys systems (cells above level r always split, groups
