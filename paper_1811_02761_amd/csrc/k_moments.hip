@@ -105,7 +105,19 @@ __global__ __launch_bounds__(256) void k_mom_leaf(DevScalars *__restrict__ sc, u
   const uint32_t P0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pb);
   const uint32_t P1 = (uint32_t)__builtin_amdgcn_readlane((int)pe, (int)kl);
   const uint32_t span = (P1 > P0 && P1 <= n) ? min(P1 - P0, kLeafStage) : 0u;
-  for (uint32_t t = lane; t < span; t += 64u) stage[w][t] = xyzm[P0 + t];
+  {  // all loads in flight before the LDS stores (a rolled loop waited on each)
+    float4 tmp[kLeafStage / 64];
+#pragma unroll
+    for (uint32_t u = 0; u < kLeafStage / 64; ++u) {
+      const uint32_t t = lane + 64u * u;
+      tmp[u] = t < span ? xyzm[P0 + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kLeafStage / 64; ++u) {
+      const uint32_t t = lane + 64u * u;
+      if (t < span) stage[w][t] = tmp[u];
+    }
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -115,6 +127,7 @@ __global__ __launch_bounds__(256) void k_mom_leaf(DevScalars *__restrict__ sc, u
     return;
   }
   double mm = 0.0, xx = 0.0, yy = 0.0, zz = 0.0;
+#pragma unroll 4
   for (uint32_t p = pb; p < pe; ++p) {
     const float4 q = p - P0 < span ? stage[w][p - P0] : xyzm[p];
     const double m = (double)q.w;  // m x is exact in FP64 (two 24-bit significands)
@@ -125,6 +138,7 @@ __global__ __launch_bounds__(256) void k_mom_leaf(DevScalars *__restrict__ sc, u
   }
   const float3 c = com_of(mm, xx, yy, zz, pb - P0 < span ? stage[w][pb - P0] : xyzm[pb]);
   float bb = 0.0f;
+#pragma unroll 4
   for (uint32_t p = pb; p < pe; ++p) {
     const float d2 = dist2(p - P0 < span ? stage[w][p - P0] : xyzm[p], c.x, c.y, c.z);
     bb = d2 > bb ? d2 : bb;
