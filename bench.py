@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0, help="walk wavefronts per CU (0 = library)")
     ap.add_argument("--tile", type=int, default=0, help="LDS list tile entries (0 = library)")
     ap.add_argument("--frontier", type=int, default=0, help="frontier cells per wave")
+    ap.add_argument("--split", type=int, default=0, choices=(0, 1, 2, 4),
+                    help="wavefronts per group in the walk (0 = by queue length)")
     ap.add_argument("--group-max", type=int, default=64)
     ap.add_argument("--group-merge", type=int, default=1, choices=(0, 1))
     ap.add_argument("--leaf-max", type=int, default=16)
@@ -325,7 +327,8 @@ def main():
     params = nb.Params(eps=args.eps, delta_acc=args.delta, waves_per_cu=args.waves,
                        list_tile=args.tile, frontier_cap=args.frontier,
                        group_max=args.group_max, leaf_max=args.leaf_max,
-                       group_merge=args.group_merge, calcnode_sync=args.calcnode)
+                       group_merge=args.group_merge, calcnode_sync=args.calcnode,
+                       walk_split=args.split)
     block = not args.global_steps
     st = nb.State.from_numpy(gal.pos, gal.vel, gal.mass, dt=args.dt,
                              rebuild_interval=args.rebuild, block_steps=block, eta=args.eta)

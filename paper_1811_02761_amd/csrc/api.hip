@@ -276,6 +276,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) 
   // the largest row scan: the build's level rows, or the internal-cell blocks
   L.off_scan = take(4 * (size_t)std::max(scan_scratch_words(L.build_blocks, kLevels + 1),
                                          scan_scratch_words(cdiv(L.cell_cap, 256), 1)));
+  L.off_longcnt = take(4 * (size_t)L.build_blocks);
+  L.off_longslot = take(4 * (size_t)L.build_blocks * kLevels);
   // key-ordered block-step state, two sets (none without stepping: the
   // pointers then share one empty offset and are never used)
   const size_t K = stepping ? N : 0;
@@ -361,6 +363,8 @@ Ptrs carve(void *base, const Layout &L) {
   P.ilist = reinterpret_cast<uint4 *>(b + L.off_ilist);
   P.leaves = reinterpret_cast<uint2 *>(b + L.off_leaves);
   P.scan = reinterpret_cast<uint32_t *>(b + L.off_scan);
+  P.longcnt = reinterpret_cast<uint32_t *>(b + L.off_longcnt);
+  P.longslot = reinterpret_cast<uint32_t *>(b + L.off_longslot);
   for (int c = 0; c < 2; ++c) {
     P.kpos[c] = reinterpret_cast<double *>(b + L.off_kpos[c]);
     P.kvel[c] = reinterpret_cast<float *>(b + L.off_kvel[c]);

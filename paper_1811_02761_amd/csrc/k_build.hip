@@ -279,7 +279,9 @@ __global__ __launch_bounds__(kB) void k_build_d(
     int32_t *__restrict__ clevel, uint32_t *__restrict__ cpbegin,
     uint32_t *__restrict__ cpcount, int32_t *__restrict__ cfchild,
     int32_t *__restrict__ cnchild, float4 *__restrict__ nodeB,
-    uint32_t *__restrict__ leafof, uint2 *__restrict__ leaves) {
+    uint32_t *__restrict__ leafof, uint2 *__restrict__ leaves,
+    uint32_t *__restrict__ longcnt, uint32_t *__restrict__ longslot) {
+  __shared__ uint32_t s_nlong;  // cells longer than kShort starting in this block
   __shared__ uint32_t wpre[kLevels + 1][kB / 64];  // row kLevels: leaf starts
   __shared__ uint32_t lvl_off[kLevels + 1];
   __shared__ uint64_t bound[kLevels][kChunks];       // bit j: s_{b0+j} <= level (or past n)
@@ -291,6 +293,7 @@ __global__ __launch_bounds__(kB) void k_build_d(
   const bool valid = i < n;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
+  if (threadIdx.x == 0) s_nlong = 0;
   // boundary masks: wave w covers chunks 2w and 2w + 1
   for (int c = 2 * w; c < 2 * w + 2; ++c) {
     const int64_t q = (int64_t)b0 + c * 64 + lane;
@@ -359,6 +362,11 @@ __global__ __launch_bounds__(kB) void k_build_d(
     const int e = first_bit(bound[l], r, r + kShort);
     if (e < 0) {  // longer than kShort: counted by the cooperative pass
       cpcount[idx] = kLongCell;
+      // at most one such cell per level starts in a block of kShort
+      // particles (an earlier one of its level would end inside the block)
+      const uint32_t slot = atomicAdd(&s_nlong, 1u);
+      if (slot < (uint32_t)kLevels) longslot[(size_t)blockIdx.x * kLevels + slot] = idx;
+      else atomicOr(&sc->status, kStCorrupt);
       continue;
     }
     const uint32_t end = b0 + (uint32_t)e;
@@ -379,6 +387,8 @@ __global__ __launch_bounds__(kB) void k_build_d(
       // wB[2] (first child) is written by pass E
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) longcnt[blockIdx.x] = min(s_nlong, (uint32_t)kLevels);
 }
 
 // End of the level-l run from i, searched by the whole wavefront: a round of
@@ -418,28 +428,30 @@ __device__ uint32_t wave_run_end(const uint64_t *__restrict__ K, uint32_t n, uin
   return hi;
 }
 
-// The cells pass D left (count still kLongCell): each wavefront checks 64
-// cells at a time, every nw-th cell (nw wavefronts; the long cells sit
-// together at the top levels, so striding spreads them), and serves the
-// marked ones one after the other, finding the cell's end and, for an
-// internal cell, its children's ends.
+// The cells pass D left (count still kLongCell), listed per build block:
+// wavefront w takes blocks w, w + nw, ... (nw wavefronts; the long cells sit
+// together in the dense regions, so dealing blocks out one at a time spreads
+// them) and serves their cells one after the other, finding the cell's end
+// and, for an internal cell, its number of children.
 __global__ __launch_bounds__(256) void k_build_long(
     const uint64_t *__restrict__ K, uint32_t n, const uint32_t *__restrict__ pinfo,
     const DevScalars *__restrict__ sc, const int32_t *__restrict__ clevel,
     const uint32_t *__restrict__ cpbegin, uint32_t *__restrict__ cpcount,
     int32_t *__restrict__ cfchild, int32_t *__restrict__ cnchild,
-    float4 *__restrict__ nodeB, uint32_t *__restrict__ leafof) {
+    float4 *__restrict__ nodeB, uint32_t *__restrict__ leafof,
+    const uint32_t *__restrict__ longcnt, const uint32_t *__restrict__ longslot,
+    uint32_t nblk) {
   const uint32_t nc = sc->ncell;
   const uint32_t lane = lane_id();
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
   const uint32_t wv = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
                                                      (threadIdx.x >> 6));
-  for (uint64_t b = 0; wv + b * 64u * nw < nc; ++b) {
-    const uint64_t cl = wv + (b * 64u + lane) * nw;
-    uint64_t todo = __ballot(cl < nc && cpcount[cl] == kLongCell);
-    while (todo) {
-      const uint32_t idx = (uint32_t)(wv + (b * 64u + (uint64_t)__builtin_ctzll(todo)) * nw);
-      todo &= todo - 1;
+  for (uint32_t bk = wv; bk < nblk; bk += nw) {
+    const uint32_t cntb = __builtin_amdgcn_readfirstlane(longcnt[bk]);
+    for (uint32_t q = 0; q < cntb; ++q) {
+      const uint32_t idx =
+          __builtin_amdgcn_readfirstlane(longslot[(size_t)bk * kLevels + q]);
+      if (idx >= nc) continue;
       const int l = clevel[idx];
       const uint32_t i = cpbegin[idx];
       const int D = (pinfo[i] >> 5) & 31;
@@ -455,15 +467,19 @@ __global__ __launch_bounds__(256) void k_build_long(
         }
         for (uint32_t p = i + lane; p < end; p += 64) leafof[p] = idx;
       } else {
-        int nch = 0;
-        for (uint32_t j = i; j < end; ++nch) j = wave_run_end(K, n, j, l + 1);
+        // the children: the level-(l+1) cells from the first child (pass D
+        // wrote it) that begin before end (cells of a level are numbered in
+        // particle order, so they follow one another)
+        const uint32_t f = (uint32_t)cfchild[idx];
+        const uint32_t lend = sc->lvl_off[l + 2 <= kLevels ? l + 2 : kLevels];
+        const uint32_t c1 = f + 1u + lane;
+        const bool more = lane < 7u && c1 < lend && cpbegin[c1] < end;
+        const int nch = 1 + (int)__popcll(__ballot(more));
         if (lane == 0) {
           cnchild[idx] = nch;
           wB[3] = (uint32_t)nch;
         }
       }
-      // every lane has read the marker before it is overwritten
-      __builtin_amdgcn_wave_barrier();
       if (lane == 0) cpcount[idx] = cnt;
     }
   }
@@ -690,10 +706,10 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
   hipLaunchKernelGGL(k_build_c, dim3(1), dim3(64), 0, st, totals, P.sc, L.cell_cap);
   hipLaunchKernelGGL(k_build_d, dim3(nblk), dim3(kB), 0, st, P.pinfo, (uint32_t)n, P.lvlblk,
                      nblk, P.sc, L.cell_cap, P.clevel, P.cpbegin, P.cpcount, P.cfchild,
-                     P.cnchild, P.nodeB, P.leafof, P.leaves);
+                     P.cnchild, P.nodeB, P.leafof, P.leaves, P.longcnt, P.longslot);
   hipLaunchKernelGGL(k_build_long, dim3(1024), dim3(256), 0, st, keys, (uint32_t)n, P.pinfo,
                      P.sc, P.clevel, P.cpbegin, P.cpcount, P.cfchild, P.cnchild, P.nodeB,
-                     P.leafof);
+                     P.leafof, P.longcnt, P.longslot, nblk);
   int64_t ge = cdiv(n, 256);
   if (ge > 4096) ge = 4096;
   hipLaunchKernelGGL(k_build_e, dim3(ge), dim3(256), 0, st, P.sc, P.clevel, P.cfchild,

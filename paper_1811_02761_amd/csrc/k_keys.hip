@@ -23,15 +23,32 @@ __global__ __launch_bounds__(256) void k_bbox(Coords c,
   float lo[3] = {INFINITY, INFINITY, INFINITY};
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float v[3] = {c.x[i * c.stride], c.y[i * c.stride], c.z[i * c.stride]};
+  auto take = [&](float x, float y, float z) {
+    const float v[3] = {x, y, z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       bad |= !isfinite(v[k]);
       lo[k] = fminf(lo[k], v[k]);
       hi[k] = fmaxf(hi[k], v[k]);
     }
+  };
+  // four particles per trip, their loads issued together; (x, y, z, m)
+  // records are read as one 16-byte load each
+  constexpr int kU = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool rec = c.stride == 4;
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n; i0 += kU * stride) {
+    float4 q[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = i0 + u * stride;
+      const int64_t j = i < n ? i : i0;  // (i0 < n)
+      q[u] = rec ? reinterpret_cast<const float4 *>(c.x)[j]
+                 : make_float4(c.x[j], c.y[j], c.z[j], 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (i0 + u * stride < n) take(q[u].x, q[u].y, q[u].z);
   }
   __shared__ float red[6][4];
   const int w = threadIdx.x >> 6;

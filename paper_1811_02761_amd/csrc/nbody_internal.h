@@ -88,7 +88,8 @@ struct Layout {
       off_gent, off_ghash, off_order, off_frontier, off_prevcnt, off_atmp, off_retry,
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
-      off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan;
+      off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan,
+      off_longcnt, off_longslot;
   size_t off_kpos[2], off_kvel[2], off_kacc[2], off_kmass[2], off_kpt[2], off_klv[2];
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
@@ -150,6 +151,8 @@ struct Ptrs {
                         // (cell, first child, children, particles)
   uint2 *leaves;        // leaves in particle order: (cell, first particle)
   uint32_t *scan;       // tile sums of the row scans
+  uint32_t *longcnt;    // per build block: its cells longer than one block (<= kLevels)
+  uint32_t *longslot;   // [blocks][kLevels] those cells
   // block steps inside one nbody_step call: the state in key order, two sets
   // (a rebuild permutes set c into set 1 - c)
   double *kpos[2];      // [3][n] x, y, z (FP64)
