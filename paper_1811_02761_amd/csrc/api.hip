@@ -616,7 +616,7 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   if (ctx->sys_r > 0) {
     launch_sys_keys(c, n, ctx->nsys, ctx->sys_r, P, ctx->st);
   } else {
-    launch_bbox(c, n, P.sc, ctx->st);
+    launch_bbox(c, n, P.sc, P.blkcnt, ctx->st);  // (block counts are free before the build)
     launch_keys(c, n, P.sc, P.keysA, P.valsA, ctx->st);
   }
   uint64_t *ks;

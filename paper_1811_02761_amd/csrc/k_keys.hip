@@ -11,15 +11,12 @@
 
 namespace nb {
 
-__global__ void k_bbox_init(DevScalars *sc) {
-  if (threadIdx.x < 3) {
-    sc->bbox[threadIdx.x] = 0xffffffffu;     // min of ordered ints
-    sc->bbox[3 + threadIdx.x] = 0u;          // max
-  }
-}
-
-__global__ __launch_bounds__(256) void k_bbox(Coords c,
-                                              int64_t n, DevScalars *sc) {
+// Bounds of the particles: each workgroup reduces its share to six ordered
+// integers in part[6 * block] (min x, y, z, max x, y, z); k_bbox_fold
+// reduces the blocks (no atomics on the six words: thousands of workgroups
+// contending for them were most of the pass).
+__global__ __launch_bounds__(256) void k_bbox(Coords c, int64_t n, DevScalars *sc,
+                                              uint32_t *__restrict__ part) {
   float lo[3] = {INFINITY, INFINITY, INFINITY};
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
@@ -32,9 +29,9 @@ __global__ __launch_bounds__(256) void k_bbox(Coords c,
       hi[k] = fmaxf(hi[k], v[k]);
     }
   };
-  // four particles per trip, their loads issued together; (x, y, z, m)
+  // kU particles per trip, their loads issued together; (x, y, z, m)
   // records are read as one 16-byte load each
-  constexpr int kU = 4;
+  constexpr int kU = 8;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool rec = c.stride == 4;
   for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n; i0 += kU * stride) {
@@ -70,8 +67,44 @@ __global__ __launch_bounds__(256) void k_bbox(Coords c,
       a = fminf(a, red[k][q]);
       b = fmaxf(b, red[3 + k][q]);
     }
-    atomicMin(&sc->bbox[k], f2ord(a));
-    atomicMax(&sc->bbox[3 + k], f2ord(b));
+    part[6 * blockIdx.x + k] = f2ord(a);
+    part[6 * blockIdx.x + 3 + k] = f2ord(b);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bbox_fold(const uint32_t *__restrict__ part, int nb,
+                                                   DevScalars *sc) {
+  uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = min(lo[k], part[6 * b + k]);
+      hi[k] = max(hi[k], part[6 * b + 3 + k]);
+    }
+  __shared__ uint32_t red[6][4];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t a = lo[k], c = hi[k];
+    for (int d = 32; d >= 1; d >>= 1) {
+      a = min(a, (uint32_t)__shfl_xor((int)a, d, 64));
+      c = max(c, (uint32_t)__shfl_xor((int)c, d, 64));
+    }
+    if (lane_id() == 0) {
+      red[k][w] = a;
+      red[3 + k][w] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    uint32_t a = red[k][0], c = red[3 + k][0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+      a = min(a, red[k][q]);
+      c = max(c, red[3 + k][q]);
+    }
+    sc->bbox[k] = a;
+    sc->bbox[3 + k] = c;
   }
 }
 
@@ -251,9 +284,10 @@ static int grid_for(int64_t n, int per_thread, int cap) {
   return (int)g;
 }
 
-void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_bbox_init, dim3(1), dim3(64), 0, st, sc);
-  hipLaunchKernelGGL(k_bbox, dim3(grid_for(n, 8, 2048)), dim3(256), 0, st, c, n, sc);
+void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, uint32_t *part, hipStream_t st) {
+  const int nb = grid_for(n, 16, 1024);  // 6 words of part per block
+  hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, st, c, n, sc, part);
+  hipLaunchKernelGGL(k_bbox_fold, dim3(1), dim3(256), 0, st, part, nb, sc);
 }
 
 void launch_sys_keys(const Coords &c, int64_t n, int nsys, int r, const Ptrs &P,

@@ -175,7 +175,8 @@ struct Coords {
 };
 
 // ---- launchers (each enqueues on `st`; grid sizes depend only on n) ----
-void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, hipStream_t st);
+// part: 6 x ceil(n / 4096) words of scratch
+void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, uint32_t *part, hipStream_t st);
 void launch_keys(const Coords &c, int64_t n, DevScalars *sc, uint64_t *keys, uint32_t *vals,
                  hipStream_t st);
 // returns pointer (A or B) holding the sorted result
