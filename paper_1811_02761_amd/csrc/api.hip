@@ -985,11 +985,11 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       return s;
     if ((s = do_calc(ctx, st->ax, st->ay, st->az, st->ax, st->ay, st->az)) != NBODY_OK)
       return s;
-    launch_blk_init(n, st->ax, st->ay, st->az, st->level, bc, sc, ctx->st);
+    launch_blk_init(n, st->ax, st->ay, st->az, st->level, bc, sc, P.blkcnt, ctx->st);
     st->have_acc = 1;
     ctx->since_rebuild = 0;
   } else {
-    launch_blk_scan(n, st->level, bc, sc, ctx->st);
+    launch_blk_scan(n, st->level, bc, sc, P.blkcnt, ctx->st);
     if (!ctx->have_tree || ctx->n != n) {
       // no tree of these particles: the first step builds one from the
       // drifted positions (the key-ordered layout needs one for its order
@@ -1052,7 +1052,7 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
     if (!keyed) ensure_asort(ctx, st);
     if ((s = do_calc(ctx, S.ax, S.ay, S.az, tx, ty, tz, true)) != NBODY_OK) break;
     launch_blk_close(n, S.ax, S.ay, S.az, tx, ty, tz, S.vx, S.vy, S.vz, S.lv, bc,
-                     keyed ? nullptr : P.asort, P.inv, sc, ctx->st);
+                     keyed ? nullptr : P.asort, P.inv, sc, P.blkcnt, ctx->st);
     ctx->since_rebuild++;
     ctx->steps++;
     s = hip_status();

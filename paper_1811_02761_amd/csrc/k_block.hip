@@ -67,8 +67,11 @@ __device__ int level_of(float ax, float ay, float az, const BlkTables &t, int lo
   return t.level_max;
 }
 
-// Block-wide max and sum, then one atomic each per block.
-__device__ void block_fold(int kmax, uint32_t cnt, DevScalars *sc, bool with_count) {
+// Block-wide max and sum, written to part[2 block], part[2 block + 1];
+// k_blk_fold reduces the blocks (atomics on two words from every block of a
+// launch queued up behind each other: 2 x 1024 of them cost more than the
+// closing kick's own traffic).
+__device__ void block_fold(int kmax, uint32_t cnt, uint32_t *part) {
   __shared__ int s_max[kBlkThreads / 64];
   __shared__ uint32_t s_cnt[kBlkThreads / 64];
   for (int d = 32; d >= 1; d >>= 1) {
@@ -88,8 +91,37 @@ __device__ void block_fold(int kmax, uint32_t cnt, DevScalars *sc, bool with_cou
       m = max(m, s_max[q]);
       c += s_cnt[q];
     }
-    atomicMax(&sc->kmax_next, (uint32_t)m);
-    if (with_count) atomicAdd(&sc->nactive, c);
+    part[2 * blockIdx.x] = (uint32_t)m;
+    part[2 * blockIdx.x + 1] = c;
+  }
+}
+
+// The blocks' maxima and counts: kmax_next = max, and (with_count) nactive
+// += sum.
+__global__ __launch_bounds__(256) void k_blk_fold(const uint32_t *__restrict__ part, int nb,
+                                                  DevScalars *sc, int with_count) {
+  uint32_t m = 0, c = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    m = max(m, part[2 * b]);
+    c += part[2 * b + 1];
+  }
+  __shared__ uint32_t s_m[4], s_c[4];
+  for (int d = 32; d >= 1; d >>= 1) {
+    m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    c += (uint32_t)__shfl_xor((int)c, d, 64);
+  }
+  if (lane_id() == 0) {
+    s_m[threadIdx.x >> 6] = m;
+    s_c[threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q) {
+      m = max(m, s_m[q]);
+      c += s_c[q];
+    }
+    sc->kmax_next = max(sc->kmax_next, m);
+    if (with_count) sc->nactive += c;
   }
 }
 
@@ -107,7 +139,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_init(int64_t n, const float
                                                           const float *__restrict__ ay,
                                                           const float *__restrict__ az,
                                                           int8_t *__restrict__ level,
-                                                          BlkTables t, DevScalars *sc) {
+                                                          BlkTables t, DevScalars *sc,
+                                                          uint32_t *__restrict__ part) {
   const int lo = max(t.level_min, align_level(sc->tick));
   int kmax = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -116,13 +149,13 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_init(int64_t n, const float
     level[i] = (int8_t)k;
     kmax = max(kmax, k);
   }
-  block_fold(kmax, 0u, sc, false);
+  block_fold(kmax, 0u, part);
 }
 
 __global__ __launch_bounds__(kBlkThreads) void k_blk_scan(int64_t n,
                                                           const int8_t *__restrict__ level,
                                                           int level_min, int level_max,
-                                                          DevScalars *sc) {
+                                                          DevScalars *sc, uint32_t *__restrict__ part) {
   int kmax = 0;
   bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -132,7 +165,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_scan(int64_t n,
     kmax = max(kmax, k);
   }
   if (bad) atomicOr(&sc->status, kStCorrupt);
-  block_fold(min(kmax, kTickBits), 0u, sc, false);
+  block_fold(min(kmax, kTickBits), 0u, part);
 }
 
 __global__ void k_blk_begin(DevScalars *sc) {
@@ -275,7 +308,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
     const float *__restrict__ nax, const float *__restrict__ nay,
     const float *__restrict__ naz, float *__restrict__ vx, float *__restrict__ vy,
     float *__restrict__ vz, int8_t *__restrict__ level, BlkTables t,
-    float4 *__restrict__ asort, const uint32_t *__restrict__ inv, DevScalars *sc) {
+    float4 *__restrict__ asort, const uint32_t *__restrict__ inv, DevScalars *sc,
+    uint32_t *__restrict__ part) {
   const long long t1 = sc->tick;
   const int lo = max(t.level_min, align_level(t1));
   int kmax = 0;
@@ -317,7 +351,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
       kmax = max(kmax, k);
     }
   }
-  block_fold(kmax, cnt, sc, true);
+  block_fold(kmax, cnt, part);
 }
 
 namespace {
@@ -334,15 +368,20 @@ void launch_blk_setup(long long tick, DevScalars *sc, hipStream_t st) {
 }
 
 void launch_blk_init(int64_t n, const float *ax, const float *ay, const float *az,
-                     int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_blk_init, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, ax, ay, az,
-                     level, make_tables(c), sc);
+                     int8_t *level, const BlockCfg &c, DevScalars *sc, uint32_t *part,
+                     hipStream_t st) {
+  const unsigned g = blk_grid(n);
+  hipLaunchKernelGGL(k_blk_init, dim3(g), dim3(kBlkThreads), 0, st, n, ax, ay, az, level,
+                     make_tables(c), sc, part);
+  hipLaunchKernelGGL(k_blk_fold, dim3(1), dim3(256), 0, st, part, (int)g, sc, 0);
 }
 
 void launch_blk_scan(int64_t n, const int8_t *level, const BlockCfg &c, DevScalars *sc,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_blk_scan, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, level,
-                     c.level_min, c.level_max, sc);
+                     uint32_t *part, hipStream_t st) {
+  const unsigned g = blk_grid(n);
+  hipLaunchKernelGGL(k_blk_scan, dim3(g), dim3(kBlkThreads), 0, st, n, level, c.level_min,
+                     c.level_max, sc, part);
+  hipLaunchKernelGGL(k_blk_fold, dim3(1), dim3(256), 0, st, part, (int)g, sc, 0);
 }
 
 void launch_blk_begin(DevScalars *sc, hipStream_t st) {
@@ -384,9 +423,15 @@ void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, cons
 void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
                       const float *nay, const float *naz, float *vx, float *vy, float *vz,
                       int8_t *level, const BlockCfg &c, float4 *asort, const uint32_t *inv,
-                      DevScalars *sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_blk_close, dim3(blk_grid(n)), dim3(kBlkThreads), 0, st, n, ax, ay, az,
-                     nax, nay, naz, vx, vy, vz, level, make_tables(c), asort, inv, sc);
+                      DevScalars *sc, uint32_t *part, hipStream_t st) {
+  // one trip of four particles per thread: a thread's loads of the levels
+  // and then of the active particles' values are two round trips (a capped
+  // grid left each thread eight of them)
+  int64_t g = cdiv(n, 4 * kBlkThreads);
+  g = std::min<int64_t>(std::max<int64_t>(g, 1), 16384);
+  hipLaunchKernelGGL(k_blk_close, dim3((unsigned)g), dim3(kBlkThreads), 0, st, n, ax, ay, az,
+                     nax, nay, naz, vx, vy, vz, level, make_tables(c), asort, inv, sc, part);
+  hipLaunchKernelGGL(k_blk_fold, dim3(1), dim3(256), 0, st, part, (int)g, sc, 1);
 }
 
 }  // namespace nb

@@ -378,11 +378,14 @@ struct BlockCfg {
 };
 void launch_blk_setup(long long tick, DevScalars *sc, hipStream_t st);
 // level of every particle from a (at the current tick); kmax_next = max level
+// part: scratch of 2 x (workgroups) words for the per-workgroup maxima and
+// counts (the build's block counts, free outside a build)
 void launch_blk_init(int64_t n, const float *ax, const float *ay, const float *az,
-                     int8_t *level, const BlockCfg &c, DevScalars *sc, hipStream_t st);
+                     int8_t *level, const BlockCfg &c, DevScalars *sc, uint32_t *part,
+                     hipStream_t st);
 // kmax_next = max level; levels outside [level_min, level_max] set kStCorrupt
 void launch_blk_scan(int64_t n, const int8_t *level, const BlockCfg &c, DevScalars *sc,
-                     hipStream_t st);
+                     uint32_t *part, hipStream_t st);
 // next tick; opening kicks at tick0; drift of every particle to tick
 void launch_blk_begin(DevScalars *sc, hipStream_t st);
 void launch_blk_open_drift(int64_t n, double *x, double *y, double *z, float *vx, float *vy,
@@ -397,7 +400,7 @@ void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, cons
 void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
                       const float *nay, const float *naz, float *vx, float *vy, float *vz,
                       int8_t *level, const BlockCfg &c, float4 *asort, const uint32_t *inv,
-                      DevScalars *sc, hipStream_t st);
+                      DevScalars *sc, uint32_t *part, hipStream_t st);
 void launch_order_by_count(int64_t n, const Ptrs &P, hipStream_t st);
 
 // ---- device helpers ----
