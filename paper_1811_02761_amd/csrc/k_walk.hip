@@ -395,9 +395,24 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
       const bool leaf = (w1 & kLeafBit) != 0u;
       const uint32_t ne = !has ? 0u : accept ? 1u : leaf ? (w1 & ~kLeafBit) : 0u;
       const uint32_t nch = (has && !accept && !leaf) ? w1 : 0u;
-      // children -> stack (over the popped chunk, in lane order)
-      const uint32_t chi = wave_incl_scan_dpp(nch);
-      const uint32_t chtot = wave_last(chi);
+      // children -> stack (over the popped chunk, in lane order) and entries
+      // -> list: one scan of both counts (children <= 8 per lane, so at most
+      // 512 per chunk: 10 bits; entries in the 22 bits above), or two scans
+      // when a leaf is so large (coincident particles) that they might not fit
+      uint32_t chi, chtot, ei, etot;
+      if (__ballot(ne >= 65536u) == 0ull) {  // (wave-uniform)
+        const uint32_t both = wave_incl_scan_dpp((ne << 10) | nch);
+        const uint32_t btot = wave_last(both);
+        chi = both & 1023u;
+        chtot = btot & 1023u;
+        ei = both >> 10;
+        etot = btot >> 10;
+      } else {
+        chi = wave_incl_scan_dpp(nch);
+        chtot = wave_last(chi);
+        ei = wave_incl_scan_dpp(ne);
+        etot = wave_last(ei);
+      }
       if (top + chtot > F) {
         overflow = true;
         break;
@@ -410,8 +425,6 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
       // [incl_k - ne_k, incl_k); the copy is cooperative: lane r of the wave
       // fetches entry done + r, finding its owner by binary search. With
       // K > 1 only this part's blocks are copied.
-      const uint32_t ei = wave_incl_scan_dpp(ne);
-      const uint32_t etot = wave_last(ei);
       if (kHash) {
         if (accept) hsum += mix64((uint64_t)c);
         else if (ne)
