@@ -117,6 +117,16 @@ KoSet ko_set(const Ptrs &P, int c, int64_t n) {
   return k;
 }
 
+// The region of set c as 64-byte records (4 x uint4 per particle).
+uint4 *ko_records(const Ptrs &P, int c) { return reinterpret_cast<uint4 *>(P.kpos[c]); }
+
+// Scratch for the state hash's per-workgroup partials: the block counts'
+// buffer, free between launches (ko_hash_parts(n) <= ceil(n / 1024) 8-byte
+// words; the buffer holds 23 ceil(n / 256) + 23 4-byte words).
+unsigned long long *hash_parts(const Ptrs &P) {
+  return reinterpret_cast<unsigned long long *>(P.blkcnt);
+}
+
 int device_cu_count(int *dev_out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
@@ -279,7 +289,10 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) 
   L.off_longcnt = take(4 * (size_t)L.build_blocks);
   L.off_longslot = take(4 * (size_t)L.build_blocks * kLevels);
   // key-ordered block-step state, two sets (none without stepping: the
-  // pointers then share one empty offset and are never used)
+  // pointers then share one empty offset and are never used); each set's
+  // region, from its positions on, spans at least 64 bytes per particle: it
+  // holds the 64-byte records of the entry and exit moves while the other
+  // set holds the state
   const size_t K = stepping ? N : 0;
   for (int c = 0; c < 2; ++c) {
     L.off_kpos[c] = take(24 * K);
@@ -288,6 +301,8 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) 
     L.off_kmass[c] = take(4 * K);
     L.off_kpt[c] = take(4 * K);
     L.off_klv[c] = take(K);
+    const size_t used = o - L.off_kpos[c];
+    if (used < 64 * K) take(64 * K - used);
   }
   L.total = o;
   return L;
@@ -1015,9 +1030,11 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
       return NBODY_EHIP;
     if (kept)
       launch_ko_hash(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
-                     st->m, st->level, &sc->ko_hash[1], ctx->st);
-    launch_ko_gather(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
-                     st->m, st->level, k0, kept ? sc->ko_hash : nullptr, ctx->st);
+                     st->m, st->level, &sc->ko_hash[1], hash_parts(P), ctx->st);
+    const KoSet caller{st->x,  st->y,  st->z,  st->vx, st->vy,   st->vz,
+                       st->ax, st->ay, st->az, st->m,  nullptr, st->level};
+    launch_ko_gather(n, caller, k0, ko_records(P, 1 - c), kept ? sc->ko_hash : nullptr,
+                     ctx->st);
     ctx->ko = c;
     ctx->perm = k0.pt;
   }
@@ -1059,12 +1076,12 @@ nbody_status step_block(nbody_ctx *ctx, nbody_state *st, int32_t n_steps) {
   }
   if (keyed) {
     // back to caller order; the tree keeps its permutation and gets its inverse
-    launch_ko_scatter(n, ko_set(P, ctx->ko, n), st->x, st->y, st->z, st->vx, st->vy, st->vz,
-                      st->ax, st->ay, st->az, st->level, ctx->st);
-    launch_invert(ctx->perm, n, P.inv, ctx->st);
+    // (and the hash a later call checks the caller's arrays against)
+    const KoSet caller{st->x,  st->y,  st->z,  st->vx, st->vy,   st->vz,
+                       st->ax, st->ay, st->az, st->m,  nullptr, st->level};
+    launch_ko_scatter(n, ko_set(P, ctx->ko, n), caller, ko_records(P, 1 - ctx->ko), P.inv,
+                      &sc->ko_hash[0], hash_parts(P), ctx->st);
     if (s == NBODY_OK) {
-      launch_ko_hash(n, st->x, st->y, st->z, st->vx, st->vy, st->vz, st->ax, st->ay, st->az,
-                     st->m, st->level, &sc->ko_hash[0], ctx->st);
       ctx->ko_keep = ctx->ko;
       ctx->ko_keep_epoch = ctx->epoch;
     }

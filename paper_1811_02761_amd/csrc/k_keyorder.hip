@@ -10,6 +10,15 @@
 // in order), and scattered back to caller order on exit. The arithmetic of a
 // step does not depend on where a particle's values are stored, so results
 // are bit-identical to a caller-order step.
+//
+// Caller order is unrelated to key order, so the entry and exit moves are
+// random accesses. They go through 64-byte records (one per particle, in the
+// region of the set that does not hold the state): one pass packs the
+// eleven arrays into records with contiguous reads, and writes each record
+// whole to its destination slot (or the next pass reads it whole from its
+// source slot); the other pass moves between records and arrays in order.
+// Eleven random 4- or 8-byte accesses per particle (each a partial line)
+// become one access of a whole record.
 #include "nbody_internal.h"
 
 namespace nb {
@@ -23,50 +32,126 @@ int ko_grid(int64_t n) {
 }
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_ko_gather(
-    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const float *__restrict__ vx, const float *__restrict__ vy,
-    const float *__restrict__ vz, const float *__restrict__ ax, const float *__restrict__ ay,
-    const float *__restrict__ az, const float *__restrict__ m,
-    const int8_t *__restrict__ level, KoSet k, const unsigned long long *__restrict__ skip) {
+namespace {
+// splitmix64's finaliser (Steele, Lea and Flood 2014).
+__device__ __forceinline__ unsigned long long state_mix(unsigned long long x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ unsigned long long pack2(float a, float b) {
+  return (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
+}
+
+// The hash term of caller index i and its values (a chain of mixes).
+__device__ __forceinline__ unsigned long long state_hash(int64_t i, double x, double y, double z,
+                                                         float vx, float vy, float vz, float ax,
+                                                         float ay, float az, float m,
+                                                         int8_t lv) {
+  unsigned long long h = state_mix((unsigned long long)i * 0x9e3779b97f4a7c15ull);
+  h = state_mix(h ^ (unsigned long long)__double_as_longlong(x));
+  h = state_mix(h ^ (unsigned long long)__double_as_longlong(y));
+  h = state_mix(h ^ (unsigned long long)__double_as_longlong(z));
+  h = state_mix(h ^ pack2(vx, vy));
+  h = state_mix(h ^ pack2(vz, ax));
+  h = state_mix(h ^ pack2(ay, az));
+  return state_mix(h ^ ((unsigned long long)__float_as_uint(m) |
+                        ((unsigned long long)(uint8_t)lv << 32)));
+}
+
+// Sum of a 256-thread workgroup's values into part[blockIdx.x] (same-address
+// atomics from thousands of workgroups would serialise; k_ko_hash_fold adds
+// the partials).
+__device__ __forceinline__ void block_hash_part(unsigned long long acc,
+                                                unsigned long long *__restrict__ part) {
+  __shared__ unsigned long long wsum[4];
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane_id() == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__device__ __forceinline__ uint32_t lo32(double v) {
+  return (uint32_t)(unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ uint32_t hi32(double v) {
+  return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+__device__ __forceinline__ double dbl(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+}  // namespace
+
+// Record of element s of a (without masses: 0), with s as its index, written
+// to rec slot to[s] (to == null: slot s).
+__global__ __launch_bounds__(256) void k_ko_put(int64_t n, KoSet a,
+                                                const uint32_t *__restrict__ to,
+                                                uint4 *__restrict__ rec,
+                                                const unsigned long long *__restrict__ skip) {
   if (skip && skip[0] == skip[1]) return;  // the set holds this state already
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t o = k.pt[s];
-    k.x[s] = x[o];
-    k.y[s] = y[o];
-    k.z[s] = z[o];
-    k.vx[s] = vx[o];
-    k.vy[s] = vy[o];
-    k.vz[s] = vz[o];
-    k.ax[s] = ax[o];
-    k.ay[s] = ay[o];
-    k.az[s] = az[o];
-    k.m[s] = m[o];
-    k.lv[s] = level[o];
+    const double x = a.x[s], y = a.y[s], z = a.z[s];
+    uint4 *r = rec + 4 * (size_t)(to ? to[s] : (uint32_t)s);
+    r[0] = make_uint4(lo32(x), hi32(x), lo32(y), hi32(y));
+    r[1] = make_uint4(lo32(z), hi32(z), __float_as_uint(a.vx[s]), __float_as_uint(a.vy[s]));
+    r[2] = make_uint4(__float_as_uint(a.vz[s]), __float_as_uint(a.ax[s]),
+                      __float_as_uint(a.ay[s]), __float_as_uint(a.az[s]));
+    r[3] = make_uint4(a.m ? __float_as_uint(a.m[s]) : 0u, (uint32_t)(uint8_t)a.lv[s],
+                      (uint32_t)s, 0u);
   }
 }
 
-__global__ __launch_bounds__(256) void k_ko_scatter(int64_t n, KoSet k, double *__restrict__ x,
-                                                    double *__restrict__ y, double *__restrict__ z,
-                                                    float *__restrict__ vx, float *__restrict__ vy,
-                                                    float *__restrict__ vz, float *__restrict__ ax,
-                                                    float *__restrict__ ay, float *__restrict__ az,
-                                                    int8_t *__restrict__ level) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t o = k.pt[s];
-    x[o] = k.x[s];
-    y[o] = k.y[s];
-    z[o] = k.z[s];
-    vx[o] = k.vx[s];
-    vy[o] = k.vy[s];
-    vz[o] = k.vz[s];
-    ax[o] = k.ax[s];
-    ay[o] = k.ay[s];
-    az[o] = k.az[s];
-    level[o] = k.lv[s];
+// Element j of b from rec slot from[j] (from == null: slot j); masses only
+// where b has them; tag[j] = the record's index; with part, the workgroup's
+// sum of the elements' hash terms goes to part[blockIdx.x].
+__global__ __launch_bounds__(256) void k_ko_get(int64_t n, const uint4 *__restrict__ rec,
+                                                const uint32_t *__restrict__ from, KoSet b,
+                                                uint32_t *__restrict__ tag,
+                                                unsigned long long *__restrict__ part,
+                                                const unsigned long long *__restrict__ skip) {
+  if (skip && skip[0] == skip[1]) return;  // the set holds this state already
+  unsigned long long acc = 0;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 *r = rec + 4 * (size_t)(from ? from[j] : (uint32_t)j);
+    const uint4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+    const double x = dbl(r0.x, r0.y), y = dbl(r0.z, r0.w), z = dbl(r1.x, r1.y);
+    const float vx = __uint_as_float(r1.z), vy = __uint_as_float(r1.w);
+    const float vz = __uint_as_float(r2.x), ax = __uint_as_float(r2.y);
+    const float ay = __uint_as_float(r2.z), az = __uint_as_float(r2.w);
+    const float m = __uint_as_float(r3.x);
+    const int8_t lv = (int8_t)(uint8_t)r3.y;
+    b.x[j] = x;
+    b.y[j] = y;
+    b.z[j] = z;
+    b.vx[j] = vx;
+    b.vy[j] = vy;
+    b.vz[j] = vz;
+    b.ax[j] = ax;
+    b.ay[j] = ay;
+    b.az[j] = az;
+    if (b.m) b.m[j] = m;
+    b.lv[j] = lv;
+    if (tag) tag[j] = r3.z;
+    if (part) acc += state_hash(j, x, y, z, vx, vy, vz, ax, ay, az, m, lv);
   }
+  if (part) block_hash_part(acc, part);
+}
+
+// *out = the sum of nb partials (one workgroup of 256).
+__global__ __launch_bounds__(256) void k_ko_hash_fold(const unsigned long long *__restrict__ part,
+                                                      int nb, unsigned long long *__restrict__ out) {
+  __shared__ unsigned long long wsum[4];
+  unsigned long long acc = 0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane_id() == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 __global__ __launch_bounds__(256) void k_ko_permute(int64_t n, const uint32_t *__restrict__ perm,
@@ -89,20 +174,6 @@ __global__ __launch_bounds__(256) void k_ko_permute(int64_t n, const uint32_t *_
   }
 }
 
-namespace {
-// splitmix64's finaliser (Steele, Lea and Flood 2014).
-__device__ __forceinline__ unsigned long long state_mix(unsigned long long x) {
-  x ^= x >> 30;
-  x *= 0xbf58476d1ce4e5b9ull;
-  x ^= x >> 27;
-  x *= 0x94d049bb133111ebull;
-  return x ^ (x >> 31);
-}
-
-__device__ __forceinline__ unsigned long long pack2(float a, float b) {
-  return (unsigned long long)__float_as_uint(a) | ((unsigned long long)__float_as_uint(b) << 32);
-}
-}  // namespace
 
 // Sum over particles of a chained mix of the particle's index and the bit
 // patterns of its values (order-free, so the result does not depend on the
@@ -112,26 +183,13 @@ __global__ __launch_bounds__(256) void k_ko_hash(
     const double *__restrict__ z, const float *__restrict__ vx, const float *__restrict__ vy,
     const float *__restrict__ vz, const float *__restrict__ ax, const float *__restrict__ ay,
     const float *__restrict__ az, const float *__restrict__ m,
-    const int8_t *__restrict__ level, unsigned long long *__restrict__ out) {
-  __shared__ unsigned long long part[4];
+    const int8_t *__restrict__ level, unsigned long long *__restrict__ part) {
   unsigned long long acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    unsigned long long h = state_mix((unsigned long long)i * 0x9e3779b97f4a7c15ull);
-    h = state_mix(h ^ (unsigned long long)__double_as_longlong(x[i]));
-    h = state_mix(h ^ (unsigned long long)__double_as_longlong(y[i]));
-    h = state_mix(h ^ (unsigned long long)__double_as_longlong(z[i]));
-    h = state_mix(h ^ pack2(vx[i], vy[i]));
-    h = state_mix(h ^ pack2(vz[i], ax[i]));
-    h = state_mix(h ^ pack2(ay[i], az[i]));
-    h = state_mix(h ^ ((unsigned long long)__float_as_uint(m[i]) |
-                   ((unsigned long long)(uint8_t)level[i] << 32)));
-    acc += h;
-  }
-  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += state_hash(i, x[i], y[i], z[i], vx[i], vy[i], vz[i], ax[i], ay[i], az[i], m[i],
+                      level[i]);
+  block_hash_part(acc, part);
 }
 
 // One thread per sorted position; the first position of a run of equal keys
@@ -160,30 +218,38 @@ __global__ __launch_bounds__(256) void k_ko_ties(int64_t n, const uint64_t *__re
   }
 }
 
-void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
-                      const float *vx, const float *vy, const float *vz, const float *ax,
-                      const float *ay, const float *az, const float *m, const int8_t *level,
-                      const KoSet &k, const unsigned long long *skip, hipStream_t st) {
-  hipLaunchKernelGGL(k_ko_gather, dim3(ko_grid(n)), dim3(256), 0, st, n, x, y, z, vx, vy, vz, ax,
-                     ay, az, m, level, k, skip);
+int ko_hash_parts(int64_t n) { return ko_grid(n); }
+
+void launch_ko_gather(int64_t n, const KoSet &caller, const KoSet &k, uint4 *rec,
+                      const unsigned long long *skip, hipStream_t st) {
+  KoSet a = caller;
+  a.pt = nullptr;
+  hipLaunchKernelGGL(k_ko_put, dim3(ko_grid(n)), dim3(256), 0, st, n, a, nullptr, rec, skip);
+  hipLaunchKernelGGL(k_ko_get, dim3(ko_grid(n)), dim3(256), 0, st, n, rec, k.pt, k, nullptr,
+                     nullptr, skip);
 }
 
 void launch_ko_hash(int64_t n, const double *x, const double *y, const double *z,
                     const float *vx, const float *vy, const float *vz, const float *ax,
                     const float *ay, const float *az, const float *m, const int8_t *level,
-                    unsigned long long *out, hipStream_t st) {
-  launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 2, st);
-  int64_t g = cdiv(n, 256 * 8);
-  g = std::min<int64_t>(std::max<int64_t>(g, 1), 1024);
-  hipLaunchKernelGGL(k_ko_hash, dim3((unsigned)g), dim3(256), 0, st, n, x, y, z, vx, vy, vz, ax,
-                     ay, az, m, level, out);
+                    unsigned long long *out, unsigned long long *part, hipStream_t st) {
+  const int g = ko_grid(n);
+  hipLaunchKernelGGL(k_ko_hash, dim3(g), dim3(256), 0, st, n, x, y, z, vx, vy, vz, ax, ay, az,
+                     m, level, part);
+  hipLaunchKernelGGL(k_ko_hash_fold, dim3(1), dim3(256), 0, st, part, g, out);
 }
 
-void launch_ko_scatter(int64_t n, const KoSet &k, double *x, double *y, double *z, float *vx,
-                       float *vy, float *vz, float *ax, float *ay, float *az, int8_t *level,
+void launch_ko_scatter(int64_t n, const KoSet &k, const KoSet &caller, uint4 *rec,
+                       uint32_t *inv, unsigned long long *hash, unsigned long long *part,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_ko_scatter, dim3(ko_grid(n)), dim3(256), 0, st, n, k, x, y, z, vx, vy,
-                     vz, ax, ay, az, level);
+  KoSet b = caller;
+  b.m = nullptr;  // masses do not change
+  b.pt = nullptr;
+  const int g = ko_grid(n);
+  hipLaunchKernelGGL(k_ko_put, dim3(g), dim3(256), 0, st, n, k, k.pt, rec, nullptr);
+  hipLaunchKernelGGL(k_ko_get, dim3(g), dim3(256), 0, st, n, rec, nullptr, b, inv, part,
+                     nullptr);
+  hipLaunchKernelGGL(k_ko_hash_fold, dim3(1), dim3(256), 0, st, part, g, hash);
 }
 
 void launch_ko_permute(int64_t n, const uint32_t *perm, const KoSet &from, const KoSet &to,

@@ -294,24 +294,32 @@ struct KoSet {
   uint32_t *pt;   // caller index of slot s
   int8_t *lv;
 };
-// Caller order -> key order: slot s takes caller index pt[s] (pt filled by
-// the caller). With skip (two hashes on the
-// device), nothing is done when skip[0] == skip[1].
-void launch_ko_gather(int64_t n, const double *x, const double *y, const double *z,
-                      const float *vx, const float *vy, const float *vz, const float *ax,
-                      const float *ay, const float *az, const float *m, const int8_t *level,
-                      const KoSet &k, const unsigned long long *skip, hipStream_t st);
+// Moves between caller order and key order go through 64-byte records, one
+// per particle (x, y, z; vx, vy, vz; ax, ay, az; m; level; an index), held in
+// the region of the key-ordered set that does not hold the state (each set's
+// region is at least 64 n bytes): every particle then costs one random access
+// of a whole record instead of eleven random 4- or 8-byte accesses.
+// Caller order -> key order into set k: slot s takes caller index k.pt[s]
+// (pt filled by the caller); rec = the other set's region. With skip (two
+// hashes on the device), nothing is done when skip[0] == skip[1].
+void launch_ko_gather(int64_t n, const KoSet &caller, const KoSet &k, uint4 *rec,
+                      const unsigned long long *skip, hipStream_t st);
 // *out = a 64-bit hash of the caller-order block-step state (positions,
 // velocities, accelerations, masses, levels, by index; a sum of per-particle
 // mixes, so any change of a value changes it except with probability about
-// 2^-64). Clears *out first.
+// 2^-64). part: scratch of ko_hash_parts(n) words of 64 bits.
 void launch_ko_hash(int64_t n, const double *x, const double *y, const double *z,
                     const float *vx, const float *vy, const float *vz, const float *ax,
                     const float *ay, const float *az, const float *m, const int8_t *level,
-                    unsigned long long *out, hipStream_t st);
-// Key order -> caller order (positions, velocities, accelerations, levels).
-void launch_ko_scatter(int64_t n, const KoSet &k, double *x, double *y, double *z, float *vx,
-                       float *vy, float *vz, float *ax, float *ay, float *az, int8_t *level,
+                    unsigned long long *out, unsigned long long *part, hipStream_t st);
+int ko_hash_parts(int64_t n);
+// Key order -> caller order from set k (positions, velocities, accelerations,
+// levels; the caller's masses are not written); rec = the other set's
+// region. Also writes inv[k.pt[s]] = s and, into *hash, the hash
+// launch_ko_hash gives for the caller's arrays after the move (part: as
+// there).
+void launch_ko_scatter(int64_t n, const KoSet &k, const KoSet &caller, uint4 *rec,
+                       uint32_t *inv, unsigned long long *hash, unsigned long long *part,
                        hipStream_t st);
 // After a rebuild: slot s of the new order is slot perm[s] of the old one.
 void launch_ko_permute(int64_t n, const uint32_t *perm, const KoSet &from, const KoSet &to,
