@@ -85,59 +85,86 @@ __device__ __forceinline__ double dbl(uint32_t lo, uint32_t hi) {
 }
 }  // namespace
 
+// Records pass through LDS in tiles of 256 (one per thread), so that each
+// memory instruction moves whole 64-byte records: four consecutive lanes
+// per record, instead of one lane storing or loading 16 bytes at a 64-byte
+// stride. A tile row is padded to 80 bytes against LDS bank conflicts.
+constexpr int kRecTile = 256;
+constexpr int kRecRow = 5;  // uint4 per LDS row (4 used)
+
 // Record of element s of a (without masses: 0), with s as its index, written
 // to rec slot to[s] (to == null: slot s).
-__global__ __launch_bounds__(256) void k_ko_put(int64_t n, KoSet a,
-                                                const uint32_t *__restrict__ to,
-                                                uint4 *__restrict__ rec,
-                                                const unsigned long long *__restrict__ skip) {
+__global__ __launch_bounds__(kRecTile) void k_ko_put(int64_t n, KoSet a,
+                                                     const uint32_t *__restrict__ to,
+                                                     uint4 *__restrict__ rec,
+                                                     const unsigned long long *__restrict__ skip) {
   if (skip && skip[0] == skip[1]) return;  // the set holds this state already
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    const double x = a.x[s], y = a.y[s], z = a.z[s];
-    uint4 *r = rec + 4 * (size_t)(to ? to[s] : (uint32_t)s);
-    r[0] = make_uint4(lo32(x), hi32(x), lo32(y), hi32(y));
-    r[1] = make_uint4(lo32(z), hi32(z), __float_as_uint(a.vx[s]), __float_as_uint(a.vy[s]));
-    r[2] = make_uint4(__float_as_uint(a.vz[s]), __float_as_uint(a.ax[s]),
-                      __float_as_uint(a.ay[s]), __float_as_uint(a.az[s]));
-    r[3] = make_uint4(a.m ? __float_as_uint(a.m[s]) : 0u, (uint32_t)(uint8_t)a.lv[s],
-                      (uint32_t)s, 0u);
+  __shared__ uint4 srec[kRecTile][kRecRow];
+  __shared__ uint32_t sslot[kRecTile];
+  for (int64_t t0 = blockIdx.x * (int64_t)kRecTile; t0 < n; t0 += (int64_t)gridDim.x * kRecTile) {
+    const int64_t s = t0 + threadIdx.x;
+    if (s < n) {
+      const double x = a.x[s], y = a.y[s], z = a.z[s];
+      uint4 *r = srec[threadIdx.x];
+      r[0] = make_uint4(lo32(x), hi32(x), lo32(y), hi32(y));
+      r[1] = make_uint4(lo32(z), hi32(z), __float_as_uint(a.vx[s]), __float_as_uint(a.vy[s]));
+      r[2] = make_uint4(__float_as_uint(a.vz[s]), __float_as_uint(a.ax[s]),
+                        __float_as_uint(a.ay[s]), __float_as_uint(a.az[s]));
+      r[3] = make_uint4(a.m ? __float_as_uint(a.m[s]) : 0u, (uint32_t)(uint8_t)a.lv[s],
+                        (uint32_t)s, 0u);
+      sslot[threadIdx.x] = to ? to[s] : (uint32_t)s;
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kRecTile, n - t0);
+    for (int q = threadIdx.x; q < 4 * cnt; q += kRecTile)
+      rec[4 * (size_t)sslot[q >> 2] + (q & 3)] = srec[q >> 2][q & 3];
+    __syncthreads();
   }
 }
 
 // Element j of b from rec slot from[j] (from == null: slot j); masses only
 // where b has them; tag[j] = the record's index; with part, the workgroup's
 // sum of the elements' hash terms goes to part[blockIdx.x].
-__global__ __launch_bounds__(256) void k_ko_get(int64_t n, const uint4 *__restrict__ rec,
-                                                const uint32_t *__restrict__ from, KoSet b,
-                                                uint32_t *__restrict__ tag,
-                                                unsigned long long *__restrict__ part,
-                                                const unsigned long long *__restrict__ skip) {
+__global__ __launch_bounds__(kRecTile) void k_ko_get(int64_t n, const uint4 *__restrict__ rec,
+                                                     const uint32_t *__restrict__ from, KoSet b,
+                                                     uint32_t *__restrict__ tag,
+                                                     unsigned long long *__restrict__ part,
+                                                     const unsigned long long *__restrict__ skip) {
   if (skip && skip[0] == skip[1]) return;  // the set holds this state already
+  __shared__ uint4 srec[kRecTile][kRecRow];
   unsigned long long acc = 0;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const uint4 *r = rec + 4 * (size_t)(from ? from[j] : (uint32_t)j);
-    const uint4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-    const double x = dbl(r0.x, r0.y), y = dbl(r0.z, r0.w), z = dbl(r1.x, r1.y);
-    const float vx = __uint_as_float(r1.z), vy = __uint_as_float(r1.w);
-    const float vz = __uint_as_float(r2.x), ax = __uint_as_float(r2.y);
-    const float ay = __uint_as_float(r2.z), az = __uint_as_float(r2.w);
-    const float m = __uint_as_float(r3.x);
-    const int8_t lv = (int8_t)(uint8_t)r3.y;
-    b.x[j] = x;
-    b.y[j] = y;
-    b.z[j] = z;
-    b.vx[j] = vx;
-    b.vy[j] = vy;
-    b.vz[j] = vz;
-    b.ax[j] = ax;
-    b.ay[j] = ay;
-    b.az[j] = az;
-    if (b.m) b.m[j] = m;
-    b.lv[j] = lv;
-    if (tag) tag[j] = r3.z;
-    if (part) acc += state_hash(j, x, y, z, vx, vy, vz, ax, ay, az, m, lv);
+  for (int64_t t0 = blockIdx.x * (int64_t)kRecTile; t0 < n; t0 += (int64_t)gridDim.x * kRecTile) {
+    const int cnt = (int)min((int64_t)kRecTile, n - t0);
+    for (int q = threadIdx.x; q < 4 * cnt; q += kRecTile) {
+      const int64_t j = t0 + (q >> 2);
+      srec[q >> 2][q & 3] = rec[4 * (size_t)(from ? from[j] : (uint32_t)j) + (q & 3)];
+    }
+    __syncthreads();
+    const int64_t j = t0 + threadIdx.x;
+    if (j < n) {
+      const uint4 *r = srec[threadIdx.x];
+      const uint4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+      const double x = dbl(r0.x, r0.y), y = dbl(r0.z, r0.w), z = dbl(r1.x, r1.y);
+      const float vx = __uint_as_float(r1.z), vy = __uint_as_float(r1.w);
+      const float vz = __uint_as_float(r2.x), ax = __uint_as_float(r2.y);
+      const float ay = __uint_as_float(r2.z), az = __uint_as_float(r2.w);
+      const float m = __uint_as_float(r3.x);
+      const int8_t lv = (int8_t)(uint8_t)r3.y;
+      b.x[j] = x;
+      b.y[j] = y;
+      b.z[j] = z;
+      b.vx[j] = vx;
+      b.vy[j] = vy;
+      b.vz[j] = vz;
+      b.ax[j] = ax;
+      b.ay[j] = ay;
+      b.az[j] = az;
+      if (b.m) b.m[j] = m;
+      b.lv[j] = lv;
+      if (tag) tag[j] = r3.z;
+      if (part) acc += state_hash(j, x, y, z, vx, vy, vz, ax, ay, az, m, lv);
+    }
+    __syncthreads();
   }
   if (part) block_hash_part(acc, part);
 }
@@ -224,8 +251,8 @@ void launch_ko_gather(int64_t n, const KoSet &caller, const KoSet &k, uint4 *rec
                       const unsigned long long *skip, hipStream_t st) {
   KoSet a = caller;
   a.pt = nullptr;
-  hipLaunchKernelGGL(k_ko_put, dim3(ko_grid(n)), dim3(256), 0, st, n, a, nullptr, rec, skip);
-  hipLaunchKernelGGL(k_ko_get, dim3(ko_grid(n)), dim3(256), 0, st, n, rec, k.pt, k, nullptr,
+  hipLaunchKernelGGL(k_ko_put, dim3(ko_grid(n)), dim3(kRecTile), 0, st, n, a, nullptr, rec, skip);
+  hipLaunchKernelGGL(k_ko_get, dim3(ko_grid(n)), dim3(kRecTile), 0, st, n, rec, k.pt, k, nullptr,
                      nullptr, skip);
 }
 
@@ -246,8 +273,8 @@ void launch_ko_scatter(int64_t n, const KoSet &k, const KoSet &caller, uint4 *re
   b.m = nullptr;  // masses do not change
   b.pt = nullptr;
   const int g = ko_grid(n);
-  hipLaunchKernelGGL(k_ko_put, dim3(g), dim3(256), 0, st, n, k, k.pt, rec, nullptr);
-  hipLaunchKernelGGL(k_ko_get, dim3(g), dim3(256), 0, st, n, rec, nullptr, b, inv, part,
+  hipLaunchKernelGGL(k_ko_put, dim3(g), dim3(kRecTile), 0, st, n, k, k.pt, rec, nullptr);
+  hipLaunchKernelGGL(k_ko_get, dim3(g), dim3(kRecTile), 0, st, n, rec, nullptr, b, inv, part,
                      nullptr);
   hipLaunchKernelGGL(k_ko_hash_fold, dim3(1), dim3(256), 0, st, part, g, hash);
 }
