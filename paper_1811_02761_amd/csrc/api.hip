@@ -288,6 +288,7 @@ Layout make_layout(const nbody_params &p, int64_t n, int num_cu, bool stepping) 
                                          scan_scratch_words(cdiv(L.cell_cap, 256), 1)));
   L.off_longcnt = take(4 * (size_t)L.build_blocks);
   L.off_longslot = take(4 * (size_t)L.build_blocks * kLevels);
+  L.off_wpart = take(8 * 4 * (size_t)kStatBlocks);
   // key-ordered block-step state, two sets (none without stepping: the
   // pointers then share one empty offset and are never used); each set's
   // region, from its positions on, spans at least 64 bytes per particle: it
@@ -380,6 +381,7 @@ Ptrs carve(void *base, const Layout &L) {
   P.scan = reinterpret_cast<uint32_t *>(b + L.off_scan);
   P.longcnt = reinterpret_cast<uint32_t *>(b + L.off_longcnt);
   P.longslot = reinterpret_cast<uint32_t *>(b + L.off_longslot);
+  P.wpart = reinterpret_cast<unsigned long long *>(b + L.off_wpart);
   for (int c = 0; c < 2; ++c) {
     P.kpos[c] = reinterpret_cast<double *>(b + L.off_kpos[c]);
     P.kvel[c] = reinterpret_cast<float *>(b + L.off_kvel[c]);
@@ -729,7 +731,6 @@ nbody_status do_calc(nbody_ctx *ctx, const float *axo, const float *ayo, const f
     launch_cost_order(ctx->n, queued, mode, ctx->mlp_hidden, P, ctx->st);
   }
   const bool use_queue = queued || mode != 0;
-  launch_fill_u32(&P.sc->queue_head, 0u, 1, ctx->st);
   WalkCfg wc = walk_cfg(ctx, boot, use_queue);
   wc.asort_out = keep_mirror;
   wc.phi = phi;

@@ -62,6 +62,7 @@ struct WalkArgs {
   float4 *asort;           // key-ordered copy of the outputs with |a| (nullptr: none)
   uint32_t *retry;         // overflowing groups go here (nullptr: report instead)
   uint32_t *nretry;
+  uint32_t *head;          // the work queue's claim counter
   uint32_t *frontier;
   uint32_t *gent;
   unsigned long long *ghash;
@@ -325,7 +326,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a, float4 *lds_list) {
   // adds 1, the rest 0) and the per-group results below are stored by every
   // lane (same value, same address).
   for (;;) {
-    const uint32_t claim = atomicAdd(&a.sc->queue_head, lane == 0 ? 1u : 0u);
+    const uint32_t claim = atomicAdd(a.head, lane == 0 ? 1u : 0u);
     const uint32_t task = __builtin_amdgcn_readfirstlane(claim);
     const uint32_t qi = task >> kshift;
     const uint32_t part = task & (K - 1u);
@@ -566,28 +567,17 @@ __global__ __launch_bounds__(256) void k_walk_join(WalkArgs a, uint32_t walk_wav
   }
 }
 
-__global__ void k_walk_stat_zero(DevScalars *sc) {
-  if (threadIdx.x == 0) {
-    sc->wstat.ngroup = sc->ngroup;
-    sc->wstat.queued = 0;
-    sc->wstat.inter = 0;
-    sc->wstat.inter_a = 0;
-    sc->wstat.inter_ref = 0;
-    sc->wstat.entries = 0;
-    sc->wstat.tick = sc->tick;
-    sc->wstat.kmax = sc->kmax;
-  }
-}
-
 // Interactions of the walked groups, and of those the tree's reference walk
-// also took, now and then (the reference walk records them here); integer
-// sums, so the atomics are exact.
+// also took, now and then (the reference walk records them here): integer
+// sums per workgroup into part[4 * blockIdx.x ..] (same-address atomics from
+// every workgroup would serialise), added up by k_walk_stat_fold.
 __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
                                                    const uint32_t *__restrict__ order,
                                                    const uint32_t *__restrict__ gcount,
                                                    const uint32_t *__restrict__ gent,
-                                                   uint32_t *__restrict__ gref, int record) {
-  __shared__ unsigned long long s_cur[4], s_a[4], s_ref[4], s_e[4];
+                                                   uint32_t *__restrict__ gref, int record,
+                                                   unsigned long long *__restrict__ part) {
+  __shared__ unsigned long long s_sum[4][4];
   const uint32_t nq = order ? sc->nqueue : sc->ngroup;
   unsigned long long cur = 0, cur_a = 0, ref = 0, ent = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq;
@@ -614,26 +604,54 @@ __global__ __launch_bounds__(256) void k_walk_stat(DevScalars *__restrict__ sc,
     ref += __shfl_xor(ref, d, 64);
     ent += __shfl_xor(ent, d, 64);
   }
+  const int w = threadIdx.x >> 6;
   if (lane_id() == 0) {
-    s_cur[threadIdx.x >> 6] = cur;
-    s_a[threadIdx.x >> 6] = cur_a;
-    s_ref[threadIdx.x >> 6] = ref;
-    s_e[threadIdx.x >> 6] = ent;
+    s_sum[w][0] = cur;
+    s_sum[w][1] = cur_a;
+    s_sum[w][2] = ref;
+    s_sum[w][3] = ent;
   }
   __syncthreads();
+  if (threadIdx.x < 4)
+    part[4 * blockIdx.x + threadIdx.x] = s_sum[0][threadIdx.x] + s_sum[1][threadIdx.x] +
+                                         s_sum[2][threadIdx.x] + s_sum[3][threadIdx.x];
+}
+
+// The walk statistics: the partials' sums and the step's scalars (one
+// workgroup of kStatBlocks threads).
+__global__ __launch_bounds__(kStatBlocks) void k_walk_stat_fold(
+    DevScalars *__restrict__ sc, const unsigned long long *__restrict__ part, int queued) {
+  __shared__ unsigned long long s_sum[kStatBlocks / 64][4];
+  unsigned long long v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = part[4 * threadIdx.x + k];
+    for (int d = 32; d >= 1; d >>= 1) v[k] += __shfl_xor(v[k], d, 64);
+  }
+  if (lane_id() == 0)
+    for (int k = 0; k < 4; ++k) s_sum[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long a = 0, b = 0, r = 0, e = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      a += s_cur[w];
-      b += s_a[w];
-      r += s_ref[w];
-      e += s_e[w];
-    }
-    atomicAdd(&sc->wstat.inter, a);
-    atomicAdd(&sc->wstat.inter_a, b);
-    atomicAdd(&sc->wstat.inter_ref, r);
-    atomicAdd(&sc->wstat.entries, e);
-    if (blockIdx.x == 0) sc->wstat.queued = nq;
+    unsigned long long t[4] = {0, 0, 0, 0};
+    for (int w = 0; w < kStatBlocks / 64; ++w)
+      for (int k = 0; k < 4; ++k) t[k] += s_sum[w][k];
+    sc->wstat.ngroup = sc->ngroup;
+    sc->wstat.queued = queued ? sc->nqueue : sc->ngroup;
+    sc->wstat.inter = t[0];
+    sc->wstat.inter_a = t[1];
+    sc->wstat.inter_ref = t[2];
+    sc->wstat.entries = t[3];
+    sc->wstat.tick = sc->tick;
+    sc->wstat.kmax = sc->kmax;
+  }
+}
+
+// Both work queues' claim counters and the retry count start at zero.
+__global__ void k_walk_prep(DevScalars *sc) {
+  if (threadIdx.x == 0) {
+    sc->queue_head = 0;
+    sc->retry_head = 0;
+    sc->nretry = 0;
   }
 }
 
@@ -672,9 +690,11 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
 }
 
 void launch_walk_stat(bool queued, bool record, const Ptrs &P, hipStream_t st) {
-  hipLaunchKernelGGL(k_walk_stat_zero, dim3(1), dim3(64), 0, st, P.sc);
-  hipLaunchKernelGGL(k_walk_stat, dim3(256), dim3(256), 0, st, P.sc, queued ? P.order : nullptr,
-                     P.gcount, P.gent, P.gref, record ? 1 : 0);
+  hipLaunchKernelGGL(k_walk_stat, dim3(kStatBlocks), dim3(256), 0, st, P.sc,
+                     queued ? P.order : nullptr, P.gcount, P.gent, P.gref, record ? 1 : 0,
+                     P.wpart);
+  hipLaunchKernelGGL(k_walk_stat_fold, dim3(1), dim3(kStatBlocks), 0, st, P.sc, P.wpart,
+                     queued ? 1 : 0);
 }
 
 
@@ -695,6 +715,7 @@ WalkArgs walk_args(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
   a.asort = c.asort_out ? P.asort : nullptr;
   a.retry = P.retry;
   a.nretry = &P.sc->nretry;
+  a.head = &P.sc->queue_head;
   a.frontier = P.frontier;
   a.gent = P.gent;
   a.ghash = P.ghash;
@@ -742,7 +763,7 @@ void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax, f
                  float *az, const Ptrs &P, hipStream_t st) {
   const WalkArgs a = walk_args(c, perm, n, ax, ay, az, P);
   const int blocks = c.num_cu * c.waves_per_cu / kWalkWavesPerWG;
-  launch_fill_u32(&P.sc->nretry, 0u, 1, st);
+  hipLaunchKernelGGL(k_walk_prep, dim3(1), dim3(64), 0, st, P.sc);
   if (c.phi) {
     NB_WALK_LAUNCH(k_walk_pot, c, dim3(blocks), walk_lds(c), st, a);
     return;  // never split
@@ -765,8 +786,8 @@ void launch_walk_retry(const WalkCfg &c, const uint32_t *perm, int64_t n, float 
   r.retry = nullptr;
   r.frontier = P.frontier2;
   r.fmask = (uint32_t)c.frontier2_cap - 1u;
-  r.split_mode = -1;  // results written by the pass itself
-  launch_fill_u32(&P.sc->queue_head, 0u, 1, st);
+  r.head = &P.sc->retry_head;  // cleared with the walk's counters
+  r.split_mode = -1;           // results written by the pass itself
   if (c.phi)
     NB_WALK_LAUNCH(k_walk_pot, c, dim3(c.retry_waves / kWalkWavesPerWG), walk_lds(c), st, r);
   else

@@ -18,6 +18,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // keys per workgroup
 constexpr int kBuildThreads = 256;                   // particles per build block
 constexpr int kBuildHalo = 64;                       // >= max(leaf_max, group_max)
 constexpr int kWalkWavesPerWG = 4;
+constexpr int kStatBlocks = 256;  // workgroups of the walk statistics pass
 // split walk: 4 partial sums x 3 components x 64 lanes (FP32) per queue position
 constexpr int kSplitSlotBytes = 4 * 3 * 64 * 4;
 
@@ -60,7 +61,8 @@ struct DevScalars {
   uint32_t nqueue;         // groups in the walk queue (order[])
   uint32_t nactive;        // particles active at the end of the current step
   uint32_t nretry;         // groups handed from the walk to its retry pass
-  uint32_t pad[3];
+  uint32_t retry_head;     // the retry pass's work queue
+  uint32_t pad[2];
   WalkStat wstat;
   unsigned long long bar_epoch;  // launches of the grid-barrier calcNode so far
   uint32_t istart[kLevels + 1];  // internal cells of level l: ilist[istart[l] .. istart[l + 1])
@@ -89,7 +91,7 @@ struct Layout {
       off_frontier2, off_feat, off_target, off_pred, off_plast, off_okeys, off_qtmp, off_mlpw,
       off_mlpm, off_mlpv, off_mlpg, off_mlppart, off_gref, off_sysoff, off_sysbox, off_groot,
       off_inv, off_asort, off_split, off_gid, off_gflag, off_ilist, off_leaves, off_scan,
-      off_longcnt, off_longslot;
+      off_longcnt, off_longslot, off_wpart;
   size_t off_kpos[2], off_kvel[2], off_kacc[2], off_kmass[2], off_kpt[2], off_klv[2];
   int64_t frontier2_cap = 0;  // retry pass stack: more than any tree needs
   int retry_waves = 0;
@@ -153,6 +155,7 @@ struct Ptrs {
   uint32_t *scan;       // tile sums of the row scans
   uint32_t *longcnt;    // per build block: its cells longer than one block (<= kLevels)
   uint32_t *longslot;   // [blocks][kLevels] those cells
+  unsigned long long *wpart;  // [kStatBlocks][4] partials of the walk statistics
   // block steps inside one nbody_step call: the state in key order, two sets
   // (a rebuild permutes set c into set 1 - c)
   double *kpos[2];      // [3][n] x, y, z (FP64)
@@ -234,7 +237,7 @@ struct WalkCfg {
   int64_t split_slots;
   float *phi = nullptr;  // potential output (caller order): the potential variant
 };
-// enqueue the walk kernel (the queue head must already be zero), then its
+// enqueue the walk kernel (after clearing its queue counters), then its
 // retry pass for groups whose stack overflowed
 void launch_walk(const WalkCfg &c, const uint32_t *perm, int64_t n, float *ax,
                  float *ay, float *az, const Ptrs &P, hipStream_t st);
