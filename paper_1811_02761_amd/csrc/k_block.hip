@@ -299,8 +299,32 @@ __global__ __launch_bounds__(kBlkThreads) void k_blk_qemit(const DevScalars *__r
     }
 }
 
-__global__ void k_blk_qtotal(const uint32_t *__restrict__ total, DevScalars *sc) {
-  if (threadIdx.x == 0) sc->nqueue = total[0];
+// Exclusive scan of the per-block counts in place, by one workgroup (a
+// thread per run of consecutive blocks), and the queue length.
+constexpr int kQScanThreads = 1024;
+__global__ __launch_bounds__(kQScanThreads) void k_blk_qscan(uint32_t *__restrict__ blk,
+                                                             uint32_t nblk,
+                                                             DevScalars *__restrict__ sc) {
+  __shared__ uint32_t wsum[kQScanThreads / 64];
+  const uint32_t per = (nblk + kQScanThreads - 1) / kQScanThreads;
+  const uint32_t b0 = threadIdx.x * per, b1 = min(nblk, b0 + per);
+  uint32_t s = 0;
+  for (uint32_t k = b0; k < b1; ++k) s += blk[k];
+  const uint32_t inc = wave_incl_scan(s);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t run = inc - s, all = 0;
+  for (int q = 0; q < kQScanThreads / 64; ++q) {
+    if (q < w) run += wsum[q];
+    all += wsum[q];
+  }
+  for (uint32_t k = b0; k < b1; ++k) {
+    const uint32_t v = blk[k];
+    blk[k] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) sc->nqueue = all;
 }
 
 __global__ __launch_bounds__(kBlkThreads) void k_blk_close(
@@ -410,14 +434,13 @@ void launch_blk_queue(int64_t n, const int8_t *level, const uint32_t *perm, cons
   hipLaunchKernelGGL(k_blk_mark, dim3((unsigned)gm), dim3(kBlkThreads), 0, st, n, P.sc, perm,
                      P.gid, level, P.gflag);
   // ngroup <= n: blocks for n groups; the build's block-count buffer (free
-  // outside the build) holds the per-block counts and the total
+  // outside the build) holds the per-block counts
   const uint32_t nblk = (uint32_t)cdiv(n, kQGroups);
-  uint32_t *blk = P.blkcnt, *total = P.blkcnt + nblk;
+  uint32_t *blk = P.blkcnt;
   hipLaunchKernelGGL(k_blk_qcount, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gflag, blk);
-  launch_scan_rows(blk, nblk, 1, total, P.scan, st);
+  hipLaunchKernelGGL(k_blk_qscan, dim3(1), dim3(kQScanThreads), 0, st, blk, nblk, P.sc);
   hipLaunchKernelGGL(k_blk_qemit, dim3(nblk), dim3(kBlkThreads), 0, st, P.sc, P.gflag, blk,
                      P.order);
-  hipLaunchKernelGGL(k_blk_qtotal, dim3(1), dim3(64), 0, st, total, P.sc);
 }
 
 void launch_blk_close(int64_t n, float *ax, float *ay, float *az, const float *nax,
