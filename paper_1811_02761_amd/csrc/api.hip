@@ -640,14 +640,15 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   uint32_t *pm;
   launch_sort(n, P.keysA, P.valsA, P.keysB, P.valsB, P.hist, ctx->st, &ks, &pm);
   if (ko) launch_ko_ties(n, ks, pm, P.kpt[ctx->ko], ctx->st);  // equal keys: caller order
-  launch_gather(c, pm, n, P.xyzm, ctx->st);
+  // (key order: the state permute below writes the sorted records)
+  if (!ko) launch_gather(c, pm, n, P.xyzm, ctx->st);
   if (remap) {  // (before inv is rewritten; okeys is free outside a walk)
     launch_asort_remap(pm, P.inv, n, P.asort, reinterpret_cast<float4 *>(P.okeys), ctx->st);
     ctx->asort_epoch = ctx->epoch;
   }
   if (ko) {
     const int c1 = 1 - ctx->ko;
-    launch_ko_permute(n, pm, ko_set(P, ctx->ko, n), ko_set(P, c1, n), ctx->st);
+    launch_ko_permute(n, pm, ko_set(P, ctx->ko, n), ko_set(P, c1, n), P.xyzm, ctx->st);
     ctx->ko = c1;
   } else {
     launch_invert(pm, n, P.inv, ctx->st);

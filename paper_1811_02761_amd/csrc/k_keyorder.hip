@@ -181,21 +181,26 @@ __global__ __launch_bounds__(256) void k_ko_hash_fold(const unsigned long long *
   if (threadIdx.x == 0) *out = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+// With xyzm, also the sorted (x, y, z, m) records of the tree: the positions
+// rounded to FP32, as the drift rounded them for the keys.
 __global__ __launch_bounds__(256) void k_ko_permute(int64_t n, const uint32_t *__restrict__ perm,
-                                                    KoSet f, KoSet t) {
+                                                    KoSet f, KoSet t, float4 *__restrict__ xyzm) {
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t o = perm[s];
-    t.x[s] = f.x[o];
-    t.y[s] = f.y[o];
-    t.z[s] = f.z[o];
+    const double x = f.x[o], y = f.y[o], z = f.z[o];
+    const float m = f.m[o];
+    if (xyzm) xyzm[s] = make_float4((float)x, (float)y, (float)z, m);
+    t.x[s] = x;
+    t.y[s] = y;
+    t.z[s] = z;
     t.vx[s] = f.vx[o];
     t.vy[s] = f.vy[o];
     t.vz[s] = f.vz[o];
     t.ax[s] = f.ax[o];
     t.ay[s] = f.ay[o];
     t.az[s] = f.az[o];
-    t.m[s] = f.m[o];
+    t.m[s] = m;
     t.pt[s] = f.pt[o];
     t.lv[s] = f.lv[o];
   }
@@ -280,8 +285,9 @@ void launch_ko_scatter(int64_t n, const KoSet &k, const KoSet &caller, uint4 *re
 }
 
 void launch_ko_permute(int64_t n, const uint32_t *perm, const KoSet &from, const KoSet &to,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_ko_permute, dim3(ko_grid(n)), dim3(256), 0, st, n, perm, from, to);
+                       float4 *xyzm, hipStream_t st) {
+  hipLaunchKernelGGL(k_ko_permute, dim3(ko_grid(n)), dim3(256), 0, st, n, perm, from, to,
+                     xyzm);
 }
 
 void launch_ko_ties(int64_t n, const uint64_t *keys, uint32_t *vals, const uint32_t *pt_old,

@@ -324,9 +324,11 @@ int ko_hash_parts(int64_t n);
 void launch_ko_scatter(int64_t n, const KoSet &k, const KoSet &caller, uint4 *rec,
                        uint32_t *inv, unsigned long long *hash, unsigned long long *part,
                        hipStream_t st);
-// After a rebuild: slot s of the new order is slot perm[s] of the old one.
+// After a rebuild: slot s of the new order is slot perm[s] of the old one;
+// with xyzm, also the tree's sorted (x, y, z, m) records, (float) of the FP64
+// positions (what the drift stored as the records the keys came from).
 void launch_ko_permute(int64_t n, const uint32_t *perm, const KoSet &from, const KoSet &to,
-                       hipStream_t st);
+                       float4 *xyzm, hipStream_t st);
 // Equal keys in caller order: the sort of a key-ordered state keeps equal
 // keys in their old slot order; each run of equal keys is reordered by the
 // caller index pt_old[vals[j]].
