@@ -49,7 +49,6 @@ static_assert(kWaveSpan % kBuildThreads == 0, "wavefront ranges start at build b
 constexpr uint32_t kNoCell = 0xffffffffu;
 constexpr uint32_t kSmallCell = 64;   // bigger cells go to the particle pass (the build's E)
 constexpr uint32_t kLeafStage = 512;  // particles staged per wavefront in the leaf pass
-constexpr int kLvlBatch = 8;          // levels whose centres of mass are fetched together
 
 // Lanes 0 .. lane (inclusive) as a mask.
 __device__ __forceinline__ uint64_t lanes_le(uint32_t lane) {
