@@ -225,3 +225,32 @@ def test_layouts_bit_identical(nb, torch):
             np.testing.assert_array_equal(a, b)
         np.testing.assert_array_equal(out[0][1], o[1])
         assert out[0][2:] == o[2:]
+
+
+@pytest.mark.parametrize("n", [1, 3, 63, 257, 1000])
+def test_layouts_bit_identical_small_and_ragged(nb, torch, n):
+    # the key-ordered layout moves the state in tiles of 256 particles (and
+    # hashes it per workgroup): tiny and ragged counts in both layouts, bit
+    # for bit, across two calls with an in-place change between them
+    _say("step layouts, n", n)
+    p = I.plummer(n, 300 + n)
+    params = nb.Params(eps=2.0 ** -6, delta_acc=2.0 ** -9, leaf_max=4, group_max=16)
+    out = []
+    for layout in (1, 2):
+        st = nb.State.from_numpy(p.pos, p.vel, p.mass, dt=2.0 ** -4, rebuild_interval=2,
+                                 block_steps=True, eta=0.025)
+        ctx = nb.Context(params, n_max=n)
+        ctx.set_step_layout(layout)
+        ctx.step(st, 5)
+        st.vx[n - 1] += 2.0 ** -10
+        ctx.step(st, 4)
+        ctx.sync()
+        out.append(([t.cpu().numpy() for t in (st.x, st.y, st.z, st.vx, st.vy, st.vz, st.ax,
+                                                st.ay, st.az, st.level)],
+                    ctx.export(nb.X.PERM).cpu().numpy(), st.tick))
+    for a, b in zip(out[0][0], out[1][0]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+    for a in out[0][0][:9]:
+        assert np.all(np.isfinite(a))
