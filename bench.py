@@ -118,6 +118,19 @@ def cpu_baseline(pos32, m, eps, dacc, leaf_max, group_max, group_merge, walk_fra
     }
 
 
+def walk_lane_slots(entries, count):
+    """Wavefront lane-slots of a walk (one list entry applied by a wavefront to
+    its 64 lanes): each block of 64 list entries (the last one partial) is run
+    in S lane streams (S = 8, 4, 2, 1 for groups of at most 8, 16, 32, 64
+    members), padded to a multiple of 4 S entries (the flush unroll)."""
+    entries = entries.astype(np.int64)
+    count = count.astype(np.int64)
+    S = np.where(count <= 8, 8, np.where(count <= 16, 4, np.where(count <= 32, 2, 1)))
+    rem = entries % 64
+    pad = -(-rem // (4 * S)) * (4 * S)
+    return int(np.sum((entries // 64) * (64 // S) + pad // S))
+
+
 def accuracy(ctx, nb, torch, st, acc, delta, n_target=1 << 14):
     """Error of the tree walk's accelerations `acc` (tensors, caller order)
     at the state's positions, against Eq. 1 summed directly in FP64 (the
@@ -383,6 +396,43 @@ def main():
         t_1 = time.perf_counter()
         return ctx, s, s_0, ctx.stats(), t_0, t_1
 
+    def order_bounds(n_steps=8):
+        """Block steps from one state, the tree rebuilt at every step (from
+        the same positions in every order, so the same tree and groups): each
+        step's walk run in the size-based order (which records the walk's true
+        per-group counts), then in order 3 (those counts: the ideal order of
+        this very walk), plain and learned, each from the state before the
+        step. The walks are the same computation in every order."""
+        s = restore(snap, nb)
+        s.rebuild_interval = 1
+        ctx = nb.Context(params, n_max=args.n)
+        ctx.set_cost_model(model["hidden"], model["w"])
+        ctx.set_order(1)
+        ctx.step(s, settle)
+        ctx.sync()
+        ms = {1: 0.0, 3: 0.0, 0: 0.0, 2: 0.0}
+        for _ in range(n_steps):
+            before = snapshot(s)
+            for order in (1, 3, 0, 2):
+                s = restore(before, nb)
+                ctx.set_order(order)
+                ctx.timing(True)
+                ctx.step(s, 1)
+                ctx.sync()
+                ms[order] += ctx.stats()["walk_ms_sum"]
+        del ctx
+        rep = {"steps": n_steps, "walk_ms_per_step": {
+            "plain": ms[0] / n_steps, "size_based": ms[1] / n_steps,
+            "learned": ms[2] / n_steps, "ideal_true_counts": ms[3] / n_steps}}
+        rep["plain_over_ideal"] = ms[0] / ms[3]
+        rep["learned_over_ideal"] = ms[2] / ms[3]
+        rep["size_based_over_ideal"] = ms[1] / ms[3]
+        log("orders on each step's fresh tree, %d steps, walk ms per step: plain %.3f, "
+            "size-based %.3f, "
+            "learned %.3f, ideal (true counts) %.3f"
+            % (n_steps, ms[0] / n_steps, ms[1] / n_steps, ms[2] / n_steps, ms[3] / n_steps))
+        return rep
+
     if args.order == 2 and model is None:
         sys.exit("--order 2 needs a trained cost model (--learn-steps > 0)")
     ctx, st, s0, s1, t0, t1 = timed_run(args.order)
@@ -428,6 +478,7 @@ def main():
                    "states_bit_identical": bool(same), **model["report"]}
         log("plain/learned: step x%.3f, walk x%.3f; states bit-identical %s"
             % (learned["plain_over_learned_step"], learned["plain_over_learned_walk"], same))
+        learned["bounds_fresh_tree_each_step"] = order_bounds()
         if args.rebuild == 0 and args.order != 2:
             # the learned order under the automatic rebuild rule, as the headline runs
             c_, s_, a0_, a1_, b0_, b1_ = timed_run(2)
@@ -452,6 +503,13 @@ def main():
     s2 = ctx.stats()
     full_ms = s2["walk_ms_sum"] / max(s2["walk_calls"], 1)
     log("all-active walk %.3f ms, %.3g interactions" % (full_ms, s2["interactions_sum"]))
+    # lane-slots of that walk (every group walked): the interactions each
+    # lane could have done, idle lanes included
+    lane_slots = walk_lane_slots(ctx.export(nb.X.GENTRIES).cpu().numpy(),
+                                 ctx.export(nb.X.GCOUNT).cpu().numpy())
+    log("all-active walk: %.4g lane-slots, lane fill %.3f, %.3g lane-slot interactions/s"
+        % (lane_slots, s2["interactions_sum"] / (64.0 * lane_slots),
+           64.0 * lane_slots / (full_ms * 1e-3)))
     acc_rep = accuracy(ctx, nb, torch, st, full, args.delta)
     del full
 
@@ -502,6 +560,9 @@ def main():
         "all_active_walk_ms": full_ms,
         "all_active_interactions": s2["interactions_sum"],
         "all_active_interactions_per_s": s2["interactions_sum"] / (full_ms * 1e-3),
+        "all_active_lane_slots": lane_slots,
+        "all_active_lane_fill": s2["interactions_sum"] / (64.0 * lane_slots),
+        "all_active_lane_slot_interactions_per_s": 64.0 * lane_slots / (full_ms * 1e-3),
         "accuracy": acc_rep,
         "plain_vs_learned": learned,
         "build_ms": s1["build_ms_sum"] / max(s1["build_calls"], 1),

@@ -63,10 +63,13 @@ enum {
  *                1 longest expected work first, estimated from the group's
  *                size and its members' previous list lengths; 2 by the
  *                learned cost model (nbody_set_cost_model; plain until one is
- *                installed). Orders 1 and 2 also record the per-group
- *                features and targets of the cost model (NBODY_X_FEAT,
- *                NBODY_X_TARGET). The order never changes the results
- *                (bit-identical). nbody_set_order changes it later.
+ *                installed); 3 by the per-group log2 interaction counts the
+ *                last ordered walk recorded (NBODY_X_TARGET): the true costs
+ *                when the same groups of the same tree are walked again, an
+ *                ideal order for measurements. Orders 1-3 also record the
+ *                per-group features and targets of the cost model
+ *                (NBODY_X_FEAT, NBODY_X_TARGET). The order never changes the
+ *                results (bit-identical). nbody_set_order changes it later.
  *  frontier_cap: cells per wavefront in the walk's candidate stack (power
  *                of two >= 64; 0 = the cell capacity rounded up to a power
  *                of two, at most 16384, which no tree can fill: the stack

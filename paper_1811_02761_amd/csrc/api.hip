@@ -145,7 +145,7 @@ nbody_status check_params(const nbody_params *p) {
   if (p->group_max < 1 || p->group_max > 64) return NBODY_EINVAL;
   if (p->leaf_max < 1 || p->leaf_max > p->group_max) return NBODY_EINVAL;
   if (p->compensated != 0 && p->compensated != 1) return NBODY_EINVAL;
-  if (p->order < 0 || p->order > 2) return NBODY_EINVAL;
+  if (p->order < 0 || p->order > 3) return NBODY_EINVAL;
   if (p->frontier_cap != 0 &&
       (p->frontier_cap < 64 || (p->frontier_cap & (p->frontier_cap - 1)) != 0))
     return NBODY_EINVAL;
@@ -1435,7 +1435,7 @@ nbody_status nbody_set_cost_model(nbody_ctx *ctx, int32_t hidden, const float *w
 
 nbody_status nbody_set_order(nbody_ctx *ctx, int32_t order) {
   if (!ctx) return NBODY_EINVAL;
-  if (order < 0 || order > 2) return NBODY_EINVAL;
+  if (order < 0 || order > 3) return NBODY_EINVAL;
   ctx->order = order;
   return NBODY_OK;
 }

@@ -284,16 +284,18 @@ __global__ __launch_bounds__(256) void k_adam(int64_t np, float *__restrict__ w,
 // covers the queue's entries only (the count is read on the device).
 __global__ __launch_bounds__(256) void k_cost_keys(
     const DevScalars *__restrict__ sc, const uint32_t *__restrict__ queue, int mode,
-    const float4 *__restrict__ feat, const float *__restrict__ pred, int64_t n_upper,
-    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const float4 *__restrict__ feat, const float *__restrict__ pred,
+    const float *__restrict__ target, int64_t n_upper, uint64_t *__restrict__ keys,
+    uint32_t *__restrict__ vals) {
   const uint32_t nq = queue ? sc->nqueue : sc->ngroup;
   (void)n_upper;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nq;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t g = queue ? queue[i] : (uint32_t)i;
     const float4 f = feat[g];
-    // mode 1: log2(count) + log2(1 + previous list length); mode 2: the model
-    const float c = mode == 2 ? pred[g] : f.x + f.w;
+    // mode 1: log2(count) + log2(1 + previous list length); mode 2: the
+    // model; mode 3: the log2 interactions the last ordered walk recorded
+    const float c = mode == 2 ? pred[g] : mode == 3 ? target[g] : f.x + f.w;
     const float q = fminf(fmaxf(c * 4.0f, 0.0f), 254.0f);  // NaN -> 0
     keys[i] = 254u - (uint32_t)q;
     vals[i] = g;
@@ -385,7 +387,8 @@ void launch_cost_order(int64_t n, bool queued, int mode, int H, const Ptrs &P,
   if (mode == 2)
     launch_mlp_forward(H, P.mlpw, n, &P.sc->ngroup, P.feat, P.pred, st);
   hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(n, 256 * 8, 8192)), dim3(256), 0, st, P.sc,
-                     queued ? P.order : nullptr, mode, P.feat, P.pred, n, P.okeys, P.qtmp);
+                     queued ? P.order : nullptr, mode, P.feat, P.pred, P.target, n, P.okeys,
+                     P.qtmp);
   launch_digit_sort(n, queued ? &P.sc->nqueue : &P.sc->ngroup, 0, P.okeys, P.qtmp, P.okeys + n,
                     P.order, P.hist, st);
   hipLaunchKernelGGL(k_cost_qtotal, dim3(1), dim3(64), 0, st, P.sc, queued ? 1 : 0);

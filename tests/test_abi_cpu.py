@@ -55,7 +55,7 @@ def test_create_rejects_bad_params_without_gpu(nb):
     # parameter validation happens before any device call
     for bad in (dict(eps=0.0), dict(eps=-1.0), dict(delta_acc=-1.0), dict(group_max=65),
                 dict(leaf_max=0), dict(leaf_max=65, group_max=64), dict(compensated=2),
-                dict(order=3), dict(frontier_cap=100), dict(list_tile=60), dict(list_tile=136), dict(list_tile=2112),
+                dict(order=4), dict(frontier_cap=100), dict(list_tile=60), dict(list_tile=136), dict(list_tile=2112),
                 dict(walk_split=3),
                 dict(waves_per_cu=33), dict(checks=2), dict(group_merge=2),
                 dict(calcnode_sync=3), dict(calcnode_sync=-1)):

@@ -132,7 +132,17 @@ def test_orders_bit_identical_features_and_targets(nb, torch, orc):
     ctx.set_order(2)
     o2 = _walk(nb, torch, ctx, x, y, z, m, a_old, build=False)
     pred = ctx.export(nb.X.PRED).cpu().numpy()
-    for a in (o1, o1b, o2):
+    # order 3: by the counts the last ordered walk recorded (the same groups
+    # of the same tree here, so the true counts): longest first by
+    # quarter-octave buckets
+    t_true = ctx.export(nb.X.TARGET).cpu().numpy().copy()
+    ctx.set_order(3)
+    o3 = _walk(nb, torch, ctx, x, y, z, m, a_old, build=False)
+    q3 = ctx.export(nb.X.QUEUE).cpu().numpy()
+    np.testing.assert_array_equal(np.sort(q3), np.arange(r.grp.n))
+    b3 = np.floor(np.clip(t_true[q3] * 4.0, 0.0, 254.0))
+    assert np.all(np.diff(b3) <= 0)
+    for a in (o1, o1b, o2, o3):
         np.testing.assert_array_equal(a, plain)
     # the model's misses against the measured counts, next to the size-based
     # estimate (log2 count + log2(1 + previous list length)) and a count-only
