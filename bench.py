@@ -567,6 +567,14 @@ def main():
         "plain_vs_learned": learned,
         "build_ms": s1["build_ms_sum"] / max(s1["build_calls"], 1),
         "rebuilds_in_timed_steps": rebuilds,
+        # per step, from the live HIP-event spans: the walks, the rebuilds
+        # (bounds and keys, sort, state permute, cells, groups and the new
+        # tree's moments) and the rest (moments on kept trees, drift, kicks,
+        # queue, bookkeeping); per kernel in the committed kernel trace
+        "phases_ms_per_step": {
+            "walk": s1["walk_ms_sum"] / args.steps,
+            "rebuild": s1["build_ms_sum"] / args.steps,
+            "other": sec_per_step * 1e3 - (s1["walk_ms_sum"] + s1["build_ms_sum"]) / args.steps},
         "pct_fp32_vector_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
         "roofline": {
             "bound": "alu",
