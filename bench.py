@@ -4,21 +4,25 @@ Workload (default): three-component galaxy, N = 2^23 equal-mass particles
 (80 % NFW halo truncated at 30 scale radii, 5 % Hernquist bulge, 15 %
 exponential disc with scale height 0.1 scale length), softening 2^-6, Eq. 2
 accuracy parameter 2^-9, individual block time steps (dt_max = 2^-3, eta =
-0.025, so the finest occupied level steps by 2^-7) and the tree rebuild
+0.025, so the finest occupied level steps by 2^-6) and the tree rebuild
 interval chosen by the library's measured-excess rule. A step = one smallest
 block step: opening kicks, drift of every particle (FP64), tree rebuild or
 refit (keys, sort, build, moments), group boxes, walk of the groups holding
 particles whose step ends, closing kicks and new levels.
 
-After the warm-up the same state is stepped twice on fresh contexts: with the
-plain (Morton) walk queue, which gives `value`, and with the queue ordered by
-the learned cost model (trained on the device from the warm-up's last walk);
-forces, and so the two trajectories, are bit-identical.
+After the warm-up the state is stepped on a fresh context with the plain
+(Morton) walk queue, which gives `value`. Then, from the same state: plain,
+learned (a cost model trained on the device from the warm-up's walks) and
+size-based queue orders on one fixed rebuild schedule (the same trajectory
+bit for bit, only the time differs); the ideal-order bound (each step's walk
+ordered by its own true per-group counts, on a tree rebuilt at the step); the
+learned order under the automatic rule; one all-active walk (with its
+lane-slots); the acceleration error against FP64 direct summation.
 
 Prints one JSON line with s/step, interactions/s, the walk's fraction of the
 MI355X FP32 vector peak (22 Flop per interaction, rsqrt counted as 4), the
-walk's roofline record, the plain-vs-learned comparison and the CPU oracle
-baseline on a bounded sample.
+walk's roofline record, a per-step split into walk, rebuild and the rest, the
+order comparisons and the CPU oracle baseline on a bounded sample.
 """
 from __future__ import annotations
 
