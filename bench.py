@@ -288,7 +288,7 @@ def run_batch(args):
     print(json.dumps(rec), flush=True)
 
 
-def main():
+def build_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
@@ -323,7 +323,11 @@ def main():
                          "(use --seed 4)")
     ap.add_argument("--learn-steps", type=int, default=300,
                     help="Adam steps of the cost model for the plain-vs-learned walks (0: skip)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = build_parser().parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
