@@ -631,7 +631,9 @@ nbody_status do_build(nbody_ctx *ctx, int64_t n, const Coords &c) {
   ctx->mac_walks = 0;
   const int sp = span_begin(ctx, 0);
   if (ctx->sys_r > 0) {
-    launch_sys_keys(c, n, ctx->nsys, ctx->sys_r, P, ctx->st);
+    // (block counts are free before the build)
+    launch_sys_keys(c, n, ctx->nsys, ctx->sys_r, P, P.blkcnt,
+                    (int64_t)(kLevels + 1) * ctx->L.build_blocks + kLevels + 1, ctx->st);
   } else {
     launch_bbox(c, n, P.sc, P.blkcnt, ctx->st);  // (block counts are free before the build)
     launch_keys(c, n, P.sc, P.keysA, P.valsA, ctx->st);

@@ -168,13 +168,39 @@ __global__ __launch_bounds__(256) void k_keys(Coords c,
 // index fills the top r octal digits of the key above a (21 - r)-level
 // Morton key in that cube.
 
-// One workgroup per system: exact bounds, then lo and L of its root cube.
+// lo and L of a system's root cube from the exact bounds (p: minima, q:
+// maxima) of its particles.
+__device__ __forceinline__ double4 sys_cube(const float p[3], const float q[3]) {
+  double l[3], ext = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    l[k] = (double)p[k];
+    const double e = (double)q[k] - (double)p[k];
+    ext = e > ext ? e : ext;
+  }
+  int eL = 0;
+  if (ext > 0.0) {
+    int e;
+    const double f = frexp(ext, &e);
+    eL = (f == 0.5) ? e - 1 : e;
+  }
+  return make_double4(l[0], l[1], l[2], ldexp(1.0, eL));
+}
+
+// Exact bounds of share k = blockIdx.y of gridDim.y consecutive shares of
+// system s = blockIdx.x. With one share per system the workgroup writes the
+// system's root cube itself; otherwise it writes its bounds to
+// part[6 * (s * shares + k) ..] (min x, y, z, max x, y, z) and
+// k_sys_bbox_fold reduces them (one workgroup for a system of 2^18 particles
+// was most of the batch's key pass).
 __global__ __launch_bounds__(256) void k_sys_bbox(Coords c,
                                                   const uint32_t *__restrict__ off,
                                                   double4 *__restrict__ sysbox,
-                                                  DevScalars *sc) {
-  const uint32_t s = blockIdx.x;
-  const uint32_t a = off[s], b = off[s + 1];
+                                                  DevScalars *sc, float *__restrict__ part) {
+  const uint32_t s = blockIdx.x, k = blockIdx.y, shares = gridDim.y;
+  const uint32_t a0 = off[s], len = off[s + 1] - a0;
+  const uint32_t per = (uint32_t)(((uint64_t)len + shares - 1) / shares);
+  const uint32_t a = a0 + (uint32_t)std::min<uint64_t>(len, (uint64_t)k * per);
+  const uint32_t b = a0 + (uint32_t)std::min<uint64_t>(len, (uint64_t)(k + 1) * per);
   float lo[3] = {INFINITY, INFINITY, INFINITY};
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
@@ -201,25 +227,42 @@ __global__ __launch_bounds__(256) void k_sys_bbox(Coords c,
   if (__any(bad) && lane_id() == 0) atomicOr(&sc->status, kStNonFinite);
   __syncthreads();
   if (threadIdx.x == 0) {
-    double l[3], ext = 0.0;
+    float p[3], q[3];
     for (int k = 0; k < 3; ++k) {
-      float p = red[k][0], q = red[3 + k][0];
+      p[k] = red[k][0];
+      q[k] = red[3 + k][0];
       for (int j = 1; j < (int)(blockDim.x >> 6); ++j) {
-        p = fminf(p, red[k][j]);
-        q = fmaxf(q, red[3 + k][j]);
+        p[k] = fminf(p[k], red[k][j]);
+        q[k] = fmaxf(q[k], red[3 + k][j]);
       }
-      l[k] = (double)p;
-      const double e = (double)q - (double)p;
-      ext = e > ext ? e : ext;
     }
-    int eL = 0;
-    if (ext > 0.0) {
-      int e;
-      const double f = frexp(ext, &e);
-      eL = (f == 0.5) ? e - 1 : e;
+    if (shares == 1) {
+      sysbox[s] = sys_cube(p, q);
+    } else {
+      float *o = part + 6 * ((size_t)s * shares + k);
+      for (int j = 0; j < 3; ++j) {
+        o[j] = p[j];
+        o[3 + j] = q[j];
+      }
     }
-    sysbox[s] = make_double4(l[0], l[1], l[2], ldexp(1.0, eL));
   }
+}
+
+// One thread per system: the shares' bounds, then its root cube.
+__global__ __launch_bounds__(256) void k_sys_bbox_fold(const float *__restrict__ part,
+                                                       int shares, int nsys,
+                                                       double4 *__restrict__ sysbox) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  float p[3] = {INFINITY, INFINITY, INFINITY}, q[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int k = 0; k < shares; ++k) {
+    const float *o = part + 6 * ((size_t)s * shares + k);
+    for (int j = 0; j < 3; ++j) {
+      p[j] = fminf(p[j], o[j]);
+      q[j] = fmaxf(q[j], o[3 + j]);
+    }
+  }
+  sysbox[s] = sys_cube(p, q);
 }
 
 __device__ __forceinline__ uint32_t quantise_bits(float v, double lo, double scale,
@@ -291,8 +334,17 @@ void launch_bbox(const Coords &c, int64_t n, DevScalars *sc, uint32_t *part, hip
 }
 
 void launch_sys_keys(const Coords &c, int64_t n, int nsys, int r, const Ptrs &P,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_sys_bbox, dim3(nsys), dim3(256), 0, st, c, P.sysoff, P.sysbox, P.sc);
+                     uint32_t *part, int64_t part_words, hipStream_t st) {
+  // shares per system: up to 32 (2048 workgroups for 64 systems), as the
+  // scratch allows; a single share writes the cube directly
+  const int shares = (int)std::max<int64_t>(
+      1, std::min<int64_t>(32, part_words / (6 * (int64_t)std::max(nsys, 1))));
+  float *fpart = reinterpret_cast<float *>(part);
+  hipLaunchKernelGGL(k_sys_bbox, dim3(nsys, shares), dim3(256), 0, st, c, P.sysoff, P.sysbox,
+                     P.sc, fpart);
+  if (shares > 1)
+    hipLaunchKernelGGL(k_sys_bbox_fold, dim3((uint32_t)cdiv(nsys, 256)), dim3(256), 0, st, fpart,
+                       shares, nsys, P.sysbox);
   hipLaunchKernelGGL(k_sys_keys, dim3(grid_for(n, 4, 8192)), dim3(256), 0, st, c, n,
                      P.sysoff, nsys, r, P.sysbox, P.keysA, P.valsA);
 }

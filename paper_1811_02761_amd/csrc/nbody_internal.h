@@ -194,8 +194,9 @@ void launch_build(const uint64_t *keys, int64_t n, int leaf_max, int group_max,
                   int group_merge, int nsys, int r, const Ptrs &P, const Layout &L,
                   hipStream_t st);
 // batch keys into P.keysA / P.valsA from P.sysoff; per-system cubes to P.sysbox
+// (part: part_words words of scratch for partial bounds)
 void launch_sys_keys(const Coords &c, int64_t n, int nsys, int r, const Ptrs &P,
-                     hipStream_t st);
+                     uint32_t *part, int64_t part_words, hipStream_t st);
 constexpr int kMaxSystems = 4096;
 // calcNode synchronisation (nbody_params.calcnode_sync)
 constexpr int kCalcNodeLevels = 1;  // one launch per tree level
