@@ -49,10 +49,12 @@ def test_batch_keys(orc):
             assert int(k[i]) == (s << (3 * bits)) | _interleave(*q, bits)
 
 
+# (the second batch holds systems of 2 to about 3000 particles: neighbouring
+# system roots small enough to be group cells, which must not be joined)
 @pytest.mark.parametrize("merge", [0, 1])
-def test_batch_equals_separate_systems(orc, merge):
-    ps, off, x, y, z, m = _batch(9, 5)
-    S = 9
+@pytest.mark.parametrize("S,seed,lo,hi", [(9, 5, 7.0, 10.5), (40, 7, 1.0, 12.0)])
+def test_batch_equals_separate_systems(orc, merge, S, seed, lo, hi):
+    ps, off, x, y, z, m = _batch(S, seed, lo, hi)
     r = orc.system_digits(S)
     rb = orc.tree_forces(x, y, z, m, a_old=None, systems=off, group_merge=merge)
     cl = rb.cells
