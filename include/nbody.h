@@ -87,7 +87,8 @@ enum {
  *                group cells are joined, in octant order, while the joined
  *                count stays within group_max (fewer, fuller groups, hence
  *                fewer interaction lists; results change only through the
- *                grouping).
+ *                grouping). In a batch (nbody_set_systems) only siblings
+ *                within one system are joined: a group never spans systems.
  *  walk_split  : wavefronts sharing one group's interaction list: 0 chosen
  *                per walk from the queued group count q and the walk's
  *                wavefront count w (4 if q < 2w, 2 if q < 4w, else 1), or

@@ -27,7 +27,8 @@
 // holding at most group_max particles whose parent holds more (the root if
 // it holds at most group_max); an oversized level-21 cell is cut into pieces
 // of group_max. With group_merge, consecutive sibling group cells are joined
-// greedily in octant order while the joined count stays within group_max.
+// greedily in octant order while the joined count stays within group_max
+// (siblings within one system only: a batch's system roots are never joined).
 // Each cell holding more than group_max particles marks the group starts
 // among its children; a scan over the marked particles lists the groups in
 // particle order.
@@ -573,8 +574,10 @@ __device__ __forceinline__ bool group_ok(int32_t level, uint32_t cnt, int nchild
 
 // Group starts: the root if it may hold a group; otherwise every cell that
 // may not marks the group starts among its children (joining consecutive
-// small siblings when `merge`; an over-full leaf is cut into pieces of
-// group_max). Every particle is marked at most once.
+// small siblings when `merge` and the cell lies within one system: above
+// min_level its children are the roots of distinct systems; an over-full
+// leaf is cut into pieces of group_max). Every particle is marked at most
+// once.
 __global__ __launch_bounds__(256) void k_group_mark(DevScalars *__restrict__ sc,
                                                     const int32_t *__restrict__ clevel,
                                                     const uint32_t *__restrict__ cpbegin,
@@ -596,11 +599,12 @@ __global__ __launch_bounds__(256) void k_group_mark(DevScalars *__restrict__ sc,
     if (ok || k == 0) continue;
     const int32_t f = cfchild[c];
     uint32_t run = 0;  // particles in the open joined group (0: none open)
+    const bool join = merge && clevel[c] >= min_level;
     for (int q = 0; q < k; ++q) {
       const uint32_t cb = cpbegin[f + q], cc = cpcount[f + q];
       const bool cok = group_ok(clevel[f + q], cc, cnchild[f + q], gmax, min_level);
       if (cok && cc <= gmax) {
-        if (merge && run > 0 && run + cc <= gmax) {
+        if (join && run > 0 && run + cc <= gmax) {
           run += cc;
         } else {
           pinfo[cb] |= kGroupMark;

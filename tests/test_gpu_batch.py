@@ -62,7 +62,11 @@ def _calc(nb, torch, ctx, x, y, z, m, a_old):
     return np.stack([_np(a) for a in acc], 1)
 
 
-@pytest.mark.parametrize("n_sys,seed,lo,hi", [(9, 5, 7.0, 10.5), (64, 4, 8.0, 12.0)])
+# (the last case: systems of 2 to about 3000 particles, whose per-system
+# bounds are split into 7 shares, so that the smallest systems leave shares
+# without particles)
+@pytest.mark.parametrize("n_sys,seed,lo,hi", [(9, 5, 7.0, 10.5), (64, 4, 8.0, 12.0),
+                                              (40, 7, 1.0, 12.0)])
 def test_batch_matches_oracle_and_separate_runs(nb, torch, orc, n_sys, seed, lo, hi):
     ps, off, x, y, z, m = _batch(n_sys, seed, lo, hi)
     n = x.shape[0]
