@@ -135,6 +135,7 @@ CASES = [
     ("plummer", 5000, 7, 8, 32),
     ("galaxy", 3001, 9, 4, 16),
     ("plummer", 777, 2, 1, 8),
+    ("plummer", 40, 4, 16, 64),  # the root is the only group, and it is split
 ]
 
 
